@@ -1,0 +1,209 @@
+/*
+ * hsweep -- moving-PML sweeping preconditioner for the 7-point heterogeneous
+ * 3D Helmholtz operator on one MI355X (gfx950).
+ *
+ * The problem is the one of Poulson, Engquist, Li and Ying, "A parallel
+ * sweeping preconditioner for heterogeneous 3D Helmholtz equations":
+ * given the velocity c(x), the angular frequency omega and a grid, solve
+ * A u = f with A = -Delta - omega^2/c^2 (Sec. 1, Eq. 1.1) discretised by
+ * second-order finite differences with PML, using GMRES(k) (Sec. 2.4)
+ * preconditioned by the sweep (Sec. 1.1, Algs. 1.3-1.5) over panels whose
+ * auxiliary problems H_i are factored by a multifrontal LDL^T over a
+ * nested-dissection tree (Secs. 2.1-2.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Grid.  Interior nodes i_j = 1..n_j at x_j = i_j h; gamma PML nodes are
+ *   added past every face, so a vector lives on the padded grid of
+ *   N_j = n_j + 2 gamma nodes per axis, lexicographic with x1 fastest
+ *   (index a1 + a2 N1 + a3 N1 N2), homogeneous Dirichlet just outside.
+ * - Vectors are complex128 (hsw_c128, interleaved re/im).  A block of nrhs
+ *   vectors stores each vector contiguously, vector r starting at r * ld,
+ *   ld >= N_pad = N1 N2 N3.
+ * - Pointers named as device pointers must be device memory of the device
+ *   the context was created on; they are read/written in order on the
+ *   context's stream.  The library keeps no caller pointer after a call
+ *   returns; it owns the plan, factors and workspace until hsw_destroy.
+ * - Every call returns a status and never aborts; hsw_last_error gives the
+ *   message of the last failure.  A context is not thread-safe.
+ */
+#ifndef HSWEEP_H
+#define HSWEEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsw_ctx hsw_ctx;
+
+typedef struct {
+    double re, im;
+} hsw_c128;
+
+typedef enum {
+    HSW_OK = 0,
+    HSW_E_INVAL = 1,     /* bad argument (size, pointer, non-positive or non-finite c) */
+    HSW_E_NOMEM = 2,     /* plan does not fit in device memory; nothing allocated */
+    HSW_E_STATE = 3,     /* call out of order (e.g. apply before setup) */
+    HSW_E_BREAKDOWN = 4, /* zero or non-finite pivot in the unpivoted LDL^T */
+    HSW_E_NOCONV = 5,    /* GMRES reached maxit; x holds the last iterate */
+    HSW_E_DEVICE = 6     /* HIP runtime error */
+} hsw_status;
+
+typedef enum {
+    HSW_C128 = 0,        /* fronts, sweep and GMRES in complex FP64 */
+    HSW_C64 = 1,         /* fronts and sweep in complex FP32, GMRES in FP64 */
+    HSW_C64_BF16GEMM = 2 /* as HSW_C64, Schur-update GEMM inputs rounded to bf16 */
+} hsw_precision;
+
+/* One problem: the grid, frequency and preconditioner parameters. */
+typedef struct {
+    int32_t n[3];        /* interior nodes per axis */
+    double h;            /* grid spacing, same on every axis */
+    double omega;        /* angular frequency (Sec. 1, Eq. 1.1) */
+    double alpha;        /* damping of J = -Delta - (omega + i alpha)^2/c^2 (Sec. 1.1, Eq. 1.5);
+                            0 makes J = A */
+    int32_t gamma;       /* PML nodes per face, physical and artificial (Sec. 1.1) */
+    double pml_amp;      /* PML amplitude C in sigma(t) = (C/eta)(t/eta)^2, eta = (gamma+1) h */
+    int32_t panel_depth; /* interior x3 planes per panel, d (Sec. 1.1, before Alg. 1.4) */
+    int32_t leaf;        /* nested-dissection leaf lateral extent (>= 2) (Sec. 2.1) */
+} hsw_problem;
+
+typedef struct {
+    int32_t restart_k;   /* GMRES restart length k (Sec. 2.4) */
+    int32_t maxit;       /* cap on preconditioner applications per right-hand side */
+    double rtol;         /* stop when ||b - A x|| / ||b|| < rtol (true residual, FP64) */
+} hsw_solve_opts;
+
+typedef struct {
+    int32_t iters_max;   /* max over right-hand sides of the iteration count */
+    int32_t* iters;      /* host array, sum(nrhs) entries, or NULL */
+    double* relres;      /* host array, sum(nrhs) entries: final true relative residual, or NULL */
+    double t_setup;      /* seconds of the last hsw_setup (device events) */
+    double t_solve;      /* seconds of this hsw_solve (device events) */
+    int32_t bad_problem, bad_panel, bad_front, bad_pivot; /* breakdown location, else -1 */
+} hsw_solve_info;
+
+/*
+ * Plan the symbolic structure of nprob problems and allocate the factors and
+ * workspace.  Builds the panels of every problem (Sec. 1.1, Alg. 1.4:
+ * m = ceil(n3 / d); panel 0 also owns the bottom gamma PML planes, panel m-1
+ * the top ones), the nested dissection of every panel (Sec. 2.1: full-depth
+ * separators, postorder), the update sets and extend-add maps, and the level
+ * schedule that batches every front of one tree depth over all panels and
+ * problems into one launch.  `stream` is a hipStream_t (NULL: the default
+ * stream).  Returns HSW_E_NOMEM, allocating nothing, when the factors and
+ * workspace do not fit the device.  On success *out owns everything.
+ */
+hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precision prec,
+                      void* stream, hsw_ctx** out);
+
+/*
+ * Load the velocity of every problem: c[k] is a device pointer to
+ * n[0]*n[1]*n[2] doubles of problem k, x1 fastest.  The values are copied;
+ * c must be positive and finite (HSW_E_INVAL otherwise).  The PML stretch
+ * tables are formed here; the matrix entries of A and of every H_i are
+ * generated from them on the device when needed.
+ */
+hsw_status hsw_assemble(hsw_ctx* ctx, const double* const* c);
+
+/*
+ * Factor every auxiliary problem of every panel (Sec. 1.1, Alg. 1.4) by the
+ * multifrontal partial LDL^T of Sec. 2.2, level by level over all panels and
+ * problems, then form the selectively inverted fronts used by the solves.
+ * Returns HSW_E_BREAKDOWN (location in hsw_solve_info of the next solve and
+ * in hsw_last_error) on a zero or non-finite pivot.
+ */
+hsw_status hsw_setup(hsw_ctx* ctx);
+
+/*
+ * z = M^{-1} r: one application of the sweep (Sec. 1.1, Alg. 1.5) of problem
+ * `prob` to nrhs vectors.  r and z are device pointers (may not alias), each
+ * nrhs vectors of the padded grid with leading dimension ld.
+ */
+hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, hsw_c128* z,
+                     int32_t nrhs, int64_t ld);
+
+/*
+ * y = T_i v: the approximate inverse Schur complement of panel i alone
+ * (Sec. 1.1, Alg. 1.3: zero-extend over the artificial PML, solve with H_i,
+ * extract).  v and y are device pointers to nrhs panel vectors (the panel's
+ * planes [lo, hi) of the padded grid, x1 fastest), leading dimension ld
+ * >= (hi - lo) N1 N2.  hsw_query keys "panel_lo"/"panel_hi" (with the panel
+ * index in the key's value argument) give lo and hi.
+ */
+hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel, const hsw_c128* v,
+                           hsw_c128* y, int32_t nrhs, int64_t ld);
+
+/*
+ * y = A x with the undamped 7-point operator of problem `prob` (Sec. 1,
+ * Eq. 1.1 with the PML stretch).  Device pointers, nrhs vectors, ld.
+ */
+hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, hsw_c128* y,
+                      int32_t nrhs, int64_t ld);
+
+/*
+ * Solve A x = b for every problem by right-preconditioned flexible GMRES(k)
+ * in FP64 (Sec. 2.4) from a zero initial guess, all right-hand sides of a
+ * problem advanced together.  b[k], x[k]: device pointers to nrhs[k] padded
+ * vectors of problem k (ld = N_pad).  info (may be NULL) receives the
+ * iteration counts and true FP64 relative residuals.
+ */
+hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128* const* x,
+                     const int32_t* nrhs, const hsw_solve_opts* opts, hsw_solve_info* info);
+
+/*
+ * Integer facts about problem `prob`.  Keys: "N_pad", "N_int", "m" (panels),
+ * "N1", "N2", "N3", "fronts" (per panel), "levels", "factor_bytes",
+ * "setup_flops", "apply_flops" (per right-hand side), "panel_lo",
+ * "panel_hi", "panel_nz", "panel_artificial" (for these four *val holds the
+ * panel index on entry).
+ */
+hsw_status hsw_query(const hsw_ctx* ctx, int32_t prob, const char* key, int64_t* val);
+
+/*
+ * Elimination order of panel `panel`: perm_host[e] (host array of the
+ * panel's auxiliary size) is the index a1 + a2 N1 + q N1 N2 of the e-th
+ * eliminated node of its auxiliary box, q = 0 being the first artificial
+ * plane (or the panel's first plane when it has none).
+ */
+hsw_status hsw_get_perm(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t* perm_host);
+
+/*
+ * Structure of front `front` (postorder number) of a panel:
+ * info[0..4] = {first elimination position, s, u, parent front (-1 root),
+ * depth}; urows (may be NULL) receives the u elimination positions of the
+ * update set, ascending.
+ */
+hsw_status hsw_get_front_info(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
+                              int32_t* info, int32_t* urows);
+
+/*
+ * Host copies (upcast to complex128) of the factored front (Sec. 2.2):
+ * D (s), L_TL (s x s, column-major, unit lower; the upper part is zeroed)
+ * and the final coupling F_BL = F_BL^ L_F^{-T} D_F^{-1} (u x s, column-major).
+ * Any output may be NULL.  Requires hsw_setup.
+ */
+hsw_status hsw_get_front(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
+                         hsw_c128* D, hsw_c128* L_TL, hsw_c128* F_BL, int32_t* s, int32_t* u);
+
+/*
+ * Host copy of the selectively inverted front used by the solves (Sec. 2.2):
+ * G = [L_F^{-1}; F_BL L_F^{-1}], (s+u) x s column-major, upcast to complex128.
+ */
+hsw_status hsw_get_front_inverse(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
+                                 hsw_c128* G);
+
+/* Message of the last failing call on ctx (or of the last failed create when ctx is NULL). */
+const char* hsw_last_error(const hsw_ctx* ctx);
+
+/* Free everything the context owns.  NULL is accepted. */
+void hsw_destroy(hsw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSWEEP_H */

@@ -1,0 +1,107 @@
+// Types shared by the host driver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hsw {
+
+// Interleaved complex number (re, im) in FP32 or FP64.
+template <typename R>
+struct __align__(2 * sizeof(R)) Cx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ inline Cx<R> cx(R re, R im) {
+    Cx<R> z;
+    z.re = re;
+    z.im = im;
+    return z;
+}
+template <typename R>
+__host__ __device__ inline Cx<R> operator+(Cx<R> a, Cx<R> b) { return cx<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ inline Cx<R> operator-(Cx<R> a, Cx<R> b) { return cx<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ inline Cx<R> operator-(Cx<R> a) { return cx<R>(-a.re, -a.im); }
+template <typename R>
+__host__ __device__ inline Cx<R> operator*(Cx<R> a, Cx<R> b) {
+    return cx<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ inline Cx<R> scale(Cx<R> a, R s) { return cx<R>(a.re * s, a.im * s); }
+// acc += a * b
+template <typename R>
+__host__ __device__ inline void cfma(Cx<R>& acc, Cx<R> a, Cx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+// acc -= a * b
+template <typename R>
+__host__ __device__ inline void cfms(Cx<R>& acc, Cx<R> a, Cx<R> b) {
+    acc.re = fma(-a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(-a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+// conj(a) * b
+template <typename R>
+__host__ __device__ inline Cx<R> cjmul(Cx<R> a, Cx<R> b) {
+    return cx<R>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+// 1 / b by the plain formula conj(b) / |b|^2, with a power-of-two prescale so
+// that |b|^2 neither overflows nor underflows in the working precision.
+template <typename R>
+__host__ __device__ inline Cx<R> crecip(Cx<R> b) {
+    R m = fmax(fabs(b.re), fabs(b.im));
+    int e = 0;
+    frexp(m, &e);
+    R br = ldexp(b.re, -e), bi = ldexp(b.im, -e);
+    R den = br * br + bi * bi;
+    return cx<R>(ldexp(br / den, -e), ldexp(-bi / den, -e));
+}
+template <typename R>
+__host__ __device__ inline Cx<R> cdiv(Cx<R> a, Cx<R> b) { return a * crecip(b); }
+
+template <typename To, typename From>
+__host__ __device__ inline Cx<To> ccast(Cx<From> a) { return cx<To>((To)a.re, (To)a.im); }
+
+template <typename R>
+__host__ __device__ inline R cabs2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// One front of one panel of one problem (a node of the elimination tree).
+struct FrontInst {
+    int32_t s, u, start, wvoff;  // pivots, update size, first elimination position,
+                                 // update-vector offset within the panel's class
+    int32_t child0, child1;      // instance ids of the children, -1 if none
+    int32_t uoff, moff;          // absolute offsets into the update-set and extend-add map arrays
+    int32_t panel, depth;        // global panel id, depth in the tree
+    int32_t pad0, pad1;
+    int64_t loff;                // offset of the (s+u) x s factor block (complex elements)
+    int64_t woff;                // offset of the u x u update matrix in its depth-parity workspace
+    int64_t doff;                // offset of the s reciprocal pivots
+};
+
+struct PanelDev {
+    int32_t prob, cls, Nx, Ny, nz, ga, lo, hi;
+    int32_t perm_off;    // offset into the elimination-order arrays
+    int32_t e3_off;      // offset of this panel's x3 stretch tables (node nz, inverse half nz+1)
+    int32_t inst_base;   // instance id of the panel's front 0
+    int32_t nfront;
+};
+
+struct ProbDev {
+    int32_t n[3], N[3];
+    int32_t gamma, pad;
+    int64_t Npad;
+    double h, omega, alpha;
+    int32_t e_off[3];    // per axis: node stretch (N_j) then inverse half-node stretch (N_j + 1)
+    int32_t pad2;
+    const double* c;     // interior velocity, x1 fastest
+};
+
+}  // namespace hsw

@@ -1,0 +1,999 @@
+// Context and C-ABI entry points of the sweeping preconditioner.
+//
+// Setup (Sec. 1.1, Alg. 1.4) factors every panel of every problem; the
+// fronts of one elimination-tree depth over all panels and problems share
+// each launch (Sec. 2: panel factorisations are independent).  The sweep
+// (Alg. 1.5) runs the panel solves in order (they are sequential), all
+// right-hand sides of a problem together.  GMRES(k) (Sec. 2.4) is flexible
+// and right-preconditioned, in FP64 on the device; the host reads one
+// residual estimate per Arnoldi step to decide when to stop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "devtypes.hpp"
+#include "hsweep.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace hsw;
+
+namespace {
+
+std::string g_create_error;
+
+struct Launch {
+    int64_t off;
+    int count;
+    int k;
+};
+
+struct DepthSchedule {
+    Launch assemble;
+    std::vector<Launch> ldlt, trail;  // one per pivot block
+};
+
+struct SolveLevel {
+    int64_t foff = 0, boff = 0;
+    int fcount = 0, bcount = 0;
+    int smax = 0, nmax = 0;
+};
+
+struct ProbHost {
+    int N[3] = {0, 0, 0};
+    int64_t Npad = 0, Nint = 0;
+    int m = 0;
+    int panel_base = 0;  // global panel id of panel 0
+    int64_t c_off = 0;   // offset of the velocity in the context's copy
+    double setup_cmac = 0, inverse_cmac = 0, apply_cmac = 0;
+    int64_t factor_entries = 0;
+    int levels = 0;
+};
+
+}  // namespace
+
+struct hsw_ctx {
+    hipStream_t st = nullptr;
+    hsw_precision prec = HSW_C128;
+    int esz = 16;  // bytes per complex entry of the factors
+    std::vector<hsw_problem> probs;
+    std::vector<ProbHost> ph;
+    std::vector<LatTree> trees;
+    std::vector<PanelClass> classes;
+    std::vector<int> cls_perm_off, cls_ulist_off, cls_cmap_off;
+    std::vector<PanelDev> pan_h;
+    std::vector<ProbDev> prob_h;
+    std::vector<FrontInst> inst_h;
+    std::vector<DepthSchedule> fsched;  // index = depth
+    Launch inv_launch{0, 0, 0};
+    std::vector<std::vector<SolveLevel>> slevels;  // per class, per depth
+    int maxdepth = 0;
+    int64_t ws_size[2] = {0, 0};
+    int64_t L_size = 0, D_size = 0;
+    int max_naux = 0;
+    int64_t max_wsize = 0;
+    int64_t et_size = 0;
+    std::vector<int64_t> et_prob_off, et_panel_off;
+
+    // device
+    FrontInst* d_inst = nullptr;
+    PanelDev* d_pan = nullptr;
+    ProbDev* d_prob = nullptr;
+    int *d_perm = nullptr, *d_iperm = nullptr, *d_ulist = nullptr, *d_cmap = nullptr;
+    int2* d_fwork = nullptr;
+    int* d_swork = nullptr;
+    Cx<double>* d_et = nullptr;
+    double* d_c = nullptr;
+    void *d_L = nullptr, *d_G = nullptr, *d_dinv = nullptr, *d_ws[2] = {nullptr, nullptr};
+    int* d_err = nullptr;
+    // solve workspace (grown on demand)
+    int nrhs_cap = 0;
+    void *d_xin = nullptr, *d_xmid = nullptr, *d_xout = nullptr, *d_wv = nullptr;
+
+    bool assembled = false, factored = false;
+    double t_setup = 0;
+    int bad_inst = -1, bad_pivot = -1;
+    std::string err;
+};
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
+            return HSW_E_DEVICE;                                                         \
+        }                                                                                \
+    } while (0)
+
+static hsw_status fail(hsw_ctx* ctx, hsw_status s, const std::string& msg) {
+    ctx->err = msg;
+    return s;
+}
+
+template <typename P>
+static hipError_t dalloc(P** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    return hipMalloc((void**)p, bytes);
+}
+
+static void free_all(hsw_ctx* ctx) {
+    void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_iperm, ctx->d_ulist,
+                    ctx->d_cmap, ctx->d_fwork, ctx->d_swork, ctx->d_et, ctx->d_c, ctx->d_L,
+                    ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err, ctx->d_xin,
+                    ctx->d_xmid, ctx->d_xout, ctx->d_wv};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
+    std::map<std::tuple<int, int, int>, int> tree_idx;
+    std::map<std::tuple<int, int, int, int>, int> cls_idx;
+    int64_t c_off = 0;
+    for (int k = 0; k < nprob; ++k) {
+        const hsw_problem& q = p[k];
+        for (int j = 0; j < 3; ++j)
+            if (q.n[j] < 1) return fail(ctx, HSW_E_INVAL, "n must be positive");
+        if (!(q.h > 0) || !(q.omega > 0) || !(q.alpha >= 0) || !(q.pml_amp >= 0) ||
+            !std::isfinite(q.h) || !std::isfinite(q.omega) || !std::isfinite(q.alpha) ||
+            !std::isfinite(q.pml_amp))
+            return fail(ctx, HSW_E_INVAL, "h, omega must be positive; alpha, pml_amp >= 0");
+        if (q.gamma < 1 || q.panel_depth < 1 || q.leaf < 2)
+            return fail(ctx, HSW_E_INVAL, "gamma >= 1, panel_depth >= 1, leaf >= 2 required");
+        ProbHost h;
+        for (int j = 0; j < 3; ++j) h.N[j] = q.n[j] + 2 * q.gamma;
+        h.Npad = (int64_t)h.N[0] * h.N[1] * h.N[2];
+        h.Nint = (int64_t)q.n[0] * q.n[1] * q.n[2];
+        if (h.Npad > (int64_t)1 << 31) return fail(ctx, HSW_E_INVAL, "grid too large");
+        h.m = (q.n[2] + q.panel_depth - 1) / q.panel_depth;
+        h.panel_base = (int)ctx->pan_h.size();
+        h.c_off = c_off;
+        c_off += h.Nint;
+        auto tk = std::make_tuple(h.N[0], h.N[1], q.leaf);
+        if (!tree_idx.count(tk)) {
+            tree_idx[tk] = (int)ctx->trees.size();
+            ctx->trees.push_back(build_lateral_tree(h.N[0], h.N[1], q.leaf));
+        }
+        const int ti = tree_idx[tk];
+        for (int i = 0; i < h.m; ++i) {
+            PanelDev P{};
+            P.prob = k;
+            P.Nx = h.N[0];
+            P.Ny = h.N[1];
+            P.lo = i == 0 ? 0 : q.gamma + i * q.panel_depth;
+            P.hi = i == h.m - 1 ? h.N[2] : q.gamma + (i + 1) * q.panel_depth;
+            P.ga = i == 0 ? 0 : q.gamma;
+            P.nz = P.ga + P.hi - P.lo;
+            auto ck = std::make_tuple(h.N[0], h.N[1], P.nz, q.leaf);
+            if (!cls_idx.count(ck)) {
+                PanelClass pc;
+                std::string e = build_class(ctx->trees[ti], P.nz, pc);
+                if (!e.empty()) return fail(ctx, HSW_E_INVAL, "plan: " + e);
+                cls_idx[ck] = (int)ctx->classes.size();
+                ctx->classes.push_back(std::move(pc));
+            }
+            P.cls = cls_idx[ck];
+            ctx->pan_h.push_back(P);
+        }
+        ctx->ph.push_back(h);
+    }
+    // class arrays, concatenated
+    int po = 0, uo = 0, mo = 0;
+    for (auto& c : ctx->classes) {
+        ctx->cls_perm_off.push_back(po);
+        ctx->cls_ulist_off.push_back(uo);
+        ctx->cls_cmap_off.push_back(mo);
+        po += c.naux;
+        uo += (int)c.ulist.size();
+        mo += (int)c.cmap.size();
+        ctx->max_naux = std::max(ctx->max_naux, c.naux);
+        ctx->max_wsize = std::max(ctx->max_wsize, c.wsize);
+        ctx->maxdepth = std::max(ctx->maxdepth, c.maxdepth);
+    }
+    // front instances
+    int64_t loff = 0, doff = 0;
+    for (size_t g = 0; g < ctx->pan_h.size(); ++g) {
+        PanelDev& P = ctx->pan_h[g];
+        const PanelClass& c = ctx->classes[P.cls];
+        P.perm_off = ctx->cls_perm_off[P.cls];
+        P.inst_base = (int)ctx->inst_h.size();
+        P.nfront = c.nfront;
+        ProbHost& h = ctx->ph[P.prob];
+        h.setup_cmac += c.factor_cmac;
+        h.inverse_cmac += c.inverse_cmac;
+        h.apply_cmac += c.solve_cmac * (P.prob >= 0 ? 1 : 0);
+        h.factor_entries += c.lsize;
+        h.levels = std::max(h.levels, c.maxdepth + 1);
+        for (int f = 0; f < c.nfront; ++f) {
+            FrontInst fi{};
+            fi.s = c.s[f];
+            fi.u = c.u[f];
+            fi.start = c.start[f];
+            fi.wvoff = c.woff[f];
+            fi.child0 = c.child0[f] >= 0 ? P.inst_base + c.child0[f] : -1;
+            fi.child1 = c.child1[f] >= 0 ? P.inst_base + c.child1[f] : -1;
+            fi.uoff = ctx->cls_ulist_off[P.cls] + c.uoff[f];
+            fi.moff = ctx->cls_cmap_off[P.cls] + c.moff[f];
+            fi.panel = (int)g;
+            fi.depth = c.depth[f];
+            fi.loff = loff;
+            fi.doff = doff;
+            loff += (int64_t)(fi.s + fi.u) * fi.s;
+            doff += fi.s;
+            ctx->inst_h.push_back(fi);
+        }
+    }
+    ctx->L_size = loff;
+    ctx->D_size = doff;
+    for (auto& h : ctx->ph) {
+        // one sweep application: 2m - 1 panel solves; the first m are forward
+        (void)h;
+    }
+    for (size_t k = 0; k < ctx->ph.size(); ++k) {
+        ProbHost& h = ctx->ph[k];
+        double fwd = 0, last = 0;
+        for (int i = 0; i < h.m; ++i) {
+            const PanelClass& c = ctx->classes[ctx->pan_h[h.panel_base + i].cls];
+            fwd += c.solve_cmac;
+            if (i == h.m - 1) last = c.solve_cmac;
+        }
+        h.apply_cmac = 2 * fwd - last;
+    }
+    return HSW_OK;
+}
+
+static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int>& swork) {
+    const int D = ctx->maxdepth;
+    std::vector<std::vector<int>> at(D + 1);
+    for (size_t i = 0; i < ctx->inst_h.size(); ++i) at[ctx->inst_h[i].depth].push_back((int)i);
+    ctx->fsched.assign(D + 1, DepthSchedule{});
+    for (int d = D; d >= 0; --d) {
+        DepthSchedule& ds = ctx->fsched[d];
+        int64_t woff = 0;
+        int smax = 0;
+        for (int i : at[d]) {
+            FrontInst& f = ctx->inst_h[i];
+            f.woff = woff;
+            woff += (int64_t)f.u * f.u;
+            smax = std::max(smax, f.s);
+        }
+        ctx->ws_size[d & 1] = std::max(ctx->ws_size[d & 1], woff);
+        ds.assemble.off = (int64_t)fwork.size();
+        for (int i : at[d]) {
+            const FrontInst& f = ctx->inst_h[i];
+            int nt = (f.s + f.u + TILE - 1) / TILE;
+            for (int t = 0; t < nt * (nt + 1) / 2; ++t) fwork.push_back(make_int2(i, t));
+        }
+        ds.assemble.count = (int)(fwork.size() - ds.assemble.off);
+        for (int k = 0; k < smax; k += NB) {
+            Launch l{(int64_t)fwork.size(), 0, k};
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                int nrb = (f.s + f.u - k + 63) / 64;
+                for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
+            }
+            l.count = (int)(fwork.size() - l.off);
+            ds.ldlt.push_back(l);
+            Launch t{(int64_t)fwork.size(), 0, k};
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                int b = std::min(NB, f.s - k);
+                int tr = f.s + f.u - k - b;
+                if (tr <= 0) continue;
+                int nt = (tr + TILE - 1) / TILE;
+                for (int q = 0; q < nt * (nt + 1) / 2; ++q) fwork.push_back(make_int2(i, q));
+            }
+            t.count = (int)(fwork.size() - t.off);
+            ds.trail.push_back(t);
+        }
+    }
+    ctx->inv_launch.off = (int64_t)fwork.size();
+    for (size_t i = 0; i < ctx->inst_h.size(); ++i) {
+        const FrontInst& f = ctx->inst_h[i];
+        int nrb = (f.s + f.u + 63) / 64;
+        for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2((int)i, rb));
+    }
+    ctx->inv_launch.count = (int)(fwork.size() - ctx->inv_launch.off);
+    // solve work lists per class and depth
+    ctx->slevels.assign(ctx->classes.size(), {});
+    for (size_t ci = 0; ci < ctx->classes.size(); ++ci) {
+        const PanelClass& c = ctx->classes[ci];
+        ctx->slevels[ci].assign(c.maxdepth + 1, SolveLevel{});
+        for (int d = 0; d <= c.maxdepth; ++d) {
+            SolveLevel& sl = ctx->slevels[ci][d];
+            sl.foff = (int64_t)swork.size();
+            swork.insert(swork.end(), c.fwd_work[d].begin(), c.fwd_work[d].end());
+            sl.fcount = (int)c.fwd_work[d].size() / 2;
+            sl.boff = (int64_t)swork.size();
+            swork.insert(swork.end(), c.bwd_work[d].begin(), c.bwd_work[d].end());
+            sl.bcount = (int)c.bwd_work[d].size() / 2;
+            for (int f : c.at_depth[d]) {
+                sl.smax = std::max(sl.smax, c.s[f]);
+                sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precision prec,
+                                 void* stream, hsw_ctx** out) {
+    if (!out) return HSW_E_INVAL;
+    *out = nullptr;
+    if (!p || nprob < 1) {
+        g_create_error = "need at least one problem";
+        return HSW_E_INVAL;
+    }
+    if (prec != HSW_C128 && prec != HSW_C64 && prec != HSW_C64_BF16GEMM) {
+        g_create_error = "unknown precision";
+        return HSW_E_INVAL;
+    }
+    hsw_ctx* ctx = new hsw_ctx();
+    ctx->st = (hipStream_t)stream;
+    ctx->prec = prec;
+    ctx->esz = prec == HSW_C128 ? 16 : 8;
+    ctx->probs.assign(p, p + nprob);
+    hsw_status s = plan_all(ctx, p, nprob);
+    if (s != HSW_OK) {
+        g_create_error = ctx->err;
+        delete ctx;
+        return s;
+    }
+    std::vector<int2> fwork;
+    std::vector<int> swork;
+    schedule_all(ctx, fwork, swork);
+    // stretch tables: per problem 3 axes, per panel one x3 table
+    int64_t eo = 0;
+    for (size_t k = 0; k < ctx->ph.size(); ++k) {
+        ctx->et_prob_off.push_back(eo);
+        for (int j = 0; j < 3; ++j) eo += 2 * ctx->ph[k].N[j] + 1;
+    }
+    for (auto& P : ctx->pan_h) {
+        P.e3_off = (int32_t)eo;
+        ctx->et_panel_off.push_back(eo);
+        eo += 2 * P.nz + 1;
+    }
+    ctx->et_size = eo;
+    for (size_t k = 0; k < ctx->ph.size(); ++k) {
+        ProbDev Q{};
+        const hsw_problem& q = ctx->probs[k];
+        for (int j = 0; j < 3; ++j) {
+            Q.n[j] = q.n[j];
+            Q.N[j] = ctx->ph[k].N[j];
+        }
+        Q.gamma = q.gamma;
+        Q.Npad = ctx->ph[k].Npad;
+        Q.h = q.h;
+        Q.omega = q.omega;
+        Q.alpha = q.alpha;
+        int64_t o = ctx->et_prob_off[k];
+        for (int j = 0; j < 3; ++j) {
+            Q.e_off[j] = (int32_t)o;
+            o += 2 * Q.N[j] + 1;
+        }
+        Q.c = nullptr;  // set after allocation
+        ctx->prob_h.push_back(Q);
+    }
+    // memory sizing, checked before any allocation
+    int64_t nint_total = 0;
+    for (auto& h : ctx->ph) nint_total += h.Nint;
+    size_t ints = 0;
+    for (auto& c : ctx->classes) ints += 2 * (size_t)c.naux + c.ulist.size() + c.cmap.size();
+    const size_t need = (size_t)ctx->esz * (2 * ctx->L_size + ctx->D_size + ctx->ws_size[0] +
+                                             ctx->ws_size[1]) +
+                        sizeof(FrontInst) * ctx->inst_h.size() + sizeof(PanelDev) * ctx->pan_h.size() +
+                        sizeof(ProbDev) * ctx->prob_h.size() + 4 * ints + 8 * fwork.size() +
+                        4 * swork.size() + 16 * (size_t)eo + 8 * (size_t)nint_total;
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+        g_create_error = "hipMemGetInfo failed (no device?)";
+        delete ctx;
+        return HSW_E_DEVICE;
+    }
+    if (need > freeb / 100 * 95) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory, %.3f GB free",
+                 need / 1e9, freeb / 1e9);
+        g_create_error = buf;
+        delete ctx;
+        return HSW_E_NOMEM;
+    }
+#define ACHK(expr)                                                      \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) {                                         \
+            g_create_error = std::string(#expr) + ": " + hipGetErrorString(e_); \
+            free_all(ctx);                                              \
+            delete ctx;                                                 \
+            return HSW_E_DEVICE;                                        \
+        }                                                               \
+    } while (0)
+    ACHK(dalloc(&ctx->d_c, 8 * (size_t)nint_total));
+    for (size_t k = 0; k < ctx->prob_h.size(); ++k) ctx->prob_h[k].c = ctx->d_c + ctx->ph[k].c_off;
+    ACHK(dalloc(&ctx->d_inst, sizeof(FrontInst) * ctx->inst_h.size()));
+    ACHK(dalloc(&ctx->d_pan, sizeof(PanelDev) * ctx->pan_h.size()));
+    ACHK(dalloc(&ctx->d_prob, sizeof(ProbDev) * ctx->prob_h.size()));
+    std::vector<int> perm, iperm, ul, cm;
+    for (auto& c : ctx->classes) {
+        perm.insert(perm.end(), c.perm.begin(), c.perm.end());
+        iperm.insert(iperm.end(), c.iperm.begin(), c.iperm.end());
+        ul.insert(ul.end(), c.ulist.begin(), c.ulist.end());
+        cm.insert(cm.end(), c.cmap.begin(), c.cmap.end());
+    }
+    ACHK(dalloc(&ctx->d_perm, 4 * perm.size()));
+    ACHK(dalloc(&ctx->d_iperm, 4 * iperm.size()));
+    ACHK(dalloc(&ctx->d_ulist, 4 * std::max<size_t>(ul.size(), 1)));
+    ACHK(dalloc(&ctx->d_cmap, 4 * std::max<size_t>(cm.size(), 1)));
+    ACHK(dalloc(&ctx->d_fwork, 8 * std::max<size_t>(fwork.size(), 1)));
+    ACHK(dalloc(&ctx->d_swork, 4 * std::max<size_t>(swork.size(), 1)));
+    ACHK(dalloc(&ctx->d_et, 16 * (size_t)eo));
+    ACHK(dalloc(&ctx->d_L, (size_t)ctx->esz * ctx->L_size));
+    ACHK(dalloc(&ctx->d_G, (size_t)ctx->esz * ctx->L_size));
+    ACHK(dalloc(&ctx->d_dinv, (size_t)ctx->esz * ctx->D_size));
+    ACHK(dalloc(&ctx->d_ws[0], (size_t)ctx->esz * std::max<int64_t>(ctx->ws_size[0], 1)));
+    ACHK(dalloc(&ctx->d_ws[1], (size_t)ctx->esz * std::max<int64_t>(ctx->ws_size[1], 1)));
+    ACHK(dalloc(&ctx->d_err, 2 * sizeof(int)));
+    hipStream_t st = ctx->st;
+    ACHK(hipMemcpyAsync(ctx->d_inst, ctx->inst_h.data(), sizeof(FrontInst) * ctx->inst_h.size(),
+                        hipMemcpyHostToDevice, st));
+    ACHK(hipMemcpyAsync(ctx->d_pan, ctx->pan_h.data(), sizeof(PanelDev) * ctx->pan_h.size(),
+                        hipMemcpyHostToDevice, st));
+    ACHK(hipMemcpyAsync(ctx->d_prob, ctx->prob_h.data(), sizeof(ProbDev) * ctx->prob_h.size(),
+                        hipMemcpyHostToDevice, st));
+    ACHK(hipMemcpyAsync(ctx->d_perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice, st));
+    ACHK(hipMemcpyAsync(ctx->d_iperm, iperm.data(), 4 * iperm.size(), hipMemcpyHostToDevice, st));
+    if (!ul.empty())
+        ACHK(hipMemcpyAsync(ctx->d_ulist, ul.data(), 4 * ul.size(), hipMemcpyHostToDevice, st));
+    if (!cm.empty())
+        ACHK(hipMemcpyAsync(ctx->d_cmap, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice, st));
+    if (!fwork.empty())
+        ACHK(hipMemcpyAsync(ctx->d_fwork, fwork.data(), 8 * fwork.size(), hipMemcpyHostToDevice, st));
+    if (!swork.empty())
+        ACHK(hipMemcpyAsync(ctx->d_swork, swork.data(), 4 * swork.size(), hipMemcpyHostToDevice, st));
+    ACHK(hipStreamSynchronize(st));
+#undef ACHK
+    *out = ctx;
+    return HSW_OK;
+}
+
+extern "C" void hsw_destroy(hsw_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    free_all(ctx);
+    delete ctx;
+}
+
+extern "C" const char* hsw_last_error(const hsw_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" hsw_status hsw_assemble(hsw_ctx* ctx, const double* const* c) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!c) return fail(ctx, HSW_E_INVAL, "c is NULL");
+    hipStream_t st = ctx->st;
+    HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int), st));
+    for (size_t k = 0; k < ctx->ph.size(); ++k) {
+        if (!c[k]) return fail(ctx, HSW_E_INVAL, "c[k] is NULL");
+        const ProbHost& h = ctx->ph[k];
+        HIPCHK(hipMemcpyAsync(ctx->d_c + h.c_off, c[k], 8 * (size_t)h.Nint, hipMemcpyDeviceToDevice, st));
+        launch_check_velocity(ctx->d_c + h.c_off, h.Nint, ctx->d_err, st);
+        const hsw_problem& q = ctx->probs[k];
+        for (int j = 0; j < 3; ++j)
+            launch_axis_table(ctx->d_et + ctx->prob_h[k].e_off[j], q.n[j], q.gamma, q.h, q.pml_amp,
+                              q.omega, st);
+    }
+    for (auto& P : ctx->pan_h) {
+        const hsw_problem& q = ctx->probs[P.prob];
+        launch_aux_table(ctx->d_et + P.e3_off, q.n[2], q.gamma, P.lo, P.ga, P.nz, q.h, q.pml_amp,
+                         q.omega, st);
+    }
+    HIPCHK(hipGetLastError());
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) return fail(ctx, HSW_E_INVAL, "velocity must be positive and finite");
+    ctx->assembled = true;
+    ctx->factored = false;
+    return HSW_OK;
+}
+
+template <typename T>
+static hsw_status setup_impl(hsw_ctx* ctx) {
+    hipStream_t st = ctx->st;
+    Cx<T>* L = (Cx<T>*)ctx->d_L;
+    Cx<T>* G = (Cx<T>*)ctx->d_G;
+    Cx<T>* dinv = (Cx<T>*)ctx->d_dinv;
+    Cx<T>* ws[2] = {(Cx<T>*)ctx->d_ws[0], (Cx<T>*)ctx->d_ws[1]};
+    HIPCHK(hipMemsetAsync(ctx->d_err, 0xff, 2 * sizeof(int), st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    for (int d = ctx->maxdepth; d >= 0; --d) {
+        const DepthSchedule& ds = ctx->fsched[d];
+        launch_assemble<T>(ctx->d_fwork + ds.assemble.off, ds.assemble.count, ctx->d_inst, ctx->d_pan,
+                           ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap, ctx->d_et, L,
+                           ws[d & 1], ws[(d + 1) & 1], st);
+        for (size_t s = 0; s < ds.ldlt.size(); ++s) {
+            launch_ldlt_panel<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L, dinv,
+                                 ds.ldlt[s].k, ctx->d_err, st);
+            launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
+                               ws[d & 1], ds.trail[s].k, st);
+        }
+    }
+    launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L, G, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, st));
+    int err[2];
+    HIPCHK(hipMemcpyAsync(err, ctx->d_err, sizeof err, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->t_setup = ms * 1e-3;
+    ctx->bad_inst = err[0];
+    ctx->bad_pivot = err[1];
+    if (err[0] >= 0) {
+        const FrontInst& f = ctx->inst_h[err[0]];
+        const PanelDev& P = ctx->pan_h[f.panel];
+        char buf[200];
+        snprintf(buf, sizeof buf, "zero or non-finite pivot: problem %d panel %d front %d pivot %d",
+                 P.prob, f.panel - ctx->ph[P.prob].panel_base, err[0] - P.inst_base, err[1]);
+        ctx->factored = false;
+        return fail(ctx, HSW_E_BREAKDOWN, buf);
+    }
+    ctx->factored = true;
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_setup(hsw_ctx* ctx) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->assembled) return fail(ctx, HSW_E_STATE, "setup before assemble");
+    return ctx->prec == HSW_C128 ? setup_impl<double>(ctx) : setup_impl<float>(ctx);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static hsw_status ensure_solve_ws(hsw_ctx* ctx, int nrhs) {
+    if (nrhs <= ctx->nrhs_cap) return HSW_OK;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    for (void** p : {&ctx->d_xin, &ctx->d_xmid, &ctx->d_xout, &ctx->d_wv}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    const size_t xb = sizeof(Cx<T>) * (size_t)ctx->max_naux * nrhs;
+    const size_t wb = sizeof(Cx<T>) * (size_t)std::max<int64_t>(ctx->max_wsize, 1) * nrhs;
+    HIPCHK(hipMalloc(&ctx->d_xin, xb));
+    HIPCHK(hipMalloc(&ctx->d_xmid, xb));
+    HIPCHK(hipMalloc(&ctx->d_xout, xb));
+    HIPCHK(hipMalloc(&ctx->d_wv, wb));
+    ctx->nrhs_cap = nrhs;
+    return HSW_OK;
+}
+
+// y (panel planes of dst) := T_i applied to the gathered right-hand side.
+template <typename T>
+static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* src, int64_t ld,
+                         int plane0, int emode, int couple, Cx<double>* dst, int nrhs) {
+    hipStream_t st = ctx->st;
+    const PanelDev& P = ctx->pan_h[gpanel];
+    const ProbDev& Q = ctx->prob_h[P.prob];
+    const PanelClass& c = ctx->classes[P.cls];
+    const int naux = c.naux;
+    const int Wld = (int)std::max<int64_t>(c.wsize, 1);
+    Cx<T>* xin = (Cx<T>*)ctx->d_xin;
+    Cx<T>* xmid = (Cx<T>*)ctx->d_xmid;
+    Cx<T>* xout = (Cx<T>*)ctx->d_xout;
+    Cx<T>* wv = (Cx<T>*)ctx->d_wv;
+    const Cx<T>* G = (const Cx<T>*)ctx->d_G;
+    const Cx<T>* dinv = (const Cx<T>*)ctx->d_dinv;
+    launch_gather<T>(gmode, Q, P, ctx->d_perm, ctx->d_et, src, ld, plane0, nrhs, xin, naux, st);
+    const auto& lv = ctx->slevels[P.cls];
+    for (int d = c.maxdepth; d >= 0; --d)
+        launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, P.inst_base, ctx->d_inst, G, dinv,
+                      ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
+    for (int d = 0; d <= c.maxdepth; ++d)
+        launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, P.inst_base, ctx->d_inst, G,
+                      ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
+    launch_extract<T>(emode, couple, Q, P, ctx->d_iperm, ctx->d_et, xout, naux, dst, ld, plane0, nrhs, st);
+}
+
+// z := M^{-1} r (Alg. 1.5), r may equal z.
+template <typename T>
+static hsw_status sweep_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
+                             int64_t ld) {
+    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+    if (s != HSW_OK) return s;
+    const ProbHost& h = ctx->ph[prob];
+    if (r != z)
+        HIPCHK(hipMemcpy2DAsync(z, 16 * ld, r, 16 * ld, 16 * h.Npad, nrhs, hipMemcpyDeviceToDevice,
+                                ctx->st));
+    for (int i = 0; i < h.m; ++i)
+        panel_tsolve<T>(ctx, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs);
+    for (int i = h.m - 2; i >= 0; --i) panel_tsolve<T>(ctx, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs);
+    HIPCHK(hipGetLastError());
+    return HSW_OK;
+}
+
+static hsw_status check_vec_args(hsw_ctx* ctx, int32_t prob, const void* a, const void* b,
+                                 int32_t nrhs, int64_t ld, int64_t minld) {
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
+    if (!a || !b) return fail(ctx, HSW_E_INVAL, "NULL vector");
+    if (nrhs < 1 || ld < minld) return fail(ctx, HSW_E_INVAL, "nrhs >= 1 and ld >= vector length required");
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, hsw_c128* z,
+                                int32_t nrhs, int64_t ld) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->factored) return fail(ctx, HSW_E_STATE, "apply before setup");
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
+    hsw_status s = check_vec_args(ctx, prob, r, z, nrhs, ld, ctx->ph[prob].Npad);
+    if (s != HSW_OK) return s;
+    if ((const void*)r == (const void*)z) return fail(ctx, HSW_E_INVAL, "r and z alias");
+    return ctx->prec == HSW_C128
+               ? sweep_impl<double>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld)
+               : sweep_impl<float>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
+}
+
+extern "C" hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel, const hsw_c128* v,
+                                      hsw_c128* y, int32_t nrhs, int64_t ld) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->factored) return fail(ctx, HSW_E_STATE, "panel solve before setup");
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
+    const ProbHost& h = ctx->ph[prob];
+    if (panel < 0 || panel >= h.m) return fail(ctx, HSW_E_INVAL, "bad panel index");
+    const PanelDev& P = ctx->pan_h[h.panel_base + panel];
+    hsw_status s = check_vec_args(ctx, prob, v, y, nrhs, ld, (int64_t)(P.hi - P.lo) * P.Nx * P.Ny);
+    if (s != HSW_OK) return s;
+    if ((const void*)v == (const void*)y) return fail(ctx, HSW_E_INVAL, "v and y alias");
+    if (ctx->prec == HSW_C128) {
+        s = ensure_solve_ws<double>(ctx, nrhs);
+        if (s != HSW_OK) return s;
+        panel_tsolve<double>(ctx, h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
+                             (Cx<double>*)y, nrhs);
+    } else {
+        s = ensure_solve_ws<float>(ctx, nrhs);
+        if (s != HSW_OK) return s;
+        panel_tsolve<float>(ctx, h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
+                            (Cx<double>*)y, nrhs);
+    }
+    HIPCHK(hipGetLastError());
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, hsw_c128* y,
+                                 int32_t nrhs, int64_t ld) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->assembled) return fail(ctx, HSW_E_STATE, "matvec before assemble");
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
+    hsw_status s = check_vec_args(ctx, prob, x, y, nrhs, ld, ctx->ph[prob].Npad);
+    if (s != HSW_OK) return s;
+    if ((const void*)x == (const void*)y) return fail(ctx, HSW_E_INVAL, "x and y alias");
+    launch_matvec(ctx->prob_h[prob], ctx->d_et, (const Cx<double>*)x, (Cx<double>*)y, nullptr, ld, nrhs,
+                  0, ctx->st);
+    HIPCHK(hipGetLastError());
+    return HSW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Flexible right-preconditioned GMRES(k) of one problem, all right-hand
+// sides advanced together; classical Gram-Schmidt applied twice.
+template <typename T>
+static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x, int nrhs,
+                             const hsw_solve_opts& o, int* iters_out, double* relres_out) {
+    hipStream_t st = ctx->st;
+    const ProbHost& hp = ctx->ph[prob];
+    const ProbDev& Q = ctx->prob_h[prob];
+    const int64_t N = hp.Npad, ld = N;
+    const int k = o.restart_k;
+    const int64_t vs = N * nrhs;
+    const int nch = dots_chunks(N);
+    const int hld = (k + 1) * k;
+    Cx<double> *V = nullptr, *Z = nullptr, *H = nullptr, *coef = nullptr, *sn = nullptr, *g = nullptr,
+               *y = nullptr, *part = nullptr;
+    double *cs = nullptr, *bn = nullptr, *beta = nullptr, *est = nullptr, *nrm = nullptr, *partn = nullptr;
+    int *act = nullptr, *jc = nullptr;
+    auto cleanup = [&]() {
+        void* ps[] = {V, Z, H, coef, sn, g, y, part, cs, bn, beta, est, nrm, partn, act, jc};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+    };
+#define GCHK(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+            cleanup();                                                                 \
+            return HSW_E_DEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+    GCHK(hipMalloc(&V, 16 * (size_t)vs * (k + 1)));
+    GCHK(hipMalloc(&Z, 16 * (size_t)vs * k));
+    GCHK(hipMalloc(&H, 16 * (size_t)nrhs * hld));
+    GCHK(hipMalloc(&coef, 16 * (size_t)nrhs * hld));
+    GCHK(hipMalloc(&sn, 16 * (size_t)nrhs * k));
+    GCHK(hipMalloc(&g, 16 * (size_t)nrhs * (k + 1)));
+    GCHK(hipMalloc(&y, 16 * (size_t)nrhs * k));
+    GCHK(hipMalloc(&part, 16 * (size_t)nrhs * nch * (k + 1)));
+    GCHK(hipMalloc(&cs, 8 * (size_t)nrhs * k));
+    GCHK(hipMalloc(&bn, 8 * (size_t)nrhs));
+    GCHK(hipMalloc(&beta, 8 * (size_t)nrhs));
+    GCHK(hipMalloc(&est, 8 * (size_t)nrhs));
+    GCHK(hipMalloc(&nrm, 8 * (size_t)nrhs));
+    GCHK(hipMalloc(&partn, 8 * (size_t)nrhs * nch));
+    GCHK(hipMalloc(&act, 4 * (size_t)nrhs));
+    GCHK(hipMalloc(&jc, 4 * (size_t)nrhs));
+    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+    if (s != HSW_OK) { cleanup(); return s; }
+    std::vector<double> bn_h(nrhs), beta_h(nrhs), est_h(nrhs), rel(nrhs, 1.0);
+    std::vector<int> act_h(nrhs), it_h(nrhs, 0), jc_h(nrhs), done(nrhs, 0);
+    GCHK(hipMemsetAsync(H, 0, 16 * (size_t)nrhs * hld, st));
+    GCHK(hipMemset2DAsync(x, 16 * ld, 0, 16 * N, nrhs, st));
+    launch_norm(b, ld, N, nrhs, nullptr, partn, bn, nullptr, 0, st);
+    GCHK(hipMemcpyAsync(bn_h.data(), bn, 8 * nrhs, hipMemcpyDeviceToHost, st));
+    GCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) {
+        done[r] = !(bn_h[r] > 0);
+        if (done[r]) rel[r] = 0.0;
+    }
+    while (true) {
+        // true residual r = b - A x into V_0
+        launch_matvec(Q, ctx->d_et, x, V, b, ld, nrhs, 1, st);
+        launch_norm(V, ld, N, nrhs, nullptr, partn, beta, nullptr, 0, st);
+        GCHK(hipMemcpyAsync(beta_h.data(), beta, 8 * nrhs, hipMemcpyDeviceToHost, st));
+        GCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!(bn_h[r] > 0)) { act_h[r] = 0; continue; }
+            rel[r] = beta_h[r] / bn_h[r];
+            if (rel[r] < o.rtol || it_h[r] >= o.maxit) done[r] = 1;
+            act_h[r] = !done[r];
+            any = any || act_h[r];
+        }
+        if (!any) break;
+        GCHK(hipMemcpyAsync(act, act_h.data(), 4 * nrhs, hipMemcpyHostToDevice, st));
+        launch_scale(V, V, ld, N, nrhs, beta, act, st);
+        launch_cycle_init(k, nrhs, beta, g, act, st);
+        std::fill(jc_h.begin(), jc_h.end(), 0);
+        for (int j = 0; j < k; ++j) {
+            Cx<double>* Vj = V + (int64_t)j * vs;
+            Cx<double>* Vn = V + (int64_t)(j + 1) * vs;
+            Cx<double>* Zj = Z + (int64_t)j * vs;
+            s = sweep_impl<T>(ctx, prob, Vj, Zj, nrhs, ld);
+            if (s != HSW_OK) { cleanup(); return s; }
+            launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st);
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
+                            pass, st);
+                launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
+            }
+            launch_norm(Vn, ld, N, nrhs, act, partn, nrm, H + (int64_t)j * (k + 1) + j + 1, hld, st);
+            launch_scale(Vn, Vn, ld, N, nrhs, nrm, act, st);
+            launch_givens(j, k, nrhs, H, cs, sn, g, bn, est, act, st);
+            GCHK(hipGetLastError());
+            GCHK(hipMemcpyAsync(est_h.data(), est, 8 * nrhs, hipMemcpyDeviceToHost, st));
+            GCHK(hipStreamSynchronize(st));
+            bool still = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!act_h[r]) continue;
+                it_h[r] += 1;
+                jc_h[r] = j + 1;
+                if (est_h[r] < o.rtol || it_h[r] >= o.maxit) act_h[r] = 0;
+                still = still || act_h[r];
+            }
+            if (!still) break;
+            GCHK(hipMemcpyAsync(act, act_h.data(), 4 * nrhs, hipMemcpyHostToDevice, st));
+        }
+        GCHK(hipMemcpyAsync(jc, jc_h.data(), 4 * nrhs, hipMemcpyHostToDevice, st));
+        launch_lsq(k, nrhs, H, g, jc, y, st);
+        launch_axpy_multi(Z, vs, x, ld, N, k, y, k, jc, nullptr, 1, nrhs, st);
+        GCHK(hipGetLastError());
+    }
+    bool ok = true;
+    for (int r = 0; r < nrhs; ++r) {
+        if (iters_out) iters_out[r] = it_h[r];
+        if (relres_out) relres_out[r] = rel[r];
+        ok = ok && rel[r] < o.rtol;
+    }
+    cleanup();
+#undef GCHK
+    return ok ? HSW_OK : HSW_E_NOCONV;
+}
+
+extern "C" hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128* const* x,
+                                const int32_t* nrhs, const hsw_solve_opts* opts, hsw_solve_info* info) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->factored) return fail(ctx, HSW_E_STATE, "solve before setup");
+    if (!b || !x || !nrhs) return fail(ctx, HSW_E_INVAL, "NULL argument");
+    hsw_solve_opts o{20, 1000, 1e-5};
+    if (opts) o = *opts;
+    if (o.restart_k < 1 || o.maxit < 1 || !(o.rtol > 0))
+        return fail(ctx, HSW_E_INVAL, "restart_k >= 1, maxit >= 1, rtol > 0 required");
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, ctx->st));
+    hsw_status worst = HSW_OK;
+    int off = 0, itmax = 0;
+    for (size_t k = 0; k < ctx->ph.size(); ++k) {
+        if (!b[k] || !x[k] || nrhs[k] < 1) return fail(ctx, HSW_E_INVAL, "bad right-hand side block");
+        std::vector<int> it(nrhs[k]);
+        std::vector<double> rr(nrhs[k]);
+        hsw_status s = ctx->prec == HSW_C128
+                           ? gmres_impl<double>(ctx, (int)k, (const Cx<double>*)b[k], (Cx<double>*)x[k],
+                                                nrhs[k], o, it.data(), rr.data())
+                           : gmres_impl<float>(ctx, (int)k, (const Cx<double>*)b[k], (Cx<double>*)x[k],
+                                               nrhs[k], o, it.data(), rr.data());
+        if (s != HSW_OK && s != HSW_E_NOCONV) return s;
+        if (s == HSW_E_NOCONV) worst = s;
+        for (int r = 0; r < nrhs[k]; ++r) {
+            if (info && info->iters) info->iters[off + r] = it[r];
+            if (info && info->relres) info->relres[off + r] = rr[r];
+            itmax = std::max(itmax, it[r]);
+        }
+        off += nrhs[k];
+    }
+    HIPCHK(hipEventRecord(e1, ctx->st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (info) {
+        info->iters_max = itmax;
+        info->t_setup = ctx->t_setup;
+        info->t_solve = ms * 1e-3;
+        info->bad_problem = info->bad_panel = info->bad_front = info->bad_pivot = -1;
+    }
+    if (worst == HSW_E_NOCONV) ctx->err = "GMRES did not reach rtol within maxit";
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hsw_status hsw_query(const hsw_ctx* cctx, int32_t prob, const char* key, int64_t* val) {
+    hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
+    if (!ctx || !key || !val) return HSW_E_INVAL;
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
+    const ProbHost& h = ctx->ph[prob];
+    std::string k(key);
+    auto panel_of = [&](int64_t i) -> const PanelDev* {
+        if (i < 0 || i >= h.m) return nullptr;
+        return &ctx->pan_h[h.panel_base + i];
+    };
+    if (k == "N_pad") *val = h.Npad;
+    else if (k == "N_int") *val = h.Nint;
+    else if (k == "m") *val = h.m;
+    else if (k == "N1") *val = h.N[0];
+    else if (k == "N2") *val = h.N[1];
+    else if (k == "N3") *val = h.N[2];
+    else if (k == "levels") *val = h.levels;
+    else if (k == "fronts") *val = ctx->classes[ctx->pan_h[h.panel_base].cls].nfront;
+    else if (k == "factor_bytes") *val = (int64_t)h.factor_entries * ctx->esz;
+    else if (k == "setup_flops") *val = (int64_t)(8.0 * (h.setup_cmac + h.inverse_cmac));
+    else if (k == "factor_flops") *val = (int64_t)(8.0 * h.setup_cmac);
+    else if (k == "apply_flops") *val = (int64_t)(8.0 * h.apply_cmac);
+    else if (k == "panel_lo" || k == "panel_hi" || k == "panel_nz" || k == "panel_artificial" ||
+             k == "panel_naux") {
+        const PanelDev* P = panel_of(*val);
+        if (!P) return fail(ctx, HSW_E_INVAL, "bad panel index");
+        if (k == "panel_lo") *val = P->lo;
+        else if (k == "panel_hi") *val = P->hi;
+        else if (k == "panel_nz") *val = P->nz;
+        else if (k == "panel_artificial") *val = P->ga;
+        else *val = ctx->classes[P->cls].naux;
+    } else {
+        return fail(ctx, HSW_E_INVAL, "unknown key " + k);
+    }
+    return HSW_OK;
+}
+
+static const PanelDev* get_panel(hsw_ctx* ctx, int prob, int panel) {
+    if (prob < 0 || prob >= (int)ctx->ph.size()) return nullptr;
+    const ProbHost& h = ctx->ph[prob];
+    if (panel < 0 || panel >= h.m) return nullptr;
+    return &ctx->pan_h[h.panel_base + panel];
+}
+
+extern "C" hsw_status hsw_get_perm(const hsw_ctx* cctx, int32_t prob, int32_t panel, int32_t* perm_host) {
+    hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
+    if (!ctx || !perm_host) return HSW_E_INVAL;
+    const PanelDev* P = get_panel(ctx, prob, panel);
+    if (!P) return fail(ctx, HSW_E_INVAL, "bad problem or panel index");
+    const PanelClass& c = ctx->classes[P->cls];
+    std::memcpy(perm_host, c.perm.data(), 4 * (size_t)c.naux);
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_get_front_info(const hsw_ctx* cctx, int32_t prob, int32_t panel,
+                                         int32_t front, int32_t* info, int32_t* urows) {
+    hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
+    if (!ctx || !info) return HSW_E_INVAL;
+    const PanelDev* P = get_panel(ctx, prob, panel);
+    if (!P) return fail(ctx, HSW_E_INVAL, "bad problem or panel index");
+    const PanelClass& c = ctx->classes[P->cls];
+    if (front < 0 || front >= c.nfront) return fail(ctx, HSW_E_INVAL, "bad front index");
+    info[0] = c.start[front];
+    info[1] = c.s[front];
+    info[2] = c.u[front];
+    info[3] = c.parent[front];
+    info[4] = c.depth[front];
+    if (urows) std::memcpy(urows, c.ulist.data() + c.uoff[front], 4 * (size_t)c.u[front]);
+    return HSW_OK;
+}
+
+template <typename T>
+static hsw_status copy_block(hsw_ctx* ctx, const void* base, int64_t off, int64_t count,
+                             std::vector<Cx<double>>& out) {
+    std::vector<Cx<T>> tmp(count);
+    HIPCHK(hipMemcpy(tmp.data(), (const Cx<T>*)base + off, sizeof(Cx<T>) * count, hipMemcpyDeviceToHost));
+    out.resize(count);
+    for (int64_t i = 0; i < count; ++i) out[i] = ccast<double>(tmp[i]);
+    return HSW_OK;
+}
+
+static hsw_status front_block(hsw_ctx* ctx, int prob, int panel, int front, const void* base,
+                              std::vector<Cx<double>>& blk, int& s, int& u) {
+    if (!ctx->factored) return fail(ctx, HSW_E_STATE, "factors not available before setup");
+    const PanelDev* P = get_panel(ctx, prob, panel);
+    if (!P) return fail(ctx, HSW_E_INVAL, "bad problem or panel index");
+    if (front < 0 || front >= P->nfront) return fail(ctx, HSW_E_INVAL, "bad front index");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    const FrontInst& f = ctx->inst_h[P->inst_base + front];
+    s = f.s;
+    u = f.u;
+    const int64_t cnt = (int64_t)(f.s + f.u) * f.s;
+    return ctx->prec == HSW_C128 ? copy_block<double>(ctx, base, f.loff, cnt, blk)
+                                 : copy_block<float>(ctx, base, f.loff, cnt, blk);
+}
+
+extern "C" hsw_status hsw_get_front(const hsw_ctx* cctx, int32_t prob, int32_t panel, int32_t front,
+                                    hsw_c128* D, hsw_c128* L_TL, hsw_c128* F_BL, int32_t* ps,
+                                    int32_t* pu) {
+    hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
+    if (!ctx) return HSW_E_INVAL;
+    std::vector<Cx<double>> blk;
+    int s = 0, u = 0;
+    hsw_status st = front_block(ctx, prob, panel, front, ctx->d_L, blk, s, u);
+    if (st != HSW_OK) return st;
+    const int n = s + u;
+    if (ps) *ps = s;
+    if (pu) *pu = u;
+    for (int j = 0; j < s; ++j) {
+        if (D) D[j] = {blk[(int64_t)j * n + j].re, blk[(int64_t)j * n + j].im};
+        if (L_TL)
+            for (int i = 0; i < s; ++i) {
+                Cx<double> v = i > j ? blk[(int64_t)j * n + i] : cx<double>(i == j ? 1.0 : 0.0, 0.0);
+                L_TL[(int64_t)j * s + i] = {v.re, v.im};
+            }
+        if (F_BL)
+            for (int i = 0; i < u; ++i) {
+                Cx<double> v = blk[(int64_t)j * n + s + i];
+                F_BL[(int64_t)j * u + i] = {v.re, v.im};
+            }
+    }
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_get_front_inverse(const hsw_ctx* cctx, int32_t prob, int32_t panel,
+                                            int32_t front, hsw_c128* G) {
+    hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
+    if (!ctx || !G) return HSW_E_INVAL;
+    std::vector<Cx<double>> blk;
+    int s = 0, u = 0;
+    hsw_status st = front_block(ctx, prob, panel, front, ctx->d_G, blk, s, u);
+    if (st != HSW_OK) return st;
+    for (size_t i = 0; i < blk.size(); ++i) G[i] = {blk[i].re, blk[i].im};
+    return HSW_OK;
+}

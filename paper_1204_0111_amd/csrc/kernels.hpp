@@ -1,0 +1,74 @@
+// Host-side launchers of the gfx950 kernels.
+#pragma once
+
+#include "devtypes.hpp"
+#include "plan.hpp"
+
+namespace hsw {
+
+// factor.hip
+template <typename T>
+void launch_assemble(const int2* work, int nwork, const FrontInst* inst, const PanelDev* pan,
+                     const ProbDev* prob, const int* perm, const int* ulist, const int* cmap,
+                     const Cx<double>* et, Cx<T>* Lb, Cx<T>* Wcur, const Cx<T>* Wchild,
+                     hipStream_t st);
+template <typename T>
+void launch_ldlt_panel(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
+                       int k, int* err, hipStream_t st);
+template <typename T>
+void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
+                     int k, hipStream_t st);
+template <typename T>
+void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
+                    hipStream_t st);
+
+// solve.hip
+template <typename T>
+void launch_gather(int mode, const ProbDev& Q, const PanelDev& P, const int* perm,
+                   const Cx<double>* et, const Cx<double>* u, int64_t ld, int plane0, int nrhs,
+                   Cx<T>* xin, int naux, hipStream_t st);
+template <typename T>
+void launch_extract(int mode, int couple, const ProbDev& Q, const PanelDev& P, const int* iperm,
+                    const Cx<double>* et, const Cx<T>* xout, int naux, Cx<double>* u, int64_t ld,
+                    int plane0, int nrhs, hipStream_t st);
+template <typename T>
+void launch_fwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
+                int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st);
+template <typename T>
+void launch_bwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
+                hipStream_t st);
+template <typename T>
+int solve_rhs_chunk(int nrhs, int nmax);
+
+// assemble.hip
+void launch_axis_table(Cx<double>* out, int nj, int gj, double h, double C, double omega,
+                       hipStream_t st);
+void launch_aux_table(Cx<double>* out, int n3, int g, int lo, int ga, int nz, double h, double C,
+                      double omega, hipStream_t st);
+void launch_check_velocity(const double* c, int64_t n, int* bad, hipStream_t st);
+
+// krylov.hip
+void launch_matvec(const ProbDev& Q, const Cx<double>* et, const Cx<double>* x, Cx<double>* y,
+                   const Cx<double>* b, int64_t ld, int nrhs, int mode, hipStream_t st);
+int dots_chunks(int64_t N);
+void launch_dots(const Cx<double>* V, int64_t vstride, const Cx<double>* w, int64_t ld, int64_t N,
+                 int nvec, int nrhs, const int* active, Cx<double>* partial, Cx<double>* h, int hld,
+                 Cx<double>* hout, int mode, hipStream_t st);
+void launch_axpy_multi(const Cx<double>* V, int64_t vstride, Cx<double>* w, int64_t ld, int64_t N,
+                       int nvec, const Cx<double>* coef, int cld, const int* nvec_rhs,
+                       const int* active, int mode, int nrhs, hipStream_t st);
+void launch_norm(const Cx<double>* w, int64_t ld, int64_t N, int nrhs, const int* active,
+                 double* partial, double* norm, Cx<double>* hptr, int hld, hipStream_t st);
+void launch_scale(const Cx<double>* w, Cx<double>* v, int64_t ld, int64_t N, int nrhs,
+                  const double* norm, const int* active, hipStream_t st);
+void launch_givens(int j, int k, int nrhs, Cx<double>* H, double* cs, Cx<double>* sn,
+                   Cx<double>* g, const double* bnorm, double* est, const int* active,
+                   hipStream_t st);
+void launch_lsq(int k, int nrhs, const Cx<double>* H, const Cx<double>* g, const int* jcount,
+                Cx<double>* y, hipStream_t st);
+void launch_cycle_init(int k, int nrhs, const double* beta, Cx<double>* g, const int* active,
+                       hipStream_t st);
+
+}  // namespace hsw

@@ -1,0 +1,74 @@
+// Symbolic plan: nested dissection of the quasi-2D panels, front structure,
+// extend-add maps and the level schedules of the factorisation and solves.
+//
+// A panel's auxiliary box is Nx x Ny laterally and nz planes deep.  The
+// lateral box is dissected recursively (Sec. 2.1, Fig. 2.1): a box whose two
+// extents are both <= leaf is a leaf; otherwise the longer axis (the first
+// one on ties) is cut at x0 + floor(w/2) by a one-node-wide strip.  Because
+// the shallow x3 dimension is never split, every supernode is a lateral cell
+// set times all nz planes.  Supernodes are numbered in postorder, lower
+// coordinates first; inside a supernode the nodes are ordered with i1
+// fastest, then i2, then the plane index.  The update set of a supernode is
+// the set of nodes laterally adjacent to its subtree's box, over all planes,
+// in elimination order.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hsw {
+
+constexpr int TILE = 64;        // square tile of the front kernels
+constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
+constexpr int SOLVE_RB = 64;    // rows per workgroup in the forward solve
+constexpr int SOLVE_CB = 16;    // columns per workgroup in the backward solve
+
+struct LatNode {
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+    std::vector<int> cells;  // lateral index a1 + a2 * Nx, a1 fastest
+    int child[2] = {-1, -1};
+    int parent = -1;
+    int depth = 0;
+};
+
+struct LatTree {
+    int Nx = 0, Ny = 0, leaf = 0;
+    std::vector<LatNode> nodes;  // postorder
+    std::vector<int> owner;      // lateral cell -> supernode
+    std::vector<int> cellidx;    // lateral cell -> position in its supernode's cell list
+    int maxdepth = 0;
+};
+
+LatTree build_lateral_tree(int Nx, int Ny, int leaf);
+
+// Fronts of one panel class: a lateral tree extended over nz planes.
+struct PanelClass {
+    int Nx = 0, Ny = 0, nz = 0, leaf = 0;
+    int naux = 0, nfront = 0, maxdepth = 0;
+    std::vector<int> perm, iperm;  // elimination position <-> box index a1 + a2 Nx + q Nx Ny
+    std::vector<int> start, s, u, parent, child0, child1, depth;
+    std::vector<int> uoff, ulist;  // update sets, concatenated (elimination positions)
+    std::vector<int> moff, cmap;   // per front 2 (s+u) entries: position in child 0 / 1 update set or -1
+    std::vector<int64_t> loff;     // per front: offset of its (s+u) x s block, relative to the panel
+    std::vector<int> woff;         // per front: offset of its update vector (u entries per rhs)
+    int64_t lsize = 0;             // sum (s+u) s
+    int64_t wsize = 0;             // sum u
+    std::vector<std::vector<int>> at_depth;
+    // per-depth work lists of the solves: (front, block) pairs
+    std::vector<std::vector<int>> fwd_work, bwd_work;
+    double factor_cmac = 0, inverse_cmac = 0, solve_cmac = 0;  // per panel, per rhs for solves
+};
+
+// Returns an empty string on success, else an error message.
+std::string build_class(const LatTree& lt, int nz, PanelClass& pc);
+
+// Decomposition of a lower-triangular tile index t into (ti, tj), ti >= tj.
+inline void tri_decode(int t, int& ti, int& tj) {
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    ti = i;
+    tj = t - i * (i + 1) / 2;
+}
+
+}  // namespace hsw

@@ -1,0 +1,323 @@
+// Panel solves T_i (Sec. 1.1, Alg. 1.3) on the selectively inverted fronts.
+//
+// A panel solve runs on an elimination-order vector of the panel's
+// auxiliary box (nrhs columns, column r at r * naux):
+//   gather   zero-extend the panel's planes over the artificial PML (Alg. 1.3,
+//            first step; Sec. 2.3: per supernode, zero in x3) and cast to the
+//            working precision;
+//   forward  per depth, deepest first: each front assembles v_S from the
+//            gathered values and its children's update vectors (pulled,
+//            fixed order), then y = G v_S with G = [L_F^{-1}; F_BL L_F^{-1}];
+//            x_S := D_F^{-1} y_S and the front's update vector is
+//            w_U := (children's contributions) - y_U, i.e. the forward
+//            multifrontal solve of Sec. 2.2 with L_F^{-1} applied as a product;
+//   backward per depth, root first: x_S := G^T [x_S; -x_U], which equals
+//            L_F^{-T}(x_S - F_BL^T x_U) (the transpose solve, applied as a product);
+//   extract  scatter the panel's planes back to the padded grid and, in the
+//            forward sweep, apply the coupling to the next panel (Alg. 1.5).
+#include "devtypes.hpp"
+#include "kernels.hpp"
+
+namespace hsw {
+
+// Sweep coupling J_{i+1,i} between the last plane of a panel (hi-1) and the
+// next plane (hi) at lateral node (a1, a2): J[p + e3, p] = -e1 e2 ie3(hi) / h^2.
+__device__ inline Cx<double> plane_coupling(const ProbDev& Q, const Cx<double>* et, int a1, int a2,
+                                            int hi) {
+    const Cx<double> e1 = et[Q.e_off[0] + a1];
+    const Cx<double> e2 = et[Q.e_off[1] + a2];
+    const Cx<double> ie3 = et[Q.e_off[2] + Q.N[2] + hi];
+    return scale((e1 * e2) * ie3, -1.0 / (Q.h * Q.h));
+}
+
+// mode 0: x_in = zero extension of the panel planes of u.
+// mode 1: x_in = J_{i+1,i}^T u_{i+1}: nonzero on the panel's last plane only.
+// u points at plane `plane0` of the padded grid (vector r at r * ld).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(int mode, ProbDev Q, PanelDev P,
+                                                const int* __restrict__ perm,
+                                                const Cx<double>* __restrict__ et,
+                                                const Cx<double>* __restrict__ u, int64_t ld,
+                                                int plane0, int nrhs, Cx<T>* __restrict__ xin,
+                                                int naux) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= naux) return;
+    const int NxNy = P.Nx * P.Ny;
+    const int b = perm[P.perm_off + e];
+    const int q = b / NxNy, lat = b - q * NxNy;
+    if (mode == 0) {
+        const bool live = q >= P.ga;
+        const int64_t g = (int64_t)(P.lo + q - P.ga - plane0) * NxNy + lat;
+        for (int r = 0; r < nrhs; ++r)
+            xin[(int64_t)r * naux + e] = live ? ccast<T>(u[r * ld + g]) : cx<T>(0, 0);
+    } else {
+        const bool live = q == P.nz - 1;
+        Cx<double> cf = cx<double>(0, 0);
+        int64_t g = 0;
+        if (live) {
+            const int a2 = lat / P.Nx, a1 = lat - a2 * P.Nx;
+            cf = plane_coupling(Q, et, a1, a2, P.hi);
+            g = (int64_t)(P.hi - plane0) * NxNy + lat;
+        }
+        for (int r = 0; r < nrhs; ++r)
+            xin[(int64_t)r * naux + e] = live ? ccast<T>(cf * u[r * ld + g]) : cx<T>(0, 0);
+    }
+}
+
+// mode 0: u_i := x (panel planes), and when couple != 0 also
+//         u_{i+1}(first plane) -= J_{i+1,i} u_i;  mode 1: u_i -= x.
+template <typename T>
+__global__ __launch_bounds__(256) void k_extract(int mode, int couple, ProbDev Q, PanelDev P,
+                                                 const int* __restrict__ iperm,
+                                                 const Cx<double>* __restrict__ et,
+                                                 const Cx<T>* __restrict__ xout, int naux,
+                                                 Cx<double>* __restrict__ u, int64_t ld, int plane0,
+                                                 int nrhs) {
+    const int NxNy = P.Nx * P.Ny;
+    const int npanel = (P.hi - P.lo) * NxNy;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= npanel) return;
+    const int pl = t / NxNy, lat = t - pl * NxNy;
+    const int b = (P.ga + pl) * NxNy + lat;
+    const int e = iperm[P.perm_off + b];
+    const int64_t g = (int64_t)(P.lo + pl - plane0) * NxNy + lat;
+    Cx<double> cf = cx<double>(0, 0);
+    const bool cpl = couple && mode == 0 && (P.lo + pl == P.hi - 1);
+    if (cpl) {
+        const int a2 = lat / P.Nx, a1 = lat - a2 * P.Nx;
+        cf = plane_coupling(Q, et, a1, a2, P.hi);
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        const Cx<double> v = ccast<double>(xout[(int64_t)r * naux + e]);
+        Cx<double>* up = u + r * ld + g;
+        if (mode == 0) {
+            *up = v;
+            if (cpl) up[NxNy] = up[NxNy] - cf * v;
+        } else {
+            *up = *up - v;
+        }
+    }
+}
+
+template <typename T, int RC>
+__global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int inst_base,
+                                             const FrontInst* __restrict__ inst,
+                                             const Cx<T>* __restrict__ G,
+                                             const Cx<T>* __restrict__ dinv,
+                                             const int* __restrict__ cmap,
+                                             const Cx<T>* __restrict__ xin, Cx<T>* __restrict__ xmid,
+                                             Cx<T>* __restrict__ wv, int naux, int Wld, int nrhs) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* sm = reinterpret_cast<Cx<T>*>(smem_raw);
+    const int fcl = work[2 * blockIdx.x], rb = work[2 * blockIdx.x + 1];
+    const FrontInst f = inst[inst_base + fcl];
+    const int n = f.s + f.u, s = f.s;
+    const int rhs0 = blockIdx.y * RC;
+    const int nr = min(RC, nrhs - rhs0);
+    Cx<T>* vS = sm;              // [RC][s]
+    Cx<T>* red = sm + RC * s;    // [4][64][RC]
+    const int tid = threadIdx.x;
+    const int c0i = f.child0, c1i = f.child1;
+    const int c0w = c0i >= 0 ? inst[c0i].wvoff : 0;
+    const int c1w = c1i >= 0 ? inst[c1i].wvoff : 0;
+    const int* map0 = cmap + f.moff;
+    const int* map1 = map0 + n;
+    for (int k = tid; k < s; k += 256) {
+        const int p0 = c0i >= 0 ? map0[k] : -1, p1 = c1i >= 0 ? map1[k] : -1;
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            Cx<T> v = cx<T>(0, 0);
+            if (r < nr) {
+                const int64_t rr = rhs0 + r;
+                v = xin[rr * naux + f.start + k];
+                if (p0 >= 0) v = v + wv[rr * Wld + c0w + p0];
+                if (p1 >= 0) v = v + wv[rr * Wld + c1w + p1];
+            }
+            vS[r * s + k] = v;
+        }
+    }
+    __syncthreads();
+    const int lr = tid & 63, ph = tid >> 6;
+    const int row = rb * 64 + lr;
+    Cx<T> acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
+    if (row < n) {
+        const int kmax = row < s ? row + 1 : s;
+        const Cx<T>* g = G + f.loff + row;
+        for (int k = ph; k < kmax; k += 4) {
+            const Cx<T> gv = g[(int64_t)k * n];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) cfma(acc[r], gv, vS[r * s + k]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) red[(ph * 64 + lr) * RC + r] = acc[r];
+    __syncthreads();
+    if (ph != 0 || row >= n) return;
+    const int p0 = (row >= s && c0i >= 0) ? map0[row] : -1;
+    const int p1 = (row >= s && c1i >= 0) ? map1[row] : -1;
+    for (int r = 0; r < nr; ++r) {
+        Cx<T> y = red[(0 * 64 + lr) * RC + r];
+        y = y + red[(1 * 64 + lr) * RC + r];
+        y = y + red[(2 * 64 + lr) * RC + r];
+        y = y + red[(3 * 64 + lr) * RC + r];
+        const int64_t rr = rhs0 + r;
+        if (row < s) {
+            xmid[rr * naux + f.start + row] = y * dinv[f.doff + row];
+        } else {
+            Cx<T> a = cx<T>(0, 0);
+            if (p0 >= 0) a = a + wv[rr * Wld + c0w + p0];
+            if (p1 >= 0) a = a + wv[rr * Wld + c1w + p1];
+            wv[rr * Wld + f.wvoff + (row - s)] = a - y;
+        }
+    }
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int RC>
+__global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int inst_base,
+                                             const FrontInst* __restrict__ inst,
+                                             const Cx<T>* __restrict__ G,
+                                             const int* __restrict__ ulist,
+                                             const Cx<T>* __restrict__ xmid, Cx<T>* __restrict__ xout,
+                                             int naux, int nrhs) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
+    const int fcl = work[2 * blockIdx.x], cbk = work[2 * blockIdx.x + 1];
+    const FrontInst f = inst[inst_base + fcl];
+    const int n = f.s + f.u, s = f.s;
+    const int rhs0 = blockIdx.y * RC;
+    const int nr = min(RC, nrhs - rhs0);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += 256) {
+        const int e = i < s ? f.start + i : ulist[f.uoff + i - s];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            Cx<T> v = cx<T>(0, 0);
+            if (r < nr) {
+                const int64_t rr = rhs0 + r;
+                v = i < s ? xmid[rr * naux + e] : -xout[rr * naux + e];
+            }
+            rv[r * n + i] = v;
+        }
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int cc = wave; cc < SOLVE_CB; cc += 4) {
+        const int j = cbk * SOLVE_CB + cc;
+        if (j >= s) break;
+        Cx<T> acc[RC];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
+        const Cx<T>* g = G + f.loff + (int64_t)j * n;
+        for (int i = j + lane; i < n; i += 64) {
+            const Cx<T> gv = g[i];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) cfma(acc[r], gv, rv[r * n + i]);
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            acc[r].re = wave_sum(acc[r].re);
+            acc[r].im = wave_sum(acc[r].im);
+        }
+        if (lane == 0)
+            for (int r = 0; r < nr; ++r) xout[(int64_t)(rhs0 + r) * naux + f.start + j] = acc[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_gather(int mode, const ProbDev& Q, const PanelDev& P, const int* perm,
+                   const Cx<double>* et, const Cx<double>* u, int64_t ld, int plane0, int nrhs,
+                   Cx<T>* xin, int naux, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather<T>, dim3((naux + 255) / 256), dim3(256), 0, st, mode, Q, P, perm, et,
+                       u, ld, plane0, nrhs, xin, naux);
+}
+template <typename T>
+void launch_extract(int mode, int couple, const ProbDev& Q, const PanelDev& P, const int* iperm,
+                    const Cx<double>* et, const Cx<T>* xout, int naux, Cx<double>* u, int64_t ld,
+                    int plane0, int nrhs, hipStream_t st) {
+    const int npanel = (P.hi - P.lo) * P.Nx * P.Ny;
+    hipLaunchKernelGGL(k_extract<T>, dim3((npanel + 255) / 256), dim3(256), 0, st, mode, couple, Q, P,
+                       iperm, et, xout, naux, u, ld, plane0, nrhs);
+}
+
+template <typename T, int RC>
+static void fwd_rc(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                   const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
+                   int naux, int Wld, int nrhs, int smax, hipStream_t st) {
+    size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + 4 * 64 * RC);
+    dim3 grid(nwork, (nrhs + RC - 1) / RC);
+    hipLaunchKernelGGL((k_fwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, dinv, cmap,
+                       xin, xmid, wv, naux, Wld, nrhs);
+}
+template <typename T, int RC>
+static void bwd_rc(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                   const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
+                   hipStream_t st) {
+    size_t shm = sizeof(Cx<T>) * (size_t)RC * nmax;
+    dim3 grid(nwork, (nrhs + RC - 1) / RC);
+    hipLaunchKernelGGL((k_bwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, ulist, xmid,
+                       xout, naux, nrhs);
+}
+
+// Right-hand sides per workgroup: as many as fit 64 KiB of LDS (front vector
+// plus the forward pass's reduction buffer), at most 8.
+template <typename T>
+int solve_rhs_chunk(int nrhs, int nmax) {
+    int rc = 8;
+    while (rc > 1 && (size_t)rc * (nmax + 256) * sizeof(Cx<T>) > 65536) rc >>= 1;
+    while (rc > 1 && rc / 2 >= nrhs) rc >>= 1;
+    return rc;
+}
+
+template <typename T>
+void launch_fwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
+                int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st) {
+    if (nwork <= 0) return;
+    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
+        case 8: fwd_rc<T, 8>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        case 4: fwd_rc<T, 4>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        case 2: fwd_rc<T, 2>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        default: fwd_rc<T, 1>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+    }
+}
+template <typename T>
+void launch_bwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
+                hipStream_t st) {
+    if (nwork <= 0) return;
+    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
+        case 8: bwd_rc<T, 8>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        case 4: bwd_rc<T, 4>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        case 2: bwd_rc<T, 2>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        default: bwd_rc<T, 1>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+    }
+}
+
+#define HSW_INST(T)                                                                               \
+    template void launch_gather<T>(int, const ProbDev&, const PanelDev&, const int*,             \
+                                   const Cx<double>*, const Cx<double>*, int64_t, int, int,      \
+                                   Cx<T>*, int, hipStream_t);                                    \
+    template void launch_extract<T>(int, int, const ProbDev&, const PanelDev&, const int*,       \
+                                    const Cx<double>*, const Cx<T>*, int, Cx<double>*, int64_t,  \
+                                    int, int, hipStream_t);                                      \
+    template void launch_fwd<T>(const int*, int, int, const FrontInst*, const Cx<T>*,            \
+                                const Cx<T>*, const int*, const Cx<T>*, Cx<T>*, Cx<T>*, int, int, \
+                                int, int, int, hipStream_t);                                     \
+    template void launch_bwd<T>(const int*, int, int, const FrontInst*, const Cx<T>*, const int*, \
+                                const Cx<T>*, Cx<T>*, int, int, int, hipStream_t);               \
+    template int solve_rhs_chunk<T>(int, int);
+HSW_INST(float)
+HSW_INST(double)
+#undef HSW_INST
+
+}  // namespace hsw

@@ -1,0 +1,28 @@
+"""Seeded parity cases shared by the GPU tests (inputs only, no method arithmetic)."""
+
+import numpy as np
+
+from paper_1204_0111_amd import workloads as wl
+
+
+def case(n=(14, 12, 13), gamma=3, d=3, leaf=4, model="grf", seed=5, C=4.0, alpha=None):
+    n = tuple(int(v) for v in n)
+    h = wl.grid_h(n)
+    if model == "grf":
+        c = wl.velocity_grf(n, h, seed)
+    elif model == "layered":
+        c = wl.velocity_layered(n, h, seed)
+    else:
+        c = wl.velocity_constant(n)
+    return dict(n=n, h=h, c=c, omega=wl.omega_for_ppw(c, h),
+                alpha=wl.ALPHA_DEFAULT if alpha is None else alpha, gamma=gamma, C=C, d=d,
+                leaf=leaf)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+TOL = {"c128": 1e-12, "c64": 1e-4}

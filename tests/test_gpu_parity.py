@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: relative 2-norm 1e-12 in complex128 and 1e-4 in complex64 for
+factors, inverted fronts, panel solves T_i and sweep applications; the solve
+itself must reach the FP64 true relative residual 1e-5, checked with the
+oracle's operator.  The plan (elimination order, update sets) must equal the
+oracle's independently written nested dissection exactly.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import gmres as gm
+from oracle import helmholtz as hz
+from oracle import ldlt as ld
+from oracle import nd
+from oracle import panels as pn
+from oracle import sweep as sw
+from paper_1204_0111_amd import workloads as wl
+from tests._cases import TOL, case, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _solver(P, prec):
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(P, precision=prec)
+    S.assemble(P["c"])
+    S.setup()
+    return S
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def small():
+    return case(n=(10, 10, 4), gamma=2, d=2, leaf=3)
+
+
+@pytest.fixture(scope="module")
+def medium():
+    return case(n=(14, 12, 13), gamma=3, d=3, leaf=4)
+
+
+@pytest.fixture(scope="module")
+def small_oracle_factors(small):
+    P = small
+    out = {}
+    N = hz.padded_shape(P["n"], P["gamma"])
+    nodes = nd.nested_dissection(N[0], N[1], P["leaf"])
+    for i in range(len(pn.panel_bounds(P["n"][2], P["gamma"], P["d"]))):
+        H, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
+                                        P["d"], i)
+        nz = ga + hi - lo
+        perm = nd.elimination_order(nodes, N[0], N[1], nz)
+        Hp = H[perm][:, perm]
+        U = nd.update_sets(nodes, nd.symbolic_structure(Hp))
+        L, d = ld.ldlt_unpivoted(Hp.toarray())
+        out[i] = (perm, U, ld.front_blocks(L, d, nodes, U), [x.start for x in nodes])
+    return out
+
+
+def test_plan_matches_oracle_nested_dissection(small, small_oracle_factors):
+    S = _solver(small, "c128")
+    for i, (perm, U, blocks, starts) in small_oracle_factors.items():
+        assert np.array_equal(S.perm(0, i), perm)
+        assert S.query(0, "fronts") == len(U)
+        for f, (u, st) in enumerate(zip(U, starts)):
+            fi = S.front_info(0, i, f)
+            assert fi["start"] == st and fi["u"] == len(u)
+            assert np.array_equal(fi["urows"], u)
+
+
+def test_matvec_matches_oracle(medium):
+    P = medium
+    S = _solver(P, "c128")
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    x = wl.random_complex((3, A.shape[0]), 1)
+    y = S.matvec(0, _cuda(x)).cpu().numpy()
+    for r in range(3):
+        assert rel(y[r], A @ x[r]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_front_factors_match_dense_ldlt(small, small_oracle_factors, prec):
+    S = _solver(small, prec)
+    for i, (perm, U, blocks, starts) in small_oracle_factors.items():
+        for f, (dF, LF, FBL) in enumerate(blocks):
+            D, L, F = S.front(0, i, f)
+            assert rel(D, dF) <= TOL[prec], (i, f)
+            assert rel(L, LF) <= TOL[prec], (i, f)
+            if len(U[f]):
+                assert rel(F, FBL) <= TOL[prec], (i, f)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_inverted_fronts_match_oracle(small, small_oracle_factors, prec):
+    S = _solver(small, prec)
+    for i, (perm, U, blocks, starts) in small_oracle_factors.items():
+        for f, (dF, LF, FBL) in enumerate(blocks):
+            GT, GB = ld.selective_inverse(LF, FBL)
+            G = S.front_inverse(0, i, f)
+            ref = np.vstack([GT, GB])
+            assert rel(G, ref) <= TOL[prec], (i, f)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_panel_solve_matches_oracle(medium, prec):
+    P = medium
+    S = _solver(P, prec)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    for i in range(O.m):
+        lo, hi = O.bounds[i]
+        v = wl.random_complex((2, (hi - lo) * O.plane), 10 + i)
+        y = S.panel_solve(0, i, _cuda(v)).cpu().numpy()
+        ref = O.T(i, v.T).T
+        assert rel(y, ref) <= TOL[prec], i
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_sweep_matches_oracle(medium, prec, nrhs):
+    P = medium
+    S = _solver(P, prec)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((nrhs, O.N_pad), 3)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    ref = O.apply(r.T).T
+    for k in range(nrhs):
+        assert rel(z[k], ref[k]) <= TOL[prec], k
+
+
+def test_sweep_is_deterministic(medium):
+    S = _solver(medium, "c64")
+    r = _cuda(wl.random_complex((2, S.N_pad()), 4))
+    z1 = S.apply(0, r).cpu().numpy()
+    z2 = S.apply(0, r).cpu().numpy()
+    assert np.array_equal(z1, z2)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_gmres_matches_oracle(medium, prec):
+    P = medium
+    S = _solver(P, prec)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], [[0.5, 0.5, 0.5], [0.3, 0.6, 0.2]])
+    b = b.reshape(2, -1)
+    xs, info = S.solve([_cuda(b)], rtol=1e-5, restart=20)
+    x = xs[0].cpu().numpy()
+    for r in range(2):
+        _, it_o, rr_o, _ = gm.gmres(lambda v: A @ v, O.apply, b[r], k=20, tol=1e-5)
+        true = np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r])
+        assert true < 1e-5 and abs(true - info["relres"][r]) <= 1e-3 * true + 1e-12
+        if prec == "c128":
+            assert abs(info["iters"][r] - it_o) <= 1, (info["iters"][r], it_o)
+        else:
+            assert info["iters"][r] <= 1.2 * it_o + 1, (info["iters"][r], it_o)
+
+
+def test_single_panel_undamped_converges_in_one_iteration():
+    P = case(n=(8, 7, 6), gamma=2, d=6, leaf=3, alpha=0.0)
+    S = _solver(P, "c128")
+    assert S.query(0, "m") == 1
+    b = wl.random_complex((1, S.N_pad()), 6)
+    xs, info = S.solve([_cuda(b)], rtol=1e-5)
+    assert info["iters"][0] == 1 and info["relres"][0] < 1e-10
+
+
+def test_ragged_non_cubic_grid_leaf_two(prec="c128"):
+    P = case(n=(9, 13, 7), gamma=2, d=2, leaf=2, model="layered")
+    S = _solver(P, prec)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((3, O.N_pad), 9)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    ref = O.apply(r.T).T
+    assert rel(z, ref) <= TOL[prec]
+
+
+def test_errors_are_reported():
+    from paper_1204_0111_amd.hsweep import HswError, Solver
+    P = case(n=(6, 6, 6), gamma=2, d=2, leaf=3)
+    S = Solver(P, precision="c64")
+    r = _cuda(np.zeros((1, S.N_pad()), dtype=np.complex128))
+    with pytest.raises(HswError) as e:
+        S.apply(0, r)
+    assert e.value.status == 3  # apply before setup
+    with pytest.raises(HswError) as e:
+        S.setup()
+    assert e.value.status == 3  # setup before assemble
+    bad = P["c"].copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(HswError) as e:
+        S.assemble(bad)
+    assert e.value.status == 1
+    S.assemble(P["c"])
+    S.setup()
+    with pytest.raises(HswError):
+        S.query(0, "no_such_key")
+    with pytest.raises(HswError):
+        Solver(dict(P, gamma=0), precision="c64")
