@@ -117,22 +117,21 @@ __global__ __launch_bounds__(256) void k_assemble(const int2* __restrict__ work,
 }
 
 // ---------------------------------------------------------------------------
-// One pivot block [k, k+b) of the blocked partial LDL^T: every workgroup
-// factors the b x b diagonal block in LDS (unpivoted, transposes only), then
-// solves its 64 rows of the panel: F_BL := F_BL L^{-T} D^{-1}.  Workgroup 0 of
-// a front writes the factored diagonal block and the reciprocal pivots.
+// Diagonal block [k, k+b) of the blocked partial LDL^T: one workgroup per
+// front factors the b x b block in LDS (unpivoted, transposes only) and
+// writes L_kk (unit lower, below the diagonal), the pivots D_kk (on the
+// diagonal) and their reciprocals.  A zero or non-finite pivot is reported.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ldlt_panel(const int2* __restrict__ work,
-                                                    const FrontInst* __restrict__ inst,
-                                                    Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ dinv,
-                                                    int k, int* __restrict__ err) {
+__global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work,
+                                                   const FrontInst* __restrict__ inst,
+                                                   Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ dinv,
+                                                   int k, int* __restrict__ err) {
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff;
-    __shared__ Cx<T> A[NB][NB + 1];   // A[col][row]
-    __shared__ Cx<T> Pn[NB][NB + 1];  // panel rows, Pn[col][row]
+    __shared__ Cx<T> A[NB][NB + 1];  // A[col][row]
     __shared__ Cx<T> dv[NB];
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -159,32 +158,48 @@ __global__ __launch_bounds__(256) void k_ldlt_panel(const int2* __restrict__ wor
         if (tid > m && tid < b) A[m][tid] = A[m][tid] * idm;
         __syncthreads();
     }
-    if (w.y == 0) {
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            int row = idx & (NB - 1), col = idx / NB;
-            if (row < b && col < b && row >= col) L[(int64_t)(k + col) * n + k + row] = A[col][row];
-        }
-        if (tid < b) dinv[f.doff + k + tid] = dv[tid];
-        if (tid == 0 && bad >= 0) {
-            if (atomicCAS(&err[0], -1, w.x) == -1) err[1] = k + bad;
-        }
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        int row = idx & (NB - 1), col = idx / NB;
+        if (row < b && col < b && row >= col) L[(int64_t)(k + col) * n + k + row] = A[col][row];
     }
-    const int rbeg = k + w.y * 64, rend = min(rbeg + 64, n);
-    const int pr0 = max(rbeg, k + b);
-    if (pr0 >= rend) return;
-    for (int idx = tid; idx < NB * 64; idx += 256) {
-        int lr = idx & 63, col = idx / 64;
-        int row = rbeg + lr;
-        if (col < b && row >= pr0 && row < rend) Pn[col][lr] = L[(int64_t)(k + col) * n + row];
+    if (tid < b) dinv[f.doff + k + tid] = dv[tid];
+    if (tid == 0 && bad >= 0) {
+        if (atomicCAS(&err[0], -1, w.x) == -1) err[1] = k + bad;
     }
+}
+
+// Panel rows below the diagonal block: F_BL := F_BL L_kk^{-T} D_kk^{-1} for 64
+// rows per workgroup, reading the already factored diagonal block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ work,
+                                                    const FrontInst* __restrict__ inst,
+                                                    Cx<T>* __restrict__ Lb,
+                                                    const Cx<T>* __restrict__ dinv, int k) {
+    const int2 w = work[blockIdx.x];
+    const FrontInst f = inst[w.x];
+    const int n = f.s + f.u;
+    const int b = min(NB, f.s - k);
+    Cx<T>* L = Lb + f.loff;
+    __shared__ Cx<T> Lk[NB][NB + 1];  // Lk[m][jj] = L_kk(jj, m), jj > m
+    __shared__ Cx<T> Pn[NB][NB + 1];  // panel rows, Pn[col][row]
+    __shared__ Cx<T> dv[NB];
+    const int tid = threadIdx.x;
+    const int rbeg = k + b + w.y * 64, rend = min(rbeg + 64, n);
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        int row = idx & (NB - 1), col = idx / NB;
+        if (row < b && col < b && row > col) Lk[col][row] = L[(int64_t)(k + col) * n + k + row];
+        int r = rbeg + row;
+        if (col < b && r < rend) Pn[col][row] = L[(int64_t)(k + col) * n + r];
+    }
+    if (tid < b) dv[tid] = dinv[f.doff + k + tid];
     __syncthreads();
     const int lr = tid & 63, jg = tid >> 6;
-    const bool active = (rbeg + lr >= pr0) && (rbeg + lr < rend);
+    const bool active = rbeg + lr < rend;
     for (int m = 0; m < b; ++m) {
         if (active) {
             const Cx<T> y = Pn[m][lr];
             for (int jj = jg; jj < b; jj += 4)
-                if (jj > m) cfms(Pn[jj][lr], y, A[m][jj]);
+                if (jj > m) cfms(Pn[jj][lr], y, Lk[m][jj]);
         }
         __syncthreads();
     }
@@ -341,10 +356,16 @@ void launch_assemble(const int2* work, int nwork, const FrontInst* inst, const P
                        ulist, cmap, et, Lb, Wcur, Wchild);
 }
 template <typename T>
-void launch_ldlt_panel(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
-                       int k, int* err, hipStream_t st) {
+void launch_ldlt_diag(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
+                      int k, int* err, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_ldlt_panel<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k, err);
+    hipLaunchKernelGGL(k_ldlt_diag<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k, err);
+}
+template <typename T>
+void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb,
+                       const Cx<T>* dinv, int k, hipStream_t st) {
+    if (nwork <= 0) return;
+    hipLaunchKernelGGL(k_panel_trsm<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k);
 }
 template <typename T>
 void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
@@ -364,8 +385,10 @@ void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx
                                      const ProbDev*, const int*, const int*, const int*,        \
                                      const Cx<double>*, Cx<T>*, Cx<T>*, const Cx<T>*,           \
                                      hipStream_t);                                              \
-    template void launch_ldlt_panel<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int,  \
-                                       int*, hipStream_t);                                      \
+    template void launch_ldlt_diag<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int,   \
+                                      int*, hipStream_t);                                       \
+    template void launch_panel_trsm<T>(const int2*, int, const FrontInst*, Cx<T>*, const Cx<T>*, \
+                                       int, hipStream_t);                                       \
     template void launch_trailing<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int,    \
                                      hipStream_t);                                              \
     template void launch_inverse<T>(const int2*, int, const FrontInst*, const Cx<T>*, Cx<T>*,    \

@@ -37,7 +37,7 @@ struct Launch {
 
 struct DepthSchedule {
     Launch assemble;
-    std::vector<Launch> ldlt, trail;  // one per pivot block
+    std::vector<Launch> ldlt, panel, trail;  // one per pivot block
 };
 
 struct SolveLevel {
@@ -275,14 +275,20 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
         ds.assemble.count = (int)(fwork.size() - ds.assemble.off);
         for (int k = 0; k < smax; k += NB) {
             Launch l{(int64_t)fwork.size(), 0, k};
+            for (int i : at[d])
+                if (ctx->inst_h[i].s > k) fwork.push_back(make_int2(i, 0));
+            l.count = (int)(fwork.size() - l.off);
+            ds.ldlt.push_back(l);
+            Launch pl{(int64_t)fwork.size(), 0, k};
             for (int i : at[d]) {
                 const FrontInst& f = ctx->inst_h[i];
                 if (f.s <= k) continue;
-                int nrb = (f.s + f.u - k + 63) / 64;
+                int b = std::min(NB, f.s - k);
+                int nrb = (f.s + f.u - k - b + 63) / 64;
                 for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
             }
-            l.count = (int)(fwork.size() - l.off);
-            ds.ldlt.push_back(l);
+            pl.count = (int)(fwork.size() - pl.off);
+            ds.panel.push_back(pl);
             Launch t{(int64_t)fwork.size(), 0, k};
             for (int i : at[d]) {
                 const FrontInst& f = ctx->inst_h[i];
@@ -525,8 +531,10 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                            ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap, ctx->d_et, L,
                            ws[d & 1], ws[(d + 1) & 1], st);
         for (size_t s = 0; s < ds.ldlt.size(); ++s) {
-            launch_ldlt_panel<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L, dinv,
-                                 ds.ldlt[s].k, ctx->d_err, st);
+            launch_ldlt_diag<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L, dinv,
+                                ds.ldlt[s].k, ctx->d_err, st);
+            launch_panel_trsm<T>(ctx->d_fwork + ds.panel[s].off, ds.panel[s].count, ctx->d_inst, L,
+                                 dinv, ds.panel[s].k, st);
             launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
                                ws[d & 1], ds.trail[s].k, st);
         }

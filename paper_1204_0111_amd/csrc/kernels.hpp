@@ -13,8 +13,11 @@ void launch_assemble(const int2* work, int nwork, const FrontInst* inst, const P
                      const Cx<double>* et, Cx<T>* Lb, Cx<T>* Wcur, const Cx<T>* Wchild,
                      hipStream_t st);
 template <typename T>
-void launch_ldlt_panel(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
-                       int k, int* err, hipStream_t st);
+void launch_ldlt_diag(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
+                      int k, int* err, hipStream_t st);
+template <typename T>
+void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb,
+                       const Cx<T>* dinv, int k, hipStream_t st);
 template <typename T>
 void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
                      int k, hipStream_t st);

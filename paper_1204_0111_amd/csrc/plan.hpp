@@ -22,7 +22,7 @@ namespace hsw {
 constexpr int TILE = 64;        // square tile of the front kernels
 constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
 constexpr int SOLVE_RB = 64;    // rows per workgroup in the forward solve
-constexpr int SOLVE_CB = 16;    // columns per workgroup in the backward solve
+constexpr int SOLVE_CB = 32;    // columns per workgroup in the backward solve
 
 struct LatNode {
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;

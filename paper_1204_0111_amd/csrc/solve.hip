@@ -99,6 +99,11 @@ __global__ __launch_bounds__(256) void k_extract(int mode, int couple, ProbDev Q
     }
 }
 
+// Forward pass over the fronts of one depth.  Workgroup = (front, 64 rows).
+// Each wave takes every fourth pivot column; eight independent loads per
+// thread are in flight before they are consumed.  Rows of G_TL = L_F^{-1}
+// above the diagonal are exact zeros, so a row block that lies in the
+// triangle stops at its own last row (uniform for the workgroup).
 template <typename T, int RC>
 __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int inst_base,
                                              const FrontInst* __restrict__ inst,
@@ -139,17 +144,26 @@ __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int i
     __syncthreads();
     const int lr = tid & 63, ph = tid >> 6;
     const int row = rb * 64 + lr;
+    const int kend = (rb * 64 + 64 <= s) ? rb * 64 + 64 : s;  // block-uniform
     Cx<T> acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
-    if (row < n) {
-        const int kmax = row < s ? row + 1 : s;
-        const Cx<T>* g = G + f.loff + row;
-        for (int k = ph; k < kmax; k += 4) {
-            const Cx<T> gv = g[(int64_t)k * n];
+    const int rowc = row < n ? row : n - 1;  // clamp: out-of-range lanes load a valid address
+    const Cx<T>* g = G + f.loff + rowc;
+    int k = ph;
+    for (; k + 28 < kend; k += 32) {
+        Cx<T> gv[8];
 #pragma unroll
-            for (int r = 0; r < RC; ++r) cfma(acc[r], gv, vS[r * s + k]);
-        }
+        for (int q = 0; q < 8; ++q) gv[q] = g[(int64_t)(k + 4 * q) * n];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) cfma(acc[r], gv[q], vS[r * s + k + 4 * q]);
+    }
+    for (; k < kend; k += 4) {
+        const Cx<T> gv = g[(int64_t)k * n];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) cfma(acc[r], gv, vS[r * s + k]);
     }
 #pragma unroll
     for (int r = 0; r < RC; ++r) red[(ph * 64 + lr) * RC + r] = acc[r];
@@ -181,6 +195,10 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Backward pass over the fronts of one depth.  Workgroup = (front, 32
+// columns); wave w owns columns c0 + w + 4q (q < 8) and its lanes stride
+// down the rows, eight column loads in flight per step, then reduce across
+// the wave.  Rows above the block's first column are zeros of G_TL.
 template <typename T, int RC>
 __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int inst_base,
                                              const FrontInst* __restrict__ inst,
@@ -188,6 +206,7 @@ __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int i
                                              const int* __restrict__ ulist,
                                              const Cx<T>* __restrict__ xmid, Cx<T>* __restrict__ xout,
                                              int naux, int nrhs) {
+    constexpr int QW = 8 / RC;  // columns per wave per pass
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
     const int fcl = work[2 * blockIdx.x], cbk = work[2 * blockIdx.x + 1];
@@ -196,7 +215,8 @@ __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int i
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, nrhs - rhs0);
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += 256) {
+    const int c0 = cbk * SOLVE_CB;
+    for (int i = c0 + tid; i < n; i += 256) {
         const int e = i < s ? f.start + i : ulist[f.uoff + i - s];
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
@@ -210,25 +230,44 @@ __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int i
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
-    for (int cc = wave; cc < SOLVE_CB; cc += 4) {
-        const int j = cbk * SOLVE_CB + cc;
-        if (j >= s) break;
-        Cx<T> acc[RC];
+    for (int pass = 0; pass < 8 / QW; ++pass) {
+        int cols[QW];
+        bool live[QW];
 #pragma unroll
-        for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
-        const Cx<T>* g = G + f.loff + (int64_t)j * n;
-        for (int i = j + lane; i < n; i += 64) {
-            const Cx<T> gv = g[i];
+        for (int q = 0; q < QW; ++q) {
+            const int j = c0 + wave + 4 * (pass * QW + q);
+            live[q] = j < s;
+            cols[q] = live[q] ? j : s - 1;
+        }
+        Cx<T> acc[QW][RC];
 #pragma unroll
-            for (int r = 0; r < RC; ++r) cfma(acc[r], gv, rv[r * n + i]);
+        for (int q = 0; q < QW; ++q)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[q][r] = cx<T>(0, 0);
+        const Cx<T>* gb = G + f.loff;
+        for (int i = c0 + lane; i < n; i += 64) {
+            Cx<T> gv[QW];
+#pragma unroll
+            for (int q = 0; q < QW; ++q) gv[q] = gb[(int64_t)cols[q] * n + i];
+#pragma unroll
+            for (int q = 0; q < QW; ++q)
+#pragma unroll
+                for (int r = 0; r < RC; ++r) cfma(acc[q][r], gv[q], rv[r * n + i]);
         }
 #pragma unroll
-        for (int r = 0; r < RC; ++r) {
-            acc[r].re = wave_sum(acc[r].re);
-            acc[r].im = wave_sum(acc[r].im);
+        for (int q = 0; q < QW; ++q)
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                acc[q][r].re = wave_sum(acc[q][r].re);
+                acc[q][r].im = wave_sum(acc[q][r].im);
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < QW; ++q)
+                if (live[q])
+                    for (int r = 0; r < nr; ++r)
+                        xout[(int64_t)(rhs0 + r) * naux + f.start + cols[q]] = acc[q][r];
         }
-        if (lane == 0)
-            for (int r = 0; r < nr; ++r) xout[(int64_t)(rhs0 + r) * naux + f.start + j] = acc[r];
     }
 }
 

@@ -1,0 +1,101 @@
+"""GPU checks at the full 50^3 benchmark size, in the launch configuration the benchmark times.
+
+The oracle cannot factor all 13 panels in test time, so these check sampled
+outputs and properties that hold at any size: one middle panel's T_i against
+the oracle's sparse LU of that panel, the mat-vec against the oracle's
+operator, bitwise reproducibility of the factors across two setups (no
+races between the workgroups of a front), and the FP64 true residual of the
+returned solution computed by the oracle's operator, with the iteration
+count against the oracle's stored count (written by
+tests/golden/make_oracle_iterations.py, which calls only the oracle).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import helmholtz as hz
+from oracle import panels as pn
+from paper_1204_0111_amd import workloads as wl
+from tests._cases import TOL, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    P = wl.make_problem(2)
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
+    return P, b
+
+
+def _solver(P, prec):
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(P, precision=prec)
+    S.assemble(P["c"])
+    S.setup()
+    return S
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_factors_bitwise_reproducible(cfg2, prec):
+    P, _ = cfg2
+    S = _solver(P, prec)
+    fronts = [(3, 0), (3, 1), (3, 2), (5, 100), (0, 0), (12, 0), (12, 255)]
+    a = [S.front_inverse(0, i, f) for i, f in fronts]
+    d = [S.front(0, i, f)[0] for i, f in fronts]
+    S.setup()
+    b = [S.front_inverse(0, i, f) for i, f in fronts]
+    e = [S.front(0, i, f)[0] for i, f in fronts]
+    for x, y in zip(a + d, b + e):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_middle_panel_solve_matches_oracle(cfg2, prec):
+    import scipy.sparse.linalg as spla
+    P, _ = cfg2
+    S = _solver(P, prec)
+    i = 5
+    H, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
+                                    P["d"], i)
+    plane = S.query(0, "N1") * S.query(0, "N2")
+    v = wl.random_complex((1, (hi - lo) * plane), 12)
+    y = S.panel_solve(0, i, torch.as_tensor(v).to("cuda")).cpu().numpy()[0]
+    ext = np.zeros(H.shape[0], dtype=np.complex128)
+    ext[ga * plane:] = v[0]
+    ref = spla.splu(H.tocsc()).solve(ext)[ga * plane:]
+    assert rel(y, ref) <= TOL[prec]
+
+
+def test_matvec_full_size(cfg2):
+    P, _ = cfg2
+    S = _solver(P, "c64")
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    x = wl.random_complex((1, A.shape[0]), 2)
+    y = S.matvec(0, torch.as_tensor(x).to("cuda")).cpu().numpy()[0]
+    assert rel(y, A @ x[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_solve_full_size_matches_oracle_iterations(cfg2, prec):
+    P, b = cfg2
+    path = os.path.join(GOLDEN, "oracle_iterations.json")
+    ref = json.load(open(path))["cfg2"]
+    assert abs(ref["C"] - P["C"]) < 1e-12, "stored count is for another PML amplitude"
+    S = _solver(P, prec)
+    xs, info = S.solve([torch.as_tensor(b).to("cuda")], rtol=1e-5, restart=20)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    x = xs[0].cpu().numpy()[0]
+    true = np.linalg.norm(b[0] - A @ x) / np.linalg.norm(b[0])
+    assert true < 1e-5
+    it = info["iters"][0]
+    if prec == "c128":
+        assert abs(it - ref["iters"]) <= 1, (it, ref["iters"])
+    else:
+        assert it <= 1.2 * ref["iters"] + 1, (it, ref["iters"])
