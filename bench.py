@@ -23,7 +23,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "unknowns/s to FP64 rel-res 1e-5: batched FP32-MFMA sweep vs plain FP64 sweep"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector_nonpacked": 78.6}
+KERNEL_CLASSES = ["fwd", "bwd", "diag", "panel", "trailing", "assemble", "inverse", "matvec"]
+# kernel class -> (symbol in rocprof output, bound, source file holding it)
+KERNEL_INFO = {"fwd": ("k_fwd", "hbm", "solve.hip"), "bwd": ("k_bwd", "hbm", "solve.hip"),
+               "diag": ("k_ldlt_diag", "hbm", "factor.hip"),
+               "panel": ("k_panel_trsm", "hbm", "factor.hip"),
+               "trailing": ("k_trailing", "mfma", "factor.hip"),
+               "assemble": ("k_assemble", "hbm", "factor.hip"),
+               "inverse": ("k_inverse", "mfma", "factor.hip"),
+               "matvec": ("k_matvec", "hbm", "krylov.hip")}
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def workload(cfg):
@@ -42,7 +53,42 @@ def describe(P):
                 pml_amp=P["C"], alpha=P["alpha"], omega=P["omega"], nrhs=P["nrhs"])
 
 
-def run_path(P, b, prec, steps, warmup):
+def source_hash(fname):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1204_0111_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def stored_traffic(kclass, workload_key):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None.
+
+    The summary records FETCH_SIZE and WRITE_SIZE per dispatch of the kernel,
+    the same counters read for a plain device copy of known size (the
+    calibration factor) and the hash of the kernel's source file; a changed
+    source makes the stored counters stale and the traffic is reported as None.
+    """
+    sym, _, src = KERNEL_INFO[kclass]
+    path = os.path.join(PROFILES, "%s_%s_pmc.txt" % (sym, workload_key))
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("result:"):
+            rec = json.loads(line[len("result:"):])
+    if not rec or rec.get("source_hash") != source_hash(src):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def roofline(S, step, kclass, prec):
+    """Time every launch of one kernel class over one full step with HIP events."""
+    S.kernel_timing(kclass, True)
+    step()
+    t = S.kernel_timing(kclass, False)
+    return t
+
+
+def run_path(P, b, prec, steps, warmup, measure=False):
     import torch
     from paper_1204_0111_amd.hsweep import Solver
     S = Solver(P, precision=prec)
@@ -71,8 +117,32 @@ def run_path(P, b, prec, steps, warmup):
                t_setup_ms=1e3 * info["t_setup"], t_solve_ms=1e3 * info["t_solve"],
                factor_bytes=S.query(0, "factor_bytes"), setup_flops=S.query(0, "setup_flops"),
                apply_flops=S.query(0, "apply_flops"), panels=S.query(0, "m"))
+    if measure:
+        # after the timed steps: one instrumented step per kernel class
+        out["kernels"] = {k: roofline(S, step, k, prec) for k in KERNEL_CLASSES}
     S.close()
     return out
+
+
+def roofline_entry(kernels, prec, workload_key):
+    """Roofline object of the dominant kernel class (largest summed launch time)."""
+    dom = max(kernels, key=lambda k: kernels[k]["seconds"])
+    t = kernels[dom]
+    sym, bound, _ = KERNEL_INFO[dom]
+    n = max(t["launches"], 1)
+    avg = t["seconds"] / n
+    traffic = stored_traffic(dom, workload_key)
+    if bound == "hbm":
+        achieved = t["bytes"] / n / avg / 1e9
+        peak, unit = HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = t["flops"] / n / avg / 1e12
+        peak = PEAK_TFLOPS["fp32_mfma" if prec != "c128" else "fp64_mfma"]
+        unit = "TFLOP/s"
+    return dict(kernel=sym, bound=bound, achieved=achieved, peak=peak, unit=unit,
+                frac=achieved / peak, traffic=traffic, launches=t["launches"],
+                avg_launch_us=1e6 * avg, algorithmic_bytes_per_launch=t["bytes"] / n,
+                algorithmic_flops_per_launch=t["flops"] / n)
 
 
 def cpu_baseline(P, iters):
@@ -126,6 +196,11 @@ def main():
     ap.add_argument("--cfg", type=int, default=2)
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pml-amp", type=float, default=None,
+                    help="override the PML amplitude C (exploration only)")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sweeping preconditioner is built and timed on a "
@@ -136,8 +211,20 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P, b = workload(args.cfg)
-    main_run = run_path(P, b, "c64", args.steps, args.warmup)
+    if args.pml_amp is not None:
+        P["C"] = args.pml_amp
+    if args.calibrate_copy_mb:
+        src = torch.empty(args.calibrate_copy_mb * (1 << 20) // 4, dtype=torch.float32,
+                          device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    main_run = run_path(P, b, "c64", args.steps, args.warmup, measure=not args.no_roofline)
+    kernels = main_run.pop("kernels", None)
     print("# c64: %s" % json.dumps(main_run), file=sys.stderr, flush=True)
+    if kernels:
+        print("# kernels: %s" % json.dumps(kernels), file=sys.stderr, flush=True)
     comp = None
     if not args.no_comparator:
         comp = run_path(P, b, "c128", args.steps, args.warmup)
@@ -154,6 +241,9 @@ def main():
                 t_setup_ms=main_run["t_setup_ms"], t_solve_ms=main_run["t_solve_ms"],
                 comparator=comp,
                 speedup_vs_fp64=(main_run["value"] / comp["value"]) if comp else None,
+                roofline=roofline_entry(kernels, "c64", "cfg%d" % args.cfg) if kernels else None,
+                kernel_times_ms={k: 1e3 * v["seconds"] for k, v in kernels.items()} if kernels
+                else None,
                 cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 

@@ -196,6 +196,20 @@ hsw_status hsw_get_front(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_
 hsw_status hsw_get_front_inverse(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
                                  hsw_c128* G);
 
+/*
+ * Measurement aid (not part of the method).  enable != 0 starts timing the
+ * named kernel class -- "fwd" / "bwd" (the two passes of the panel solves),
+ * "diag", "panel", "trailing", "assemble", "inverse" (setup) or "matvec" --
+ * and resets the totals: every later launch of that class on the context's
+ * stream is bracketed by a pair of HIP events, and the algorithmic bytes
+ * (factor blocks and vectors the launch must move, from the plan) and flops
+ * of the launch are added up.  enable == 0 stops timing, synchronizes the
+ * stream and returns the number of launches, the summed event-measured
+ * durations in seconds and the summed bytes and flops (any output may be NULL).
+ */
+hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, int64_t* launches,
+                             double* seconds, double* bytes, double* flops);
+
 /* Message of the last failing call on ctx (or of the last failed create when ctx is NULL). */
 const char* hsw_last_error(const hsw_ctx* ctx);
 

@@ -33,6 +33,8 @@ struct Launch {
     int64_t off;
     int count;
     int k;
+    double bytes_per_esz = 0;  // algorithmic bytes of the launch / bytes per complex entry
+    double cmac = 0;           // algorithmic complex multiply-adds
 };
 
 struct DepthSchedule {
@@ -44,6 +46,16 @@ struct SolveLevel {
     int64_t foff = 0, boff = 0;
     int fcount = 0, bcount = 0;
     int smax = 0, nmax = 0;
+    // algorithmic traffic in complex entries: factor part, and per right-hand side
+    double g_entries = 0, fwd_vec = 0, bwd_vec = 0, cmac = 0;
+};
+
+struct KernelTimer {
+    std::string kernel;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    int64_t launches = 0;
+    double bytes = 0, flops = 0;
 };
 
 struct ProbHost {
@@ -97,6 +109,7 @@ struct hsw_ctx {
     int nrhs_cap = 0;
     void *d_xin = nullptr, *d_xmid = nullptr, *d_xout = nullptr, *d_wv = nullptr;
 
+    KernelTimer timer;
     bool assembled = false, factored = false;
     double t_setup = 0;
     int bad_inst = -1, bad_pivot = -1;
@@ -115,6 +128,28 @@ struct hsw_ctx {
 static hsw_status fail(hsw_ctx* ctx, hsw_status s, const std::string& msg) {
     ctx->err = msg;
     return s;
+}
+
+// Run `launch`, bracketed by HIP events when the named class is being timed.
+template <class F>
+static void timed(hsw_ctx* ctx, const char* cls, double bytes, double flops, F&& launch) {
+    KernelTimer& t = ctx->timer;
+    if (t.on && t.kernel == cls) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            launch();
+            return;
+        }
+        (void)hipEventRecord(a, ctx->st);
+        launch();
+        (void)hipEventRecord(b, ctx->st);
+        t.ev.emplace_back(a, b);
+        t.launches += 1;
+        t.bytes += bytes;
+        t.flops += flops;
+    } else {
+        launch();
+    }
 }
 
 template <typename P>
@@ -273,11 +308,28 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
             for (int t = 0; t < nt * (nt + 1) / 2; ++t) fwork.push_back(make_int2(i, t));
         }
         ds.assemble.count = (int)(fwork.size() - ds.assemble.off);
+        for (int i : at[d]) {
+            const FrontInst& f = ctx->inst_h[i];
+            const double n = f.s + f.u;
+            ds.assemble.bytes_per_esz += n * (n + 1) / 2;  // the front is written once
+            for (int c : {f.child0, f.child1})
+                if (c >= 0) {
+                    const double uc = ctx->inst_h[c].u;
+                    ds.assemble.bytes_per_esz += uc * (uc + 1) / 2;  // child update pulled
+                }
+        }
         for (int k = 0; k < smax; k += NB) {
             Launch l{(int64_t)fwork.size(), 0, k};
             for (int i : at[d])
                 if (ctx->inst_h[i].s > k) fwork.push_back(make_int2(i, 0));
             l.count = (int)(fwork.size() - l.off);
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                const double b = std::min(NB, f.s - k);
+                l.bytes_per_esz += b * (b + 1) + b;  // block read + written, reciprocal pivots
+                l.cmac += b * b * b / 6;
+            }
             ds.ldlt.push_back(l);
             Launch pl{(int64_t)fwork.size(), 0, k};
             for (int i : at[d]) {
@@ -288,6 +340,14 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
                 for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
             }
             pl.count = (int)(fwork.size() - pl.off);
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                const double b = std::min(NB, f.s - k);
+                const double rows = f.s + f.u - k - b;
+                pl.bytes_per_esz += 2 * rows * b + b * b / 2 + b;
+                pl.cmac += rows * b * b / 2;
+            }
             ds.panel.push_back(pl);
             Launch t{(int64_t)fwork.size(), 0, k};
             for (int i : at[d]) {
@@ -300,6 +360,15 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
                 for (int q = 0; q < nt * (nt + 1) / 2; ++q) fwork.push_back(make_int2(i, q));
             }
             t.count = (int)(fwork.size() - t.off);
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                const double b = std::min(NB, f.s - k);
+                const double tr = f.s + f.u - k - b;
+                if (tr <= 0) continue;
+                t.bytes_per_esz += tr * (tr + 1) + tr * b;  // lower triangle read+written, panel read
+                t.cmac += tr * (tr + 1) / 2 * b;
+            }
             ds.trail.push_back(t);
         }
     }
@@ -310,6 +379,11 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
         for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2((int)i, rb));
     }
     ctx->inv_launch.count = (int)(fwork.size() - ctx->inv_launch.off);
+    for (const FrontInst& f : ctx->inst_h) {
+        const double sd = f.s, ud = f.u;
+        ctx->inv_launch.bytes_per_esz += (sd + ud) * sd + sd * (sd + 1) / 2 + ud * sd;
+        ctx->inv_launch.cmac += sd * sd * sd / 6 + ud * sd * sd / 2;
+    }
     // solve work lists per class and depth
     ctx->slevels.assign(ctx->classes.size(), {});
     for (size_t ci = 0; ci < ctx->classes.size(); ++ci) {
@@ -326,6 +400,14 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
             for (int f : c.at_depth[d]) {
                 sl.smax = std::max(sl.smax, c.s[f]);
                 sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
+                const double sd = c.s[f], ud = c.u[f];
+                double uc = 0;
+                for (int ch : {c.child0[f], c.child1[f]})
+                    if (ch >= 0) uc += c.u[ch];
+                sl.g_entries += sd * (sd + 1) / 2 + ud * sd;     // lower G_TL and G_BL
+                sl.fwd_vec += 3 * sd + ud + uc;                  // x_in, 1/D, x_mid, w_U, children's w
+                sl.bwd_vec += 2 * sd + ud;                       // x_mid, x_U gathered, x_S written
+                sl.cmac += sd * (sd + 1) / 2 + ud * sd;          // per right-hand side
             }
         }
     }
@@ -527,19 +609,31 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
     HIPCHK(hipEventRecord(e0, st));
     for (int d = ctx->maxdepth; d >= 0; --d) {
         const DepthSchedule& ds = ctx->fsched[d];
-        launch_assemble<T>(ctx->d_fwork + ds.assemble.off, ds.assemble.count, ctx->d_inst, ctx->d_pan,
-                           ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap, ctx->d_et, L,
-                           ws[d & 1], ws[(d + 1) & 1], st);
+        const double es = sizeof(Cx<T>);
+        timed(ctx, "assemble", es * ds.assemble.bytes_per_esz, 0.0, [&] {
+            launch_assemble<T>(ctx->d_fwork + ds.assemble.off, ds.assemble.count, ctx->d_inst,
+                               ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap,
+                               ctx->d_et, L, ws[d & 1], ws[(d + 1) & 1], st);
+        });
         for (size_t s = 0; s < ds.ldlt.size(); ++s) {
-            launch_ldlt_diag<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L, dinv,
-                                ds.ldlt[s].k, ctx->d_err, st);
-            launch_panel_trsm<T>(ctx->d_fwork + ds.panel[s].off, ds.panel[s].count, ctx->d_inst, L,
-                                 dinv, ds.panel[s].k, st);
-            launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
-                               ws[d & 1], ds.trail[s].k, st);
+            timed(ctx, "diag", es * ds.ldlt[s].bytes_per_esz, 8 * ds.ldlt[s].cmac, [&] {
+                launch_ldlt_diag<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L,
+                                    dinv, ds.ldlt[s].k, ctx->d_err, st);
+            });
+            timed(ctx, "panel", es * ds.panel[s].bytes_per_esz, 8 * ds.panel[s].cmac, [&] {
+                launch_panel_trsm<T>(ctx->d_fwork + ds.panel[s].off, ds.panel[s].count, ctx->d_inst,
+                                     L, dinv, ds.panel[s].k, st);
+            });
+            timed(ctx, "trailing", es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
+                launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
+                                   ws[d & 1], ds.trail[s].k, st);
+            });
         }
     }
-    launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L, G, st);
+    timed(ctx, "inverse", sizeof(Cx<T>) * ctx->inv_launch.bytes_per_esz, 8 * ctx->inv_launch.cmac, [&] {
+        launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L,
+                          G, st);
+    });
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, st));
     int err[2];
@@ -608,12 +702,17 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
     const Cx<T>* dinv = (const Cx<T>*)ctx->d_dinv;
     launch_gather<T>(gmode, Q, P, ctx->d_perm, ctx->d_et, src, ld, plane0, nrhs, xin, naux, st);
     const auto& lv = ctx->slevels[P.cls];
+    const double es = sizeof(Cx<T>);
     for (int d = c.maxdepth; d >= 0; --d)
-        launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, P.inst_base, ctx->d_inst, G, dinv,
-                      ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
+        timed(ctx, "fwd", es * (lv[d].g_entries + nrhs * lv[d].fwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
+            launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, P.inst_base, ctx->d_inst, G, dinv,
+                          ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
+        });
     for (int d = 0; d <= c.maxdepth; ++d)
-        launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, P.inst_base, ctx->d_inst, G,
-                      ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
+        timed(ctx, "bwd", es * (lv[d].g_entries + nrhs * lv[d].bwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
+            launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, P.inst_base, ctx->d_inst, G,
+                          ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
+        });
     launch_extract<T>(emode, couple, Q, P, ctx->d_iperm, ctx->d_et, xout, naux, dst, ld, plane0, nrhs, st);
 }
 
@@ -689,8 +788,11 @@ extern "C" hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, 
     hsw_status s = check_vec_args(ctx, prob, x, y, nrhs, ld, ctx->ph[prob].Npad);
     if (s != HSW_OK) return s;
     if ((const void*)x == (const void*)y) return fail(ctx, HSW_E_INVAL, "x and y alias");
-    launch_matvec(ctx->prob_h[prob], ctx->d_et, (const Cx<double>*)x, (Cx<double>*)y, nullptr, ld, nrhs,
-                  0, ctx->st);
+    const double np_ = (double)ctx->ph[prob].Npad;
+    timed(ctx, "matvec", np_ * (32.0 * nrhs + 8.0), 56.0 * np_ * nrhs, [&] {
+        launch_matvec(ctx->prob_h[prob], ctx->d_et, (const Cx<double>*)x, (Cx<double>*)y, nullptr, ld,
+                      nrhs, 0, ctx->st);
+    });
     HIPCHK(hipGetLastError());
     return HSW_OK;
 }
@@ -781,7 +883,8 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             Cx<double>* Zj = Z + (int64_t)j * vs;
             s = sweep_impl<T>(ctx, prob, Vj, Zj, nrhs, ld);
             if (s != HSW_OK) { cleanup(); return s; }
-            launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st);
+            timed(ctx, "matvec", (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
+                  [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st); });
             for (int pass = 0; pass < 2; ++pass) {
                 launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
                             pass, st);
@@ -1003,5 +1106,47 @@ extern "C" hsw_status hsw_get_front_inverse(const hsw_ctx* cctx, int32_t prob, i
     hsw_status st = front_block(ctx, prob, panel, front, ctx->d_G, blk, s, u);
     if (st != HSW_OK) return st;
     for (size_t i = 0; i < blk.size(); ++i) G[i] = {blk[i].re, blk[i].im};
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable,
+                                        int64_t* launches, double* seconds, double* bytes,
+                                        double* flops) {
+    if (!ctx || !kernel) return HSW_E_INVAL;
+    static const char* known[] = {"fwd", "bwd", "diag", "panel", "trailing", "assemble", "inverse",
+                                  "matvec"};
+    bool ok = false;
+    for (const char* k : known) ok = ok || std::strcmp(k, kernel) == 0;
+    if (!ok) return fail(ctx, HSW_E_INVAL, std::string("unknown kernel class ") + kernel);
+    KernelTimer& t = ctx->timer;
+    auto drop = [&]() {
+        for (auto& e : t.ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        t.ev.clear();
+    };
+    if (enable) {
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        drop();
+        t.kernel = kernel;
+        t.on = true;
+        t.launches = 0;
+        t.bytes = t.flops = 0;
+        return HSW_OK;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    double sec = 0;
+    for (auto& e : t.ev) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+        sec += ms * 1e-3;
+    }
+    if (launches) *launches = t.launches;
+    if (seconds) *seconds = sec;
+    if (bytes) *bytes = t.bytes;
+    if (flops) *flops = t.flops;
+    drop();
+    t.on = false;
     return HSW_OK;
 }

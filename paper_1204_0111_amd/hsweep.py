@@ -74,6 +74,8 @@ def load_library():
         "hsw_get_front": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                     c_void_p, P(c_int32), P(c_int32)]),
         "hsw_get_front_inverse": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
+        "hsw_kernel_timing": (c_int32, [c_void_p, ctypes.c_char_p, c_int32, P(c_int64),
+                                        P(c_double), P(c_double), P(c_double)]),
         "hsw_last_error": (ctypes.c_char_p, [c_void_p]),
         "hsw_destroy": (None, [c_void_p]),
     }
@@ -257,6 +259,15 @@ class Solver:
                                            c_void_p(L.ctypes.data), c_void_p(F.ctypes.data),
                                            None, None))
         return D, L, F[:u]
+
+    def kernel_timing(self, kernel, enable):
+        """Start (enable=True) or stop timing a kernel class; stopping returns the totals."""
+        n = c_int64()
+        sec, byt, fl = c_double(), c_double(), c_double()
+        self._check(self.lib.hsw_kernel_timing(self.ctx, kernel.encode(), int(bool(enable)),
+                                               ctypes.byref(n), ctypes.byref(sec),
+                                               ctypes.byref(byt), ctypes.byref(fl)))
+        return dict(launches=n.value, seconds=sec.value, bytes=byt.value, flops=fl.value)
 
     def front_inverse(self, prob, panel, front):
         fi = self.front_info(prob, panel, front)

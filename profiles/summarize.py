@@ -1,0 +1,87 @@
+"""Summarise rocprofv3 CSV output into the short text files kept in this folder.
+
+    python profiles/summarize.py stats <kernel_stats.csv> <out.txt> "<command>"
+    python profiles/summarize.py pmc <fetch_counter_collection.csv> <write_counter_collection.csv> \
+        <kernel symbol> <workload> <out.txt> "<fetch command>" "<write command>"
+
+The PMC summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
+factor the same counter reads for the plain 512 MiB device copy the benchmark
+runs with --calibrate-copy-mb 512, and records the hash of the kernel's
+source so that a changed kernel makes the numbers stale.
+"""
+
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = {"k_fwd": "solve.hip", "k_bwd": "solve.hip", "k_trailing": "factor.hip",
+       "k_inverse": "factor.hip", "k_panel_trsm": "factor.hip", "k_ldlt_diag": "factor.hip",
+       "k_assemble": "factor.hip", "k_matvec": "krylov.hip"}
+COPY_BYTES = 512 * (1 << 20)
+
+
+def src_hash(sym):
+    p = os.path.join(ROOT, "paper_1204_0111_amd", "csrc", SRC[sym])
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def stats(csv_path, out, cmd):
+    rows = list(csv.DictReader(open(csv_path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    with open(out, "w") as f:
+        f.write("# rocprofv3 --kernel-trace --stats summary\n# command: %s\n" % cmd)
+        f.write("# total kernel time %.3f ms over %d kernel names\n" % (tot / 1e6, len(rows)))
+        f.write("%-34s %7s %11s %10s %6s\n" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+        for r in rows[:20]:
+            name = r["Name"].split("(")[0].replace("void ", "")[:34]
+            f.write("%-34s %7s %11.3f %10.3f %6.2f\n" % (name, r["Calls"],
+                    float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+                    float(r["Percentage"])))
+
+
+def per_kernel(path):
+    rows = list(csv.DictReader(open(path)))
+    by = {}
+    calib = None
+    for r in rows:
+        v = float(r["Counter_Value"])
+        if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer") and int(r["Grid_Size"]) >= 65536 \
+                and calib is None:
+            calib = v
+        by.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(v)
+    return by, calib
+
+
+def pmc(fetch_csv, write_csv, sym, workload, out, cmd_f, cmd_w):
+    fb, fcal = per_kernel(fetch_csv)
+    wb, wcal = per_kernel(write_csv)
+    ff = COPY_BYTES / (fcal * 1024.0)
+    wf = COPY_BYTES / (wcal * 1024.0)
+    key = [k for k in fb if k.split("<")[0].endswith(sym)][0]
+    fk = sum(fb[key]) / len(fb[key])
+    wk = sum(wb[key]) / len(wb[key])
+    res = dict(kernel=sym, workload=workload, dispatches=len(fb[key]),
+               fetch_kib_per_dispatch=fk, write_kib_per_dispatch=wk,
+               fetch_scale=ff, write_scale=wf,
+               hbm_bytes_per_launch=fk * 1024 * ff + wk * 1024 * wf, source_hash=src_hash(sym))
+    with open(out, "w") as f:
+        f.write("# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, per dispatch of %s (%s)\n" % (sym, workload))
+        f.write("# fetch command: %s\n# write command: %s\n" % (cmd_f, cmd_w))
+        f.write("# calibration: 512 MiB device copy read FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB\n"
+                % (fcal, wcal))
+        f.write("# scale factors: fetch %.4f, write %.4f (bytes per counted KiB / 1024)\n" % (ff, wf))
+        for k in sorted(fb, key=lambda k: -sum(fb[k]))[:8]:
+            f.write("%-40s fetch %12.1f KiB/dispatch  write %12.1f KiB/dispatch  n=%d\n"
+                    % (k[:40], sum(fb[k]) / len(fb[k]), sum(wb.get(k, [0])) / max(len(wb.get(k, [1])), 1),
+                       len(fb[k])))
+        f.write("result:%s\n" % json.dumps(res))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:5])
+    else:
+        pmc(*sys.argv[2:9])

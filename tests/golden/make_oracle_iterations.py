@@ -1,0 +1,45 @@
+"""Write tests/golden/oracle_iterations.json: the CPU oracle's GMRES(20) iteration counts.
+
+Calls only the oracle (and the seeded input generators).  Usage:
+
+    python tests/golden/make_oracle_iterations.py cfg2 [cfg1 ...]
+
+Each entry records the configuration's PML amplitude, the iteration count to
+FP64 relative residual 1e-5 and the final true relative residual.  Takes a
+few minutes per 50^3 configuration (13 sparse LU factorisations).
+"""
+
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import gmres as gm  # noqa: E402
+from oracle import helmholtz as hz  # noqa: E402
+from oracle import sweep as sw  # noqa: E402
+from paper_1204_0111_amd import workloads as wl  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_iterations.json")
+
+
+def run(name):
+    P = wl.make_problem(int(name[3:]))
+    S = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(P["nrhs"], -1)
+    its, rrs = [], []
+    for r in range(P["nrhs"]):
+        _, it, rr, _ = gm.gmres(lambda v: A @ v, S.apply, b[r], k=20, tol=1e-5, maxit=400)
+        its.append(it)
+        rrs.append(rr)
+    return dict(C=P["C"], iters=max(its), iters_per_rhs=its, relres=rrs)
+
+
+if __name__ == "__main__":
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in sys.argv[1:]:
+        data[name] = run(name)
+        print(name, data[name], flush=True)
+        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
