@@ -117,10 +117,73 @@ __global__ __launch_bounds__(256) void k_assemble(const int2* __restrict__ work,
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core helpers.  A complex 64 x 64 tile product is four real products
+// per 16 x 16 x 4 step (no complex MFMA exists), FP32 MFMA for complex64 and
+// FP64 MFMA for complex128, accumulating in the same precision.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> { typedef mf4 type; };
+template <> struct MfmaAcc<double> { typedef md4 type; };
+__device__ inline mf4 mfma4(float a, float b, mf4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline md4 mfma4(double a, double b, md4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int LDP = 64 + 4;  // padded row length of the planar LDS tiles
+
+// Output row of a 16 x 16 x 4 MFMA held by lane group lk = lane / 16 in register
+// r: FP32 places four consecutive rows per lane group, FP64 interleaves them
+// (row lk + 4 r); both hold column lane % 16.
+template <typename T> __device__ inline int mfma_out_row(int lk, int r);
+template <> __device__ inline int mfma_out_row<float>(int lk, int r) { return 4 * lk + r; }
+template <> __device__ inline int mfma_out_row<double>(int lk, int r) { return lk + 4 * r; }
+
+// acc += R C^T over KC columns for the 64 x 64 tile rows x cols: R (rows) and
+// C (cols) are planar LDS tiles [k][row]; wave w owns the 32 x 32 quadrant
+// (rows (w&1)*32, cols (w>>1)*32) as 2 x 2 blocks of 16 x 16.  In block
+// (bi, bj), lane l and register r hold tile row (w&1)*32 + 16 bi + (l&15)
+// and tile column (w>>1)*32 + 16 bj + mfma_out_row<T>(l>>4, r).
+template <typename T, int KC>
+__device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
+                                  typename MfmaAcc<T>::type (&aim)[2][2], const T (*Rre)[LDP],
+                                  const T (*Rim)[LDP], const T (*Cre)[LDP], const T (*Cim)[LDP],
+                                  int kmax) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const int li = l & 15, lk = l >> 4;
+#pragma unroll 2
+    for (int kk = 0; kk < KC; kk += 4) {
+        if (kk >= kmax) break;
+        T cr[2], ci[2], rr[2], ri[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            cr[q] = Cre[kk + lk][wc + 16 * q + li];
+            ci[q] = Cim[kk + lk][wc + 16 * q + li];
+            rr[q] = Rre[kk + lk][wr + 16 * q + li];
+            ri[q] = Rim[kk + lk][wr + 16 * q + li];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                are[bi][bj] = mfma4(cr[bj], rr[bi], are[bi][bj]);
+                are[bi][bj] = mfma4(-ci[bj], ri[bi], are[bi][bj]);
+                aim[bi][bj] = mfma4(cr[bj], ri[bi], aim[bi][bj]);
+                aim[bi][bj] = mfma4(ci[bj], rr[bi], aim[bi][bj]);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Diagonal block [k, k+b) of the blocked partial LDL^T: one workgroup per
-// front factors the b x b block in LDS (unpivoted, transposes only) and
-// writes L_kk (unit lower, below the diagonal), the pivots D_kk (on the
-// diagonal) and their reciprocals.  A zero or non-finite pivot is reported.
+// front factors the b x b block in LDS (unpivoted, transposes only), then
+// inverts the unit lower factor.  It writes L_kk below the diagonal, the
+// pivots D_kk on it and L_kk^{-1} transposed in the (otherwise unused) strict
+// upper triangle of the block, plus the reciprocal pivots.  A zero or
+// non-finite pivot is reported.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work,
                                                    const FrontInst* __restrict__ inst,
@@ -132,6 +195,7 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff;
     __shared__ Cx<T> A[NB][NB + 1];  // A[col][row]
+    __shared__ Cx<T> X[NB][NB + 1];  // inverse of the unit lower factor, X[col][row]
     __shared__ Cx<T> dv[NB];
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -139,6 +203,7 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
     for (int idx = tid; idx < NB * NB; idx += 256) {
         int row = idx & (NB - 1), col = idx / NB;
         if (row < b && col < b && row >= col) A[col][row] = L[(int64_t)(k + col) * n + k + row];
+        X[col][row] = cx<T>(row == col ? (T)1 : (T)0, 0);
     }
     __syncthreads();
     for (int m = 0; m < b; ++m) {
@@ -158,9 +223,21 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
         if (tid > m && tid < b) A[m][tid] = A[m][tid] * idm;
         __syncthreads();
     }
+    // X = L_kk^{-1} by row operations: after step m, row m of X is final and
+    // rows i > m lose L(i, m) times it (columns c <= m only are nonzero).
+    for (int m = 0; m < b - 1; ++m) {
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx & (NB - 1), c = idx / NB;
+            if (i > m && i < b && c <= m) cfms(X[c][i], A[m][i], X[c][m]);
+        }
+        __syncthreads();
+    }
     for (int idx = tid; idx < NB * NB; idx += 256) {
         int row = idx & (NB - 1), col = idx / NB;
-        if (row < b && col < b && row >= col) L[(int64_t)(k + col) * n + k + row] = A[col][row];
+        if (row < b && col < b) {
+            if (row >= col) L[(int64_t)(k + col) * n + k + row] = A[col][row];
+            else L[(int64_t)(k + col) * n + k + row] = X[row][col];  // (X^T)(row, col), row < col
+        }
     }
     if (tid < b) dinv[f.doff + k + tid] = dv[tid];
     if (tid == 0 && bad >= 0) {
@@ -169,7 +246,8 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
 }
 
 // Panel rows below the diagonal block: F_BL := F_BL L_kk^{-T} D_kk^{-1} for 64
-// rows per workgroup, reading the already factored diagonal block.
+// rows per workgroup, as a product with the stored L_kk^{-1}:
+// X(r, j) = dinv_j sum_{m <= j} P(r, m) L_kk^{-1}(j, m).
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ work,
                                                     const FrontInst* __restrict__ inst,
@@ -180,45 +258,55 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff;
-    __shared__ Cx<T> Lk[NB][NB + 1];  // Lk[m][jj] = L_kk(jj, m), jj > m
-    __shared__ Cx<T> Pn[NB][NB + 1];  // panel rows, Pn[col][row]
+    __shared__ Cx<T> Li[NB][NB + 1];  // Li[j][m] = L_kk^{-1}(j, m), zero for m > j
+    __shared__ Cx<T> Pn[NB][NB + 1];  // panel rows, Pn[m][row]
     __shared__ Cx<T> dv[NB];
     const int tid = threadIdx.x;
     const int rbeg = k + b + w.y * 64, rend = min(rbeg + 64, n);
     for (int idx = tid; idx < NB * NB; idx += 256) {
-        int row = idx & (NB - 1), col = idx / NB;
-        if (row < b && col < b && row > col) Lk[col][row] = L[(int64_t)(k + col) * n + k + row];
-        int r = rbeg + row;
-        if (col < b && r < rend) Pn[col][row] = L[(int64_t)(k + col) * n + r];
+        const int row = idx & (NB - 1), col = idx / NB;
+        // stored transposed above the diagonal: L(k+m, k+j) for m < j holds L_kk^{-1}(j, m)
+        Cx<T> v = cx<T>(0, 0);
+        if (row < b && col < b) {
+            if (row < col) v = L[(int64_t)(k + col) * n + k + row];
+            else if (row == col) v = cx<T>(1, 0);
+        }
+        Li[col][row] = v;  // Li[j = col][m = row]
+        const int r = rbeg + row;
+        Pn[col][row] = (col < b && r < rend) ? L[(int64_t)(k + col) * n + r] : cx<T>(0, 0);
     }
     if (tid < b) dv[tid] = dinv[f.doff + k + tid];
     __syncthreads();
     const int lr = tid & 63, jg = tid >> 6;
-    const bool active = rbeg + lr < rend;
+    if (rbeg + lr >= rend) return;
+    Cx<T> acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = cx<T>(0, 0);
     for (int m = 0; m < b; ++m) {
-        if (active) {
-            const Cx<T> y = Pn[m][lr];
-            for (int jj = jg; jj < b; jj += 4)
-                if (jj > m) cfms(Pn[jj][lr], y, Lk[m][jj]);
-        }
-        __syncthreads();
+        const Cx<T> p = Pn[m][lr];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cfma(acc[q], p, Li[jg * 16 + q][m]);
     }
-    if (active)
-        for (int col = jg; col < b; col += 4)
-            L[(int64_t)(k + col) * n + rbeg + lr] = Pn[col][lr] * dv[col];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = jg * 16 + q;
+        if (j < b) L[(int64_t)(k + j) * n + rbeg + lr] = acc[q] * dv[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Trailing update of pivot block [k, k+b): F[i,j] -= sum_m X[i,m] d_m X[j,m]
 // over the lower triangle of rows/columns [k+b, s+u) -- the F_BR := F_BR -
 // Z F_BL^T Schur update of Sec. 2.2 applied blockwise, plus the update of
-// the remaining pivot columns.  One workgroup per 64 x 64 output tile.
+// the remaining pivot columns.  One workgroup per 64 x 64 output tile, on
+// the matrix cores.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
                                                   const FrontInst* __restrict__ inst,
                                                   Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
                                                   int k) {
     constexpr int KC = 16;
+    typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
@@ -229,118 +317,175 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
     const int r0 = t0 + ti * TILE, c0 = t0 + tj * TILE;
     Cx<T>* L = Lb + f.loff;
     Cx<T>* W = Wcur + f.woff;
-    __shared__ Cx<T> Xr[KC][TILE], Xc[KC][TILE];
+    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
     __shared__ Cx<T> dd[NB];
     const int tid = threadIdx.x;
     if (tid < b) dd[tid] = L[(int64_t)(k + tid) * n + k + tid];
-    const int lr = tid & 63, cb = (tid >> 6) * 16;
-    Cx<T> acc[16];
+    V4 are[2][2], aim[2][2];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = cx<T>(0, 0);
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            are[bi][bj] = V4{0, 0, 0, 0};
+            aim[bi][bj] = V4{0, 0, 0, 0};
+        }
     __syncthreads();
     for (int kc = 0; kc < b; kc += KC) {
         for (int idx = tid; idx < KC * TILE; idx += 256) {
-            int l = idx & 63, m = idx / 64;
-            int km = kc + m;
+            const int l = idx & 63, m = idx / 64;
+            const int km = kc + m;
             Cx<T> xr = cx<T>(0, 0), xc = cx<T>(0, 0);
             if (km < b) {
                 const Cx<T>* col = L + (int64_t)(k + km) * n;
                 if (r0 + l < n) xr = col[r0 + l];
                 if (c0 + l < n) xc = col[c0 + l] * dd[km];
             }
-            Xr[m][l] = xr;
-            Xc[m][l] = xc;
+            Rre[m][l] = xr.re;
+            Rim[m][l] = xr.im;
+            Cre[m][l] = xc.re;
+            Cim[m][l] = xc.im;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int m = 0; m < KC; ++m) {
-            const Cx<T> x = Xr[m][lr];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) cfma(acc[c], x, Xc[m][cb + c]);
-        }
+        tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, b - kc);
         __syncthreads();
     }
-    const int i = r0 + lr;
-    if (i >= n) return;
+    const int l = tid & 63, wv = tid >> 6;
+    const int li = l & 15, lk = l >> 4;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int j = c0 + cb + c;
-        if (j < n && i >= j) {
-            Cx<T>* p = front_at(L, W, n, f.s, f.u, i, j);
-            *p = *p - acc[c];
-        }
-    }
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + (wv & 1) * 32 + 16 * bi + li;
+                const int j = c0 + (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
+                if (i < n && j < n && i >= j) {
+                    Cx<T>* p = front_at(L, W, n, f.s, f.u, i, j);
+                    *p = *p - cx<T>(are[bi][bj][r], aim[bi][bj][r]);
+                }
+            }
 }
 
 // ---------------------------------------------------------------------------
 // Selective inversion (Sec. 2.2): G = X with X L_F = [I; F_BL], i.e.
 // G = [L_F^{-1}; F_BL L_F^{-1}], so that both multifrontal triangular solves
 // of a front become one product with G.  Rows are independent: one
-// workgroup per 64 rows, sweeping the pivot columns from last to first.
+// workgroup per 64 rows, sweeping the 64-column pivot blocks from last to
+// first:  acc = B_blk - X(:, later columns) L(later, blk)  and then
+// X_blk = acc L_blk^{-1}, both on the matrix cores; L_blk^{-1} is the
+// diagonal-block inverse the factorisation stored above the diagonal.
 template <typename T>
 __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                                                  const FrontInst* __restrict__ inst,
                                                  const Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Gb) {
+    constexpr int KC = 16;
+    typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u, s = f.s;
     const Cx<T>* L = Lb + f.loff;
     Cx<T>* G = Gb + f.loff;
     const int r0 = w.y * 64;
-    const int tid = threadIdx.x, lr = tid & 63, cg = tid >> 6;
-    const int row = r0 + lr;
-    __shared__ Cx<T> Xs[64][65];  // X chunk [m][row], reused as the block accumulator [jj][row]
-    __shared__ Cx<T> Ls[64][65];  // L chunk [jj][m]
+    const int tid = threadIdx.x;
+    const int l = tid & 63, wv = tid >> 6;
+    const int li = l & 15, lk = l >> 4;
+    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
+    __shared__ T Are[64][LDP], Aim[64][LDP];  // the block accumulator [col][row]
     const int ncb = (s + 63) / 64;
     for (int cbk = ncb - 1; cbk >= 0; --cbk) {
         const int c0 = cbk * 64, c1 = min(c0 + 64, s), bw = c1 - c0;
-        // rows of the identity above the block are zero in L_F^{-1}
-        if (r0 + 63 < c0) {
-            for (int jj = cg; jj < bw; jj += 4)
-                if (row < n) G[(int64_t)(c0 + jj) * n + row] = cx<T>(0, 0);
+        if (r0 + 63 < c0) {  // rows of the identity above the block: zero in L_F^{-1}
+            for (int idx = tid; idx < 64 * 64; idx += 256) {
+                const int rr = idx & 63, cc = idx / 64;
+                if (cc < bw && r0 + rr < n) G[(int64_t)(c0 + cc) * n + r0 + rr] = cx<T>(0, 0);
+            }
             continue;
         }
-        Cx<T> acc[16];
+        V4 are[2][2], aim[2][2];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int jj = cg * 16 + q;
-            Cx<T> v = cx<T>(0, 0);
-            if (row < n && jj < bw) {
-                if (row < s) v = cx<T>(row == c0 + jj ? (T)1 : (T)0, 0);
-                else v = L[(int64_t)(c0 + jj) * n + row];
-            }
-            acc[q] = v;
-        }
-        for (int mc = c1; mc < s; mc += 64) {
-            const int mw = min(64, s - mc);
-            __syncthreads();
-            for (int idx = tid; idx < 64 * 64; idx += 256) {
-                int a = idx & 63, bq = idx / 64;
-                Xs[bq][a] = (bq < mw && r0 + a < n) ? G[(int64_t)(mc + bq) * n + r0 + a] : cx<T>(0, 0);
-                Ls[bq][a] = (bq < bw && a < mw) ? L[(int64_t)(c0 + bq) * n + mc + a] : cx<T>(0, 0);
-            }
-            __syncthreads();
-            for (int m = 0; m < mw; ++m) {
-                const Cx<T> x = Xs[m][lr];
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) cfms(acc[q], x, Ls[cg * 16 + q][m]);
+            for (int bj = 0; bj < 2; ++bj) {
+                are[bi][bj] = V4{0, 0, 0, 0};
+                aim[bi][bj] = V4{0, 0, 0, 0};
             }
+        // sum over the later pivot columns m >= c1: X(rows, m) L(m, blk)
+        for (int mc = c1; mc < s; mc += KC) {
+            __syncthreads();
+            for (int idx = tid; idx < KC * 64; idx += 256) {
+                const int a = idx & 63, m = idx / 64;
+                const int mm = mc + m;
+                Cx<T> x = cx<T>(0, 0), lv = cx<T>(0, 0);
+                if (mm < s) {
+                    if (r0 + a < n) x = G[(int64_t)mm * n + r0 + a];
+                    if (a < bw) lv = L[(int64_t)(c0 + a) * n + mm];  // L(mm, c0 + a)
+                }
+                Rre[m][a] = x.re;
+                Rim[m][a] = x.im;
+                Cre[m][a] = lv.re;
+                Cim[m][a] = lv.im;
+            }
+            __syncthreads();
+            tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, s - mc);
         }
         __syncthreads();
+        // acc = B_blk - sum, into LDS as [col][row]
 #pragma unroll
-        for (int q = 0; q < 16; ++q) Xs[cg * 16 + q][lr] = acc[q];
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
-            int a = idx & 63, bq = idx / 64;  // Ls[bq][a] = L[c0 + a][c0 + bq]
-            Ls[bq][a] = (bq < bw && a < bw && a > bq) ? L[(int64_t)(c0 + bq) * n + c0 + a] : cx<T>(0, 0);
-        }
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = (wv & 1) * 32 + 16 * bi + li;
+                    const int cc = (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
+                    const int row = r0 + rr;
+                    Cx<T> bv = cx<T>(0, 0);
+                    if (cc < bw && row < n) {
+                        if (row < s) bv = cx<T>(row == c0 + cc ? (T)1 : (T)0, 0);
+                        else bv = L[(int64_t)(c0 + cc) * n + row];
+                    }
+                    Are[cc][rr] = bv.re - are[bi][bj][r];
+                    Aim[cc][rr] = bv.im - aim[bi][bj][r];
+                }
         __syncthreads();
-        for (int jj = bw - 1; jj > 0; --jj) {
-            const Cx<T> x = Xs[jj][lr];
-            for (int j2 = cg; j2 < jj; j2 += 4) cfms(Xs[j2][lr], x, Ls[j2][jj]);
+        // X_blk = acc L_blk^{-1}: X(r, j) = sum_{m >= j} acc(r, m) Linv(m, j)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                are[bi][bj] = V4{0, 0, 0, 0};
+                aim[bi][bj] = V4{0, 0, 0, 0};
+            }
+        for (int mc = 0; mc < bw; mc += KC) {
             __syncthreads();
+            for (int idx = tid; idx < KC * 64; idx += 256) {
+                const int a = idx & 63, m = idx / 64;
+                const int mm = mc + m;
+                // Linv(mm, a) for mm > a is stored at L(c0 + a, c0 + mm) (upper triangle)
+                Cx<T> lv = cx<T>(0, 0);
+                if (mm < bw && a < bw) {
+                    if (mm > a) lv = L[(int64_t)(c0 + mm) * n + c0 + a];
+                    else if (mm == a) lv = cx<T>(1, 0);
+                }
+                Cre[m][a] = lv.re;
+                Cim[m][a] = lv.im;
+                Rre[m][a] = mm < bw ? Are[mm][a] : (T)0;
+                Rim[m][a] = mm < bw ? Aim[mm][a] : (T)0;
+            }
+            __syncthreads();
+            tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, bw - mc);
         }
-        if (row < n)
-            for (int jj = cg; jj < bw; jj += 4) G[(int64_t)(c0 + jj) * n + row] = Xs[jj][lr];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = r0 + (wv & 1) * 32 + 16 * bi + li;
+                    const int cc = (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
+                    if (cc < bw && row < n)
+                        G[(int64_t)(c0 + cc) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]);
+                }
         __syncthreads();
     }
 }
@@ -352,32 +497,32 @@ void launch_assemble(const int2* work, int nwork, const FrontInst* inst, const P
                      const Cx<double>* et, Cx<T>* Lb, Cx<T>* Wcur, const Cx<T>* Wchild,
                      hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_assemble<T>, dim3(nwork), dim3(256), 0, st, work, inst, pan, prob, perm,
+    HSW_LAUNCH(k_assemble<T>, dim3(nwork), dim3(256), 0, st, work, inst, pan, prob, perm,
                        ulist, cmap, et, Lb, Wcur, Wchild);
 }
 template <typename T>
 void launch_ldlt_diag(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* dinv,
                       int k, int* err, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_ldlt_diag<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k, err);
+    HSW_LAUNCH(k_ldlt_diag<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k, err);
 }
 template <typename T>
 void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb,
                        const Cx<T>* dinv, int k, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_panel_trsm<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k);
+    HSW_LAUNCH(k_panel_trsm<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k);
 }
 template <typename T>
 void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
                      int k, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_trailing<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k);
+    HSW_LAUNCH(k_trailing<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k);
 }
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
                     hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_inverse<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Gb);
+    HSW_LAUNCH(k_inverse<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Gb);
 }
 
 #define HSW_INST(T)                                                                              \

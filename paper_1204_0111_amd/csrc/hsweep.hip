@@ -130,19 +130,27 @@ static hsw_status fail(hsw_ctx* ctx, hsw_status s, const std::string& msg) {
     return s;
 }
 
-// Run `launch`, bracketed by HIP events when the named class is being timed.
+hsw::LaunchTiming& hsw::launch_timing() {
+    static thread_local LaunchTiming lt;
+    return lt;
+}
+
+// Run `launch` (one kernel launch when count > 0); when the named class is
+// being timed the launch records a pair of HIP events at its own start and end.
 template <class F>
-static void timed(hsw_ctx* ctx, const char* cls, double bytes, double flops, F&& launch) {
+static void timed(hsw_ctx* ctx, const char* cls, int count, double bytes, double flops, F&& launch) {
     KernelTimer& t = ctx->timer;
-    if (t.on && t.kernel == cls) {
+    if (count > 0 && t.on && t.kernel == cls) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
             launch();
             return;
         }
-        (void)hipEventRecord(a, ctx->st);
+        LaunchTiming& lt = launch_timing();
+        lt.start = a;
+        lt.stop = b;
         launch();
-        (void)hipEventRecord(b, ctx->st);
+        lt.start = lt.stop = nullptr;
         t.ev.emplace_back(a, b);
         t.launches += 1;
         t.bytes += bytes;
@@ -610,27 +618,27 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
     for (int d = ctx->maxdepth; d >= 0; --d) {
         const DepthSchedule& ds = ctx->fsched[d];
         const double es = sizeof(Cx<T>);
-        timed(ctx, "assemble", es * ds.assemble.bytes_per_esz, 0.0, [&] {
+        timed(ctx, "assemble", ds.assemble.count, es * ds.assemble.bytes_per_esz, 0.0, [&] {
             launch_assemble<T>(ctx->d_fwork + ds.assemble.off, ds.assemble.count, ctx->d_inst,
                                ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap,
                                ctx->d_et, L, ws[d & 1], ws[(d + 1) & 1], st);
         });
         for (size_t s = 0; s < ds.ldlt.size(); ++s) {
-            timed(ctx, "diag", es * ds.ldlt[s].bytes_per_esz, 8 * ds.ldlt[s].cmac, [&] {
+            timed(ctx, "diag", ds.ldlt[s].count, es * ds.ldlt[s].bytes_per_esz, 8 * ds.ldlt[s].cmac, [&] {
                 launch_ldlt_diag<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L,
                                     dinv, ds.ldlt[s].k, ctx->d_err, st);
             });
-            timed(ctx, "panel", es * ds.panel[s].bytes_per_esz, 8 * ds.panel[s].cmac, [&] {
+            timed(ctx, "panel", ds.panel[s].count, es * ds.panel[s].bytes_per_esz, 8 * ds.panel[s].cmac, [&] {
                 launch_panel_trsm<T>(ctx->d_fwork + ds.panel[s].off, ds.panel[s].count, ctx->d_inst,
                                      L, dinv, ds.panel[s].k, st);
             });
-            timed(ctx, "trailing", es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
+            timed(ctx, "trailing", ds.trail[s].count, es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
                 launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
                                    ws[d & 1], ds.trail[s].k, st);
             });
         }
     }
-    timed(ctx, "inverse", sizeof(Cx<T>) * ctx->inv_launch.bytes_per_esz, 8 * ctx->inv_launch.cmac, [&] {
+    timed(ctx, "inverse", ctx->inv_launch.count, sizeof(Cx<T>) * ctx->inv_launch.bytes_per_esz, 8 * ctx->inv_launch.cmac, [&] {
         launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L,
                           G, st);
     });
@@ -704,12 +712,12 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
     const auto& lv = ctx->slevels[P.cls];
     const double es = sizeof(Cx<T>);
     for (int d = c.maxdepth; d >= 0; --d)
-        timed(ctx, "fwd", es * (lv[d].g_entries + nrhs * lv[d].fwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
+        timed(ctx, "fwd", lv[d].fcount, es * (lv[d].g_entries + nrhs * lv[d].fwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
             launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, P.inst_base, ctx->d_inst, G, dinv,
                           ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
         });
     for (int d = 0; d <= c.maxdepth; ++d)
-        timed(ctx, "bwd", es * (lv[d].g_entries + nrhs * lv[d].bwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
+        timed(ctx, "bwd", lv[d].bcount, es * (lv[d].g_entries + nrhs * lv[d].bwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
             launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, P.inst_base, ctx->d_inst, G,
                           ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
         });
@@ -789,7 +797,7 @@ extern "C" hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, 
     if (s != HSW_OK) return s;
     if ((const void*)x == (const void*)y) return fail(ctx, HSW_E_INVAL, "x and y alias");
     const double np_ = (double)ctx->ph[prob].Npad;
-    timed(ctx, "matvec", np_ * (32.0 * nrhs + 8.0), 56.0 * np_ * nrhs, [&] {
+    timed(ctx, "matvec", 1, np_ * (32.0 * nrhs + 8.0), 56.0 * np_ * nrhs, [&] {
         launch_matvec(ctx->prob_h[prob], ctx->d_et, (const Cx<double>*)x, (Cx<double>*)y, nullptr, ld,
                       nrhs, 0, ctx->st);
     });
@@ -883,7 +891,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             Cx<double>* Zj = Z + (int64_t)j * vs;
             s = sweep_impl<T>(ctx, prob, Vj, Zj, nrhs, ld);
             if (s != HSW_OK) { cleanup(); return s; }
-            timed(ctx, "matvec", (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
+            timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st); });
             for (int pass = 0; pass < 2; ++pass) {
                 launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,

@@ -1,8 +1,31 @@
 // Host-side launchers of the gfx950 kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "devtypes.hpp"
 #include "plan.hpp"
+
+namespace hsw {
+
+// Events that the next launch records at its own start and end
+// (hipExtLaunchKernelGGL), set by the driver while a kernel class is timed.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTiming& launch_timing();
+
+}  // namespace hsw
+
+#define HSW_LAUNCH(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                     \
+    do {                                                                                     \
+        ::hsw::LaunchTiming& lt_ = ::hsw::launch_timing();                                   \
+        if (lt_.start)                                                                       \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, lt_.start, lt_.stop, 0,  \
+                                  __VA_ARGS__);                                              \
+        else                                                                                 \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);               \
+    } while (0)
 
 namespace hsw {
 

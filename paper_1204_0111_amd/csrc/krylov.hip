@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_matvec(ProbDev Q, const C64* __restrict
 void launch_matvec(const ProbDev& Q, const C64* et, const C64* x, C64* y, const C64* b, int64_t ld,
                    int nrhs, int mode, hipStream_t st) {
     const int64_t nb = (Q.Npad + 255) / 256;
-    hipLaunchKernelGGL(k_matvec, dim3((unsigned)nb), dim3(256), 0, st, Q, et, x, y, b, ld, nrhs, mode);
+    HSW_LAUNCH(k_matvec, dim3((unsigned)nb), dim3(256), 0, st, Q, et, x, y, b, ld, nrhs, mode);
 }
 
 // ---------------------------------------------------------------------------

@@ -294,7 +294,7 @@ static void fwd_rc(const int* work, int nwork, int inst_base, const FrontInst* i
                    int naux, int Wld, int nrhs, int smax, hipStream_t st) {
     size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + 4 * 64 * RC);
     dim3 grid(nwork, (nrhs + RC - 1) / RC);
-    hipLaunchKernelGGL((k_fwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, dinv, cmap,
+    HSW_LAUNCH((k_fwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, dinv, cmap,
                        xin, xmid, wv, naux, Wld, nrhs);
 }
 template <typename T, int RC>
@@ -303,7 +303,7 @@ static void bwd_rc(const int* work, int nwork, int inst_base, const FrontInst* i
                    hipStream_t st) {
     size_t shm = sizeof(Cx<T>) * (size_t)RC * nmax;
     dim3 grid(nwork, (nrhs + RC - 1) / RC);
-    hipLaunchKernelGGL((k_bwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, ulist, xmid,
+    HSW_LAUNCH((k_bwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, ulist, xmid,
                        xout, naux, nrhs);
 }
 
