@@ -80,7 +80,7 @@ struct FrontInst {
     int32_t child0, child1;      // instance ids of the children, -1 if none
     int32_t uoff, moff;          // absolute offsets into the update-set and extend-add map arrays
     int32_t panel, depth;        // global panel id, depth in the tree
-    int32_t pad0, pad1;
+    int32_t cw0, cw1;            // update-vector offsets (wvoff) of the two children
     int64_t loff;                // offset of the (s+u) x s factor block (complex elements)
     int64_t woff;                // offset of the u x u update matrix in its depth-parity workspace
     int64_t doff;                // offset of the s reciprocal pivots

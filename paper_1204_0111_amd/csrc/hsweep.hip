@@ -46,6 +46,7 @@ struct SolveLevel {
     int64_t foff = 0, boff = 0;
     int fcount = 0, bcount = 0;
     int smax = 0, nmax = 0;
+    int rb = SOLVE_RB, cb = SOLVE_CB;  // forward rows / backward columns per workgroup
     // algorithmic traffic in complex entries: factor part, and per right-hand side
     double g_entries = 0, fwd_vec = 0, bwd_vec = 0, cmac = 0;
 };
@@ -263,6 +264,8 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
             fi.wvoff = c.woff[f];
             fi.child0 = c.child0[f] >= 0 ? P.inst_base + c.child0[f] : -1;
             fi.child1 = c.child1[f] >= 0 ? P.inst_base + c.child1[f] : -1;
+            fi.cw0 = c.child0[f] >= 0 ? c.woff[c.child0[f]] : 0;
+            fi.cw1 = c.child1[f] >= 0 ? c.woff[c.child1[f]] : 0;
             fi.uoff = ctx->cls_ulist_off[P.cls] + c.uoff[f];
             fi.moff = ctx->cls_cmap_off[P.cls] + c.moff[f];
             fi.panel = (int)g;
@@ -405,6 +408,8 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
             sl.boff = (int64_t)swork.size();
             swork.insert(swork.end(), c.bwd_work[d].begin(), c.bwd_work[d].end());
             sl.bcount = (int)c.bwd_work[d].size() / 2;
+            sl.rb = c.fwd_rb[d];
+            sl.cb = c.bwd_cb[d];
             for (int f : c.at_depth[d]) {
                 sl.smax = std::max(sl.smax, c.s[f]);
                 sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
@@ -713,12 +718,12 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
     const double es = sizeof(Cx<T>);
     for (int d = c.maxdepth; d >= 0; --d)
         timed(ctx, "fwd", lv[d].fcount, es * (lv[d].g_entries + nrhs * lv[d].fwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
-            launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, P.inst_base, ctx->d_inst, G, dinv,
-                          ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
+            launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, lv[d].rb, P.inst_base, ctx->d_inst,
+                          G, dinv, ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
         });
     for (int d = 0; d <= c.maxdepth; ++d)
         timed(ctx, "bwd", lv[d].bcount, es * (lv[d].g_entries + nrhs * lv[d].bwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
-            launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, P.inst_base, ctx->d_inst, G,
+            launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, lv[d].cb, P.inst_base, ctx->d_inst, G,
                           ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
         });
     launch_extract<T>(emode, couple, Q, P, ctx->d_iperm, ctx->d_et, xout, naux, dst, ld, plane0, nrhs, st);

@@ -58,11 +58,11 @@ void launch_extract(int mode, int couple, const ProbDev& Q, const PanelDev& P, c
                     const Cx<double>* et, const Cx<T>* xout, int naux, Cx<double>* u, int64_t ld,
                     int plane0, int nrhs, hipStream_t st);
 template <typename T>
-void launch_fwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+void launch_fwd(const int* work, int nwork, int rb, int inst_base, const FrontInst* inst, const Cx<T>* G,
                 const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
                 int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st);
 template <typename T>
-void launch_bwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+void launch_bwd(const int* work, int nwork, int cb, int inst_base, const FrontInst* inst, const Cx<T>* G,
                 const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
                 hipStream_t st);
 template <typename T>

@@ -159,18 +159,28 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
     }
     pc.fwd_work.assign(pc.maxdepth + 1, {});
     pc.bwd_work.assign(pc.maxdepth + 1, {});
-    for (int d = 0; d <= pc.maxdepth; ++d)
+    pc.fwd_rb.assign(pc.maxdepth + 1, SOLVE_RB);
+    pc.bwd_cb.assign(pc.maxdepth + 1, SOLVE_CB);
+    for (int d = 0; d <= pc.maxdepth; ++d) {
+        int nmax = 0;
+        for (int k : pc.at_depth[d]) nmax = std::max(nmax, pc.s[k] + pc.u[k]);
+        if (nmax >= SOLVE_SMALL_BLOCK_N) {
+            pc.fwd_rb[d] = SOLVE_RB_SMALL;
+            pc.bwd_cb[d] = SOLVE_CB_SMALL;
+        }
+        const int rb = pc.fwd_rb[d], cb = pc.bwd_cb[d];
         for (int k : pc.at_depth[d]) {
             int n = pc.s[k] + pc.u[k];
-            for (int b = 0; b < (n + SOLVE_RB - 1) / SOLVE_RB; ++b) {
+            for (int b = 0; b < (n + rb - 1) / rb; ++b) {
                 pc.fwd_work[d].push_back(k);
                 pc.fwd_work[d].push_back(b);
             }
-            for (int b = 0; b < (pc.s[k] + SOLVE_CB - 1) / SOLVE_CB; ++b) {
+            for (int b = 0; b < (pc.s[k] + cb - 1) / cb; ++b) {
                 pc.bwd_work[d].push_back(k);
                 pc.bwd_work[d].push_back(b);
             }
         }
+    }
     return "";
 }
 

@@ -23,6 +23,11 @@ constexpr int TILE = 64;        // square tile of the front kernels
 constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
 constexpr int SOLVE_RB = 64;    // rows per workgroup in the forward solve
 constexpr int SOLVE_CB = 32;    // columns per workgroup in the backward solve
+// Depths whose largest front has at least this many rows use 16-row forward
+// blocks and 8-column backward blocks, spreading few large fronts over more CUs.
+constexpr int SOLVE_SMALL_BLOCK_N = 512;
+constexpr int SOLVE_RB_SMALL = 16;
+constexpr int SOLVE_CB_SMALL = 8;
 
 struct LatNode {
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
@@ -55,8 +60,10 @@ struct PanelClass {
     int64_t lsize = 0;             // sum (s+u) s
     int64_t wsize = 0;             // sum u
     std::vector<std::vector<int>> at_depth;
-    // per-depth work lists of the solves: (front, block) pairs
+    // per-depth work lists of the solves: (front, block) pairs, and the block
+    // size (rows of the forward pass, columns of the backward pass) per depth
     std::vector<std::vector<int>> fwd_work, bwd_work;
+    std::vector<int> fwd_rb, bwd_cb;
     double factor_cmac = 0, inverse_cmac = 0, solve_cmac = 0;  // per panel, per rhs for solves
 };
 

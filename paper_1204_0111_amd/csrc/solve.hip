@@ -99,12 +99,14 @@ __global__ __launch_bounds__(256) void k_extract(int mode, int couple, ProbDev Q
     }
 }
 
-// Forward pass over the fronts of one depth.  Workgroup = (front, 64 rows).
-// Each wave takes every fourth pivot column; eight independent loads per
-// thread are in flight before they are consumed.  Rows of G_TL = L_F^{-1}
-// above the diagonal are exact zeros, so a row block that lies in the
-// triangle stops at its own last row (uniform for the workgroup).
-template <typename T, int RC>
+// Forward pass over the fronts of one depth.  Workgroup = (front, RB rows);
+// the 256 threads are RB rows x 256/RB column phases.  The first eight G
+// loads of every thread and the children's contributions to its update row
+// are issued before the front vector is assembled, and the next eight loads
+// are in flight while the current ones are consumed.  Rows of
+// G_TL = L_F^{-1} above the diagonal are exact zeros, so a row block that
+// lies in the triangle stops at its own last row (uniform for the workgroup).
+template <typename T, int RC, int RB>
 __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int inst_base,
                                              const FrontInst* __restrict__ inst,
                                              const Cx<T>* __restrict__ G,
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int i
                                              const int* __restrict__ cmap,
                                              const Cx<T>* __restrict__ xin, Cx<T>* __restrict__ xmid,
                                              Cx<T>* __restrict__ wv, int naux, int Wld, int nrhs) {
+    constexpr int P = 256 / RB;  // column phases
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* sm = reinterpret_cast<Cx<T>*>(smem_raw);
     const int fcl = work[2 * blockIdx.x], rb = work[2 * blockIdx.x + 1];
@@ -120,13 +123,33 @@ __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int i
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, nrhs - rhs0);
     Cx<T>* vS = sm;              // [RC][s]
-    Cx<T>* red = sm + RC * s;    // [4][64][RC]
+    Cx<T>* red = sm + RC * s;    // [P][RB][RC]
     const int tid = threadIdx.x;
+    const int lr = tid % RB, ph = tid / RB;
+    const int row = rb * RB + lr;
+    const int kend = (rb * RB + RB <= s) ? rb * RB + RB : s;  // block-uniform
+    const int rowc = row < n ? row : n - 1;  // out-of-range lanes load a valid address
+    const Cx<T>* g = G + f.loff + rowc;
+    Cx<T> cur[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cur[q] = g[(int64_t)min(ph + P * q, kend - 1) * n];
     const int c0i = f.child0, c1i = f.child1;
-    const int c0w = c0i >= 0 ? inst[c0i].wvoff : 0;
-    const int c1w = c1i >= 0 ? inst[c1i].wvoff : 0;
     const int* map0 = cmap + f.moff;
     const int* map1 = map0 + n;
+    Cx<T> pre[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) pre[r] = cx<T>(0, 0);
+    if (ph == 0 && row < n && row >= s) {
+        const int p0 = c0i >= 0 ? map0[row] : -1;
+        const int p1 = c1i >= 0 ? map1[row] : -1;
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+            if (r < nr) {
+                const int64_t rr = rhs0 + r;
+                if (p0 >= 0) pre[r] = pre[r] + wv[rr * Wld + f.cw0 + p0];
+                if (p1 >= 0) pre[r] = pre[r] + wv[rr * Wld + f.cw1 + p1];
+            }
+    }
     for (int k = tid; k < s; k += 256) {
         const int p0 = c0i >= 0 ? map0[k] : -1, p1 = c1i >= 0 ? map1[k] : -1;
 #pragma unroll
@@ -135,56 +158,47 @@ __global__ __launch_bounds__(256) void k_fwd(const int* __restrict__ work, int i
             if (r < nr) {
                 const int64_t rr = rhs0 + r;
                 v = xin[rr * naux + f.start + k];
-                if (p0 >= 0) v = v + wv[rr * Wld + c0w + p0];
-                if (p1 >= 0) v = v + wv[rr * Wld + c1w + p1];
+                if (p0 >= 0) v = v + wv[rr * Wld + f.cw0 + p0];
+                if (p1 >= 0) v = v + wv[rr * Wld + f.cw1 + p1];
             }
             vS[r * s + k] = v;
         }
     }
     __syncthreads();
-    const int lr = tid & 63, ph = tid >> 6;
-    const int row = rb * 64 + lr;
-    const int kend = (rb * 64 + 64 <= s) ? rb * 64 + 64 : s;  // block-uniform
     Cx<T> acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
-    const int rowc = row < n ? row : n - 1;  // clamp: out-of-range lanes load a valid address
-    const Cx<T>* g = G + f.loff + rowc;
-    int k = ph;
-    for (; k + 28 < kend; k += 32) {
-        Cx<T> gv[8];
+    for (int k = ph; k < kend; k += 8 * P) {
+        const int kn = k + 8 * P;
+        Cx<T> nxt[8];
+        if (kn < kend) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) gv[q] = g[(int64_t)(k + 4 * q) * n];
+            for (int q = 0; q < 8; ++q) nxt[q] = g[(int64_t)min(kn + P * q, kend - 1) * n];
+        }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 8; ++q) {
+            const int kq = k + P * q;
+            if (kq < kend) {
 #pragma unroll
-            for (int r = 0; r < RC; ++r) cfma(acc[r], gv[q], vS[r * s + k + 4 * q]);
+                for (int r = 0; r < RC; ++r) cfma(acc[r], cur[q], vS[r * s + kq]);
+            }
+        }
+        if (kn < kend) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        }
     }
-    for (; k < kend; k += 4) {
-        const Cx<T> gv = g[(int64_t)k * n];
 #pragma unroll
-        for (int r = 0; r < RC; ++r) cfma(acc[r], gv, vS[r * s + k]);
-    }
-#pragma unroll
-    for (int r = 0; r < RC; ++r) red[(ph * 64 + lr) * RC + r] = acc[r];
+    for (int r = 0; r < RC; ++r) red[(ph * RB + lr) * RC + r] = acc[r];
     __syncthreads();
     if (ph != 0 || row >= n) return;
-    const int p0 = (row >= s && c0i >= 0) ? map0[row] : -1;
-    const int p1 = (row >= s && c1i >= 0) ? map1[row] : -1;
     for (int r = 0; r < nr; ++r) {
-        Cx<T> y = red[(0 * 64 + lr) * RC + r];
-        y = y + red[(1 * 64 + lr) * RC + r];
-        y = y + red[(2 * 64 + lr) * RC + r];
-        y = y + red[(3 * 64 + lr) * RC + r];
+        Cx<T> y = red[lr * RC + r];
+#pragma unroll
+        for (int p = 1; p < P; ++p) y = y + red[(p * RB + lr) * RC + r];
         const int64_t rr = rhs0 + r;
-        if (row < s) {
-            xmid[rr * naux + f.start + row] = y * dinv[f.doff + row];
-        } else {
-            Cx<T> a = cx<T>(0, 0);
-            if (p0 >= 0) a = a + wv[rr * Wld + c0w + p0];
-            if (p1 >= 0) a = a + wv[rr * Wld + c1w + p1];
-            wv[rr * Wld + f.wvoff + (row - s)] = a - y;
-        }
+        if (row < s) xmid[rr * naux + f.start + row] = y * dinv[f.doff + row];
+        else wv[rr * Wld + f.wvoff + (row - s)] = pre[r] - y;
     }
 }
 
@@ -195,18 +209,21 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
-// Backward pass over the fronts of one depth.  Workgroup = (front, 32
-// columns); wave w owns columns c0 + w + 4q (q < 8) and its lanes stride
-// down the rows, eight column loads in flight per step, then reduce across
-// the wave.  Rows above the block's first column are zeros of G_TL.
-template <typename T, int RC>
+// Backward pass over the fronts of one depth.  Workgroup = (front, CB
+// columns); wave w owns columns c0 + w + 4q (q < CB/4) and its lanes stride
+// down the rows, eight loads in flight per lane (columns x unrolled rows),
+// then reduce across the wave.  Rows above the block's first column are
+// zeros of G_TL.
+template <typename T, int RC, int CB>
 __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int inst_base,
                                              const FrontInst* __restrict__ inst,
                                              const Cx<T>* __restrict__ G,
                                              const int* __restrict__ ulist,
                                              const Cx<T>* __restrict__ xmid, Cx<T>* __restrict__ xout,
                                              int naux, int nrhs) {
-    constexpr int QW = 8 / RC;  // columns per wave per pass
+    constexpr int CW = CB / 4;                                  // columns per wave
+    constexpr int QW = CW < 8 / RC ? CW : (8 / RC > 0 ? 8 / RC : 1);  // columns per pass
+    constexpr int RU = 8 / QW > 0 ? 8 / QW : 1;                 // unrolled row steps
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
     const int fcl = work[2 * blockIdx.x], cbk = work[2 * blockIdx.x + 1];
@@ -215,7 +232,24 @@ __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int i
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, nrhs - rhs0);
     const int tid = threadIdx.x;
-    const int c0 = cbk * SOLVE_CB;
+    const int c0 = cbk * CB;
+    const int wave = tid >> 6, lane = tid & 63;
+    const Cx<T>* gb = G + f.loff;
+    // first row batch of pass 0, issued before the front vector is assembled
+    int cols[QW];
+    bool live[QW];
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+        const int j = c0 + wave + 4 * q;
+        live[q] = j < s;
+        cols[q] = live[q] ? j : s - 1;
+    }
+    Cx<T> cur[RU][QW];
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int q = 0; q < QW; ++q)
+            cur[u][q] = gb[(int64_t)cols[q] * n + min(c0 + lane + 64 * u, n - 1)];
     for (int i = c0 + tid; i < n; i += 256) {
         const int e = i < s ? f.start + i : ulist[f.uoff + i - s];
 #pragma unroll
@@ -229,30 +263,51 @@ __global__ __launch_bounds__(256) void k_bwd(const int* __restrict__ work, int i
         }
     }
     __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63;
-    for (int pass = 0; pass < 8 / QW; ++pass) {
-        int cols[QW];
-        bool live[QW];
+    for (int pass = 0; pass < CW / QW; ++pass) {
+        if (pass > 0) {
 #pragma unroll
-        for (int q = 0; q < QW; ++q) {
-            const int j = c0 + wave + 4 * (pass * QW + q);
-            live[q] = j < s;
-            cols[q] = live[q] ? j : s - 1;
+            for (int q = 0; q < QW; ++q) {
+                const int j = c0 + wave + 4 * (pass * QW + q);
+                live[q] = j < s;
+                cols[q] = live[q] ? j : s - 1;
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int q = 0; q < QW; ++q)
+                    cur[u][q] = gb[(int64_t)cols[q] * n + min(c0 + lane + 64 * u, n - 1)];
         }
         Cx<T> acc[QW][RC];
 #pragma unroll
         for (int q = 0; q < QW; ++q)
 #pragma unroll
             for (int r = 0; r < RC; ++r) acc[q][r] = cx<T>(0, 0);
-        const Cx<T>* gb = G + f.loff;
-        for (int i = c0 + lane; i < n; i += 64) {
-            Cx<T> gv[QW];
+        for (int i0 = c0 + lane; i0 < n; i0 += 64 * RU) {
+            const int in = i0 + 64 * RU;
+            Cx<T> nxt[RU][QW];
+            if (in < n) {
 #pragma unroll
-            for (int q = 0; q < QW; ++q) gv[q] = gb[(int64_t)cols[q] * n + i];
+                for (int u = 0; u < RU; ++u)
 #pragma unroll
-            for (int q = 0; q < QW; ++q)
+                    for (int q = 0; q < QW; ++q)
+                        nxt[u][q] = gb[(int64_t)cols[q] * n + min(in + 64 * u, n - 1)];
+            }
 #pragma unroll
-                for (int r = 0; r < RC; ++r) cfma(acc[q][r], gv[q], rv[r * n + i]);
+            for (int u = 0; u < RU; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < n) {
+#pragma unroll
+                    for (int q = 0; q < QW; ++q)
+#pragma unroll
+                        for (int r = 0; r < RC; ++r) cfma(acc[q][r], cur[u][q], rv[r * n + i]);
+                }
+            }
+            if (in < n) {
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int q = 0; q < QW; ++q) cur[u][q] = nxt[u][q];
+            }
         }
 #pragma unroll
         for (int q = 0; q < QW; ++q)
@@ -288,23 +343,23 @@ void launch_extract(int mode, int couple, const ProbDev& Q, const PanelDev& P, c
                        iperm, et, xout, naux, u, ld, plane0, nrhs);
 }
 
-template <typename T, int RC>
+template <typename T, int RC, int RB>
 static void fwd_rc(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
                    const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
                    int naux, int Wld, int nrhs, int smax, hipStream_t st) {
-    size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + 4 * 64 * RC);
+    size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + 256 * RC);
     dim3 grid(nwork, (nrhs + RC - 1) / RC);
-    HSW_LAUNCH((k_fwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, dinv, cmap,
-                       xin, xmid, wv, naux, Wld, nrhs);
+    HSW_LAUNCH((k_fwd<T, RC, RB>), grid, dim3(256), shm, st, work, inst_base, inst, G, dinv, cmap,
+               xin, xmid, wv, naux, Wld, nrhs);
 }
-template <typename T, int RC>
+template <typename T, int RC, int CB>
 static void bwd_rc(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
                    const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
                    hipStream_t st) {
     size_t shm = sizeof(Cx<T>) * (size_t)RC * nmax;
     dim3 grid(nwork, (nrhs + RC - 1) / RC);
-    HSW_LAUNCH((k_bwd<T, RC>), grid, dim3(256), shm, st, work, inst_base, inst, G, ulist, xmid,
-                       xout, naux, nrhs);
+    HSW_LAUNCH((k_bwd<T, RC, CB>), grid, dim3(256), shm, st, work, inst_base, inst, G, ulist, xmid,
+               xout, naux, nrhs);
 }
 
 // Right-hand sides per workgroup: as many as fit 64 KiB of LDS (front vector
@@ -317,29 +372,48 @@ int solve_rhs_chunk(int nrhs, int nmax) {
     return rc;
 }
 
+template <typename T, int RB>
+static void fwd_rb(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                   const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
+                   int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st) {
+    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
+        case 8: fwd_rc<T, 8, RB>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        case 4: fwd_rc<T, 4, RB>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        case 2: fwd_rc<T, 2, RB>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+        default: fwd_rc<T, 1, RB>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
+    }
+}
+template <typename T, int CB>
+static void bwd_cb(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+                   const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
+                   hipStream_t st) {
+    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
+        case 8: bwd_rc<T, 8, CB>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        case 4: bwd_rc<T, 4, CB>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        case 2: bwd_rc<T, 2, CB>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+        default: bwd_rc<T, 1, CB>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
+    }
+}
+
 template <typename T>
-void launch_fwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+void launch_fwd(const int* work, int nwork, int rb, int inst_base, const FrontInst* inst, const Cx<T>* G,
                 const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
                 int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st) {
     if (nwork <= 0) return;
-    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
-        case 8: fwd_rc<T, 8>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
-        case 4: fwd_rc<T, 4>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
-        case 2: fwd_rc<T, 2>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
-        default: fwd_rc<T, 1>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, st); break;
-    }
+    if (rb == SOLVE_RB_SMALL)
+        fwd_rb<T, SOLVE_RB_SMALL>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, nmax, st);
+    else
+        fwd_rb<T, SOLVE_RB>(work, nwork, inst_base, inst, G, dinv, cmap, xin, xmid, wv, naux, Wld, nrhs, smax, nmax, st);
 }
 template <typename T>
-void launch_bwd(const int* work, int nwork, int inst_base, const FrontInst* inst, const Cx<T>* G,
+void launch_bwd(const int* work, int nwork, int cb, int inst_base, const FrontInst* inst, const Cx<T>* G,
                 const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
                 hipStream_t st) {
     if (nwork <= 0) return;
-    switch (solve_rhs_chunk<T>(nrhs, nmax)) {
-        case 8: bwd_rc<T, 8>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
-        case 4: bwd_rc<T, 4>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
-        case 2: bwd_rc<T, 2>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
-        default: bwd_rc<T, 1>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st); break;
-    }
+    if (cb == SOLVE_CB_SMALL)
+        bwd_cb<T, SOLVE_CB_SMALL>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st);
+    else
+        bwd_cb<T, SOLVE_CB>(work, nwork, inst_base, inst, G, ulist, xmid, xout, naux, nrhs, nmax, st);
 }
 
 #define HSW_INST(T)                                                                               \
@@ -349,10 +423,11 @@ void launch_bwd(const int* work, int nwork, int inst_base, const FrontInst* inst
     template void launch_extract<T>(int, int, const ProbDev&, const PanelDev&, const int*,       \
                                     const Cx<double>*, const Cx<T>*, int, Cx<double>*, int64_t,  \
                                     int, int, hipStream_t);                                      \
-    template void launch_fwd<T>(const int*, int, int, const FrontInst*, const Cx<T>*,            \
+    template void launch_fwd<T>(const int*, int, int, int, const FrontInst*, const Cx<T>*,       \
                                 const Cx<T>*, const int*, const Cx<T>*, Cx<T>*, Cx<T>*, int, int, \
                                 int, int, int, hipStream_t);                                     \
-    template void launch_bwd<T>(const int*, int, int, const FrontInst*, const Cx<T>*, const int*, \
+    template void launch_bwd<T>(const int*, int, int, int, const FrontInst*, const Cx<T>*,       \
+                                const int*,                                                      \
                                 const Cx<T>*, Cx<T>*, int, int, int, hipStream_t);               \
     template int solve_rhs_chunk<T>(int, int);
 HSW_INST(float)
