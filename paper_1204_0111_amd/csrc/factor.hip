@@ -206,6 +206,10 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
         X[col][row] = cx<T>(row == col ? (T)1 : (T)0, 0);
     }
     __syncthreads();
+    // Step m: pivot d_m, rank-1 update of the trailing block with the unscaled
+    // column m, and the same elimination applied to X = L_kk^{-1} (rows i > m
+    // lose l_im times row m of X, which is final; only columns c <= m are
+    // nonzero), then column m is scaled to l_im.
     for (int m = 0; m < b; ++m) {
         const Cx<T> dm = A[m][m];
         const Cx<T> idm = crecip(dm);
@@ -214,6 +218,11 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
             const Cx<T> ljj = A[m][jj] * idm;
             for (int i = jj + (tid >> 6); i < b; i += 4) cfms(A[jj][i], A[m][i], ljj);
         }
+        const int nb_ = b - m - 1;
+        for (int idx = tid; idx < nb_ * (m + 1); idx += 256) {
+            const int i = m + 1 + idx % nb_, c = idx / nb_;
+            cfms(X[c][i], A[m][i] * idm, X[c][m]);
+        }
         if (tid == 0) {
             dv[m] = idm;
             bool finite = isfinite(dm.re) && isfinite(dm.im) && isfinite(idm.re) && isfinite(idm.im);
@@ -221,15 +230,6 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
         }
         __syncthreads();
         if (tid > m && tid < b) A[m][tid] = A[m][tid] * idm;
-        __syncthreads();
-    }
-    // X = L_kk^{-1} by row operations: after step m, row m of X is final and
-    // rows i > m lose L(i, m) times it (columns c <= m only are nonzero).
-    for (int m = 0; m < b - 1; ++m) {
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int i = idx & (NB - 1), c = idx / NB;
-            if (i > m && i < b && c <= m) cfms(X[c][i], A[m][i], X[c][m]);
-        }
         __syncthreads();
     }
     for (int idx = tid; idx < NB * NB; idx += 256) {
@@ -246,52 +246,68 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
 }
 
 // Panel rows below the diagonal block: F_BL := F_BL L_kk^{-T} D_kk^{-1} for 64
-// rows per workgroup, as a product with the stored L_kk^{-1}:
-// X(r, j) = dinv_j sum_{m <= j} P(r, m) L_kk^{-1}(j, m).
+// rows per workgroup, as a product with the stored L_kk^{-1} on the matrix
+// cores: X(r, j) = dinv_j sum_{m <= j} P(r, m) L_kk^{-1}(j, m).
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ work,
                                                     const FrontInst* __restrict__ inst,
                                                     Cx<T>* __restrict__ Lb,
                                                     const Cx<T>* __restrict__ dinv, int k) {
+    constexpr int KC = 16;
+    typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff;
-    __shared__ Cx<T> Li[NB][NB + 1];  // Li[j][m] = L_kk^{-1}(j, m), zero for m > j
-    __shared__ Cx<T> Pn[NB][NB + 1];  // panel rows, Pn[m][row]
+    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
     __shared__ Cx<T> dv[NB];
     const int tid = threadIdx.x;
     const int rbeg = k + b + w.y * 64, rend = min(rbeg + 64, n);
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int row = idx & (NB - 1), col = idx / NB;
-        // stored transposed above the diagonal: L(k+m, k+j) for m < j holds L_kk^{-1}(j, m)
-        Cx<T> v = cx<T>(0, 0);
-        if (row < b && col < b) {
-            if (row < col) v = L[(int64_t)(k + col) * n + k + row];
-            else if (row == col) v = cx<T>(1, 0);
-        }
-        Li[col][row] = v;  // Li[j = col][m = row]
-        const int r = rbeg + row;
-        Pn[col][row] = (col < b && r < rend) ? L[(int64_t)(k + col) * n + r] : cx<T>(0, 0);
-    }
     if (tid < b) dv[tid] = dinv[f.doff + k + tid];
-    __syncthreads();
-    const int lr = tid & 63, jg = tid >> 6;
-    if (rbeg + lr >= rend) return;
-    Cx<T> acc[16];
+    V4 are[2][2], aim[2][2];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = cx<T>(0, 0);
-    for (int m = 0; m < b; ++m) {
-        const Cx<T> p = Pn[m][lr];
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) cfma(acc[q], p, Li[jg * 16 + q][m]);
+        for (int bj = 0; bj < 2; ++bj) {
+            are[bi][bj] = V4{0, 0, 0, 0};
+            aim[bi][bj] = V4{0, 0, 0, 0};
+        }
+    for (int kc = 0; kc < b; kc += KC) {
+        __syncthreads();
+        for (int idx = tid; idx < KC * 64; idx += 256) {
+            const int a = idx & 63, m = idx / 64;
+            const int mm = kc + m;
+            Cx<T> pv = cx<T>(0, 0), lv = cx<T>(0, 0);
+            if (mm < b) {
+                if (rbeg + a < rend) pv = L[(int64_t)(k + mm) * n + rbeg + a];
+                // L_kk^{-1}(a, mm): 1 on the diagonal, stored at L(k+mm, k+a) when mm < a
+                if (a < b) {
+                    if (mm < a) lv = L[(int64_t)(k + a) * n + k + mm];
+                    else if (mm == a) lv = cx<T>(1, 0);
+                }
+            }
+            Rre[m][a] = pv.re;
+            Rim[m][a] = pv.im;
+            Cre[m][a] = lv.re;
+            Cim[m][a] = lv.im;
+        }
+        __syncthreads();
+        tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, b - kc);
     }
+    const int l = tid & 63, wv = tid >> 6;
+    const int li = l & 15, lk = l >> 4;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int j = jg * 16 + q;
-        if (j < b) L[(int64_t)(k + j) * n + rbeg + lr] = acc[q] * dv[j];
-    }
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rbeg + (wv & 1) * 32 + 16 * bi + li;
+                const int j = (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
+                if (row < rend && j < b)
+                    L[(int64_t)(k + j) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]) * dv[j];
+            }
 }
 
 // ---------------------------------------------------------------------------

@@ -114,18 +114,32 @@ __global__ __launch_bounds__(256) void k_dots_partial(const C64* __restrict__ V,
     }
 }
 
-// h[r * hld + i] (+)= sum over chunks of partial (fixed order).  mode 0: store, 1: add.
-// Also copies the result to hout[r * hld + i] (the coefficients of the next axpy).
-__global__ void k_dots_final(const C64* __restrict__ partial, int nchunk, int nvec,
-                             const int* __restrict__ active, C64* __restrict__ h, int hld,
-                             C64* __restrict__ hout, int mode) {
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// h[r * hld + i] (+)= sum over chunks of partial (fixed order: lane-strided
+// sums, then a fixed butterfly).  mode 0: store, 1: add.  Also copies the
+// result to hout[r * hld + i] (the coefficients of the next axpy).  One
+// workgroup of four waves per right-hand side, one wave per coefficient.
+__global__ __launch_bounds__(256) void k_dots_final(const C64* __restrict__ partial, int nchunk,
+                                                    int nvec, const int* __restrict__ active,
+                                                    C64* __restrict__ h, int hld,
+                                                    C64* __restrict__ hout, int mode) {
     const int r = blockIdx.x;
     if (!active[r]) return;
-    for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i < nvec; i += 4) {
         C64 t = cx<double>(0, 0);
-        for (int c = 0; c < nchunk; ++c) t = t + partial[((int64_t)r * nchunk + c) * nvec + i];
-        hout[r * hld + i] = t;
-        h[r * hld + i] = mode == 0 ? t : h[r * hld + i] + t;
+        for (int c = lane; c < nchunk; c += 64) t = t + partial[((int64_t)r * nchunk + c) * nvec + i];
+        t.re = wave_sum_d(t.re);
+        t.im = wave_sum_d(t.im);
+        if (lane == 0) {
+            hout[r * hld + i] = t;
+            h[r * hld + i] = mode == 0 ? t : h[r * hld + i] + t;
+        }
     }
 }
 
@@ -164,17 +178,21 @@ __global__ __launch_bounds__(256) void k_norm_partial(const C64* __restrict__ w,
     if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = t.re;
 }
 
-// norm[r] = sqrt(sum of partials); if hptr: H(j+1, j) = norm.
-__global__ void k_norm_final(const double* __restrict__ partial, int nchunk,
-                             const int* __restrict__ active, double* __restrict__ norm,
-                             C64* __restrict__ hptr, int hld) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= (int)gridDim.x * (int)blockDim.x) return;
+// norm[r] = sqrt(sum of partials); if hptr: H(j+1, j) = norm.  One wave per
+// right-hand side, fixed summation order.
+__global__ __launch_bounds__(64) void k_norm_final(const double* __restrict__ partial, int nchunk,
+                                                   const int* __restrict__ active,
+                                                   double* __restrict__ norm, C64* __restrict__ hptr,
+                                                   int hld) {
+    const int r = blockIdx.x;
     if (active && !active[r]) return;
     double t = 0;
-    for (int c = 0; c < nchunk; ++c) t += partial[(int64_t)r * nchunk + c];
-    norm[r] = sqrt(t);
-    if (hptr) hptr[r * hld] = cx<double>(sqrt(t), 0.0);
+    for (int c = threadIdx.x; c < nchunk; c += 64) t += partial[(int64_t)r * nchunk + c];
+    t = wave_sum_d(t);
+    if (threadIdx.x == 0) {
+        norm[r] = sqrt(t);
+        if (hptr) hptr[r * hld] = cx<double>(sqrt(t), 0.0);
+    }
 }
 
 // v = w / norm[r]  (norm 0 leaves v = 0)
@@ -263,7 +281,7 @@ void launch_dots(const C64* V, int64_t vstride, const C64* w, int64_t ld, int64_
     const int nch = dots_chunks(N);
     hipLaunchKernelGGL(k_dots_partial, dim3(nch, nrhs), dim3(256), 0, st, V, vstride, w, ld, N, nvec,
                        active, partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(64), 0, st, partial, nch, nvec, active, h, hld,
+    hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(256), 0, st, partial, nch, nvec, active, h, hld,
                        hout, mode);
 }
 void launch_axpy_multi(const C64* V, int64_t vstride, C64* w, int64_t ld, int64_t N, int nvec,
@@ -277,7 +295,7 @@ void launch_norm(const C64* w, int64_t ld, int64_t N, int nrhs, const int* activ
                  double* norm, C64* hptr, int hld, hipStream_t st) {
     const int nch = dots_chunks(N);
     hipLaunchKernelGGL(k_norm_partial, dim3(nch, nrhs), dim3(256), 0, st, w, ld, N, active, partial);
-    hipLaunchKernelGGL(k_norm_final, dim3(nrhs), dim3(1), 0, st, partial, nch, active, norm, hptr, hld);
+    hipLaunchKernelGGL(k_norm_final, dim3(nrhs), dim3(64), 0, st, partial, nch, active, norm, hptr, hld);
 }
 void launch_scale(const C64* w, C64* v, int64_t ld, int64_t N, int nrhs, const double* norm,
                   const int* active, hipStream_t st) {
