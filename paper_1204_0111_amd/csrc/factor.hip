@@ -316,11 +316,22 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
 // Z F_BL^T Schur update of Sec. 2.2 applied blockwise, plus the update of
 // the remaining pivot columns.  One workgroup per 64 x 64 output tile, on
 // the matrix cores.
+// Round to the nearest bfloat16 (ties to even), kept in an FP32 register:
+// products of two such values are exact in FP32, so the matrix cores then
+// compute a bf16-input, FP32-accumulate product.
+__device__ inline float round_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+__device__ inline double round_bf16(double x) { return x; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
                                                   const FrontInst* __restrict__ inst,
                                                   Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
-                                                  int k) {
+                                                  int k, int bf16) {
     constexpr int KC = 16;
     typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
@@ -355,6 +366,10 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
                 const Cx<T>* col = L + (int64_t)(k + km) * n;
                 if (r0 + l < n) xr = col[r0 + l];
                 if (c0 + l < n) xc = col[c0 + l] * dd[km];
+            }
+            if (bf16) {
+                xr = cx<T>(round_bf16(xr.re), round_bf16(xr.im));
+                xc = cx<T>(round_bf16(xc.re), round_bf16(xc.im));
             }
             Rre[m][l] = xr.re;
             Rim[m][l] = xr.im;
@@ -530,9 +545,9 @@ void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>
 }
 template <typename T>
 void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
-                     int k, hipStream_t st) {
+                     int k, int bf16, hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH(k_trailing<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k);
+    HSW_LAUNCH(k_trailing<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, bf16);
 }
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
@@ -551,7 +566,7 @@ void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx
     template void launch_panel_trsm<T>(const int2*, int, const FrontInst*, Cx<T>*, const Cx<T>*, \
                                        int, hipStream_t);                                       \
     template void launch_trailing<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int,    \
-                                     hipStream_t);                                              \
+                                     int, hipStream_t);                                         \
     template void launch_inverse<T>(const int2*, int, const FrontInst*, const Cx<T>*, Cx<T>*,    \
                                     hipStream_t);
 HSW_INST(float)

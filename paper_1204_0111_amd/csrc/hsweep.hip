@@ -639,7 +639,7 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
             });
             timed(ctx, "trailing", ds.trail[s].count, es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
                 launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
-                                   ws[d & 1], ds.trail[s].k, st);
+                                   ws[d & 1], ds.trail[s].k, ctx->prec == HSW_C64_BF16GEMM, st);
             });
         }
     }

@@ -43,7 +43,7 @@ void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>
                        const Cx<T>* dinv, int k, hipStream_t st);
 template <typename T>
 void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
-                     int k, hipStream_t st);
+                     int k, int bf16, hipStream_t st);
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
                     hipStream_t st);

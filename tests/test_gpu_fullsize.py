@@ -99,3 +99,18 @@ def test_solve_full_size_matches_oracle_iterations(cfg2, prec):
         assert abs(it - ref["iters"]) <= 1, (it, ref["iters"])
     else:
         assert it <= 1.2 * ref["iters"] + 1, (it, ref["iters"])
+
+
+def test_20cubed_solve_matches_oracle_iterations():
+    """The 20^3 constant-velocity workload (gamma 5, one plane per panel) in complex128."""
+    P = wl.make_problem(1)
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_iterations.json")))["cfg1"]
+    assert abs(ref["C"] - P["C"]) < 1e-12
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
+    S = _solver(P, "c128")
+    assert S.query(0, "m") == 20 and S.query(0, "fronts") == 31
+    xs, info = S.solve([torch.as_tensor(b).to("cuda")], rtol=1e-5, restart=20)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    x = xs[0].cpu().numpy()[0]
+    assert np.linalg.norm(b[0] - A @ x) / np.linalg.norm(b[0]) < 1e-5
+    assert abs(info["iters"][0] - ref["iters"]) <= 1, (info["iters"][0], ref["iters"])

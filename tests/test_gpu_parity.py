@@ -204,3 +204,53 @@ def test_errors_are_reported():
         S.query(0, "no_such_key")
     with pytest.raises(HswError):
         Solver(dict(P, gamma=0), precision="c64")
+
+
+def test_bf16_schur_inputs_change_factors_and_still_converge(medium):
+    """Complex BF16 Schur-update inputs: the preconditioner is coarser, FP64 GMRES still converges.
+
+    Tolerance: bf16 keeps 8 significand bits (unit roundoff 2^-8 ~ 3.9e-3); the
+    panel solves amplify it by the conditioning of the fronts, so the sweep is
+    asserted within 5e-2 of the oracle, and it must differ from the complex64
+    sweep by more than complex64 rounding (the rounding is active).
+    """
+    P = medium
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((1, O.N_pad), 13)
+    ref = O.apply(r.T).T
+    Sb = _solver(P, "c64_bf16")
+    S4 = _solver(P, "c64")
+    zb = Sb.apply(0, _cuda(r)).cpu().numpy()
+    z4 = S4.apply(0, _cuda(r)).cpu().numpy()
+    eb, e4 = rel(zb, ref), rel(z4, ref)
+    assert eb <= 5e-2 and eb > 10 * e4, (eb, e4)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], [[0.5, 0.5, 0.5]]).reshape(1, -1)
+    xs, info = Sb.solve([_cuda(b)], rtol=1e-5, restart=20)
+    x = xs[0].cpu().numpy()[0]
+    assert np.linalg.norm(b[0] - A @ x) / np.linalg.norm(b[0]) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_several_problems_in_one_context(prec):
+    """Problems of different sizes share every setup launch; each matches its own oracle."""
+    Ps = [case(n=(9, 8, 10), gamma=2, d=2, leaf=3, seed=21),
+          case(n=(12, 10, 7), gamma=3, d=3, leaf=4, seed=22, model="layered")]
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(Ps, precision=prec)
+    S.assemble([P["c"] for P in Ps])
+    S.setup()
+    bs = []
+    for k, P in enumerate(Ps):
+        O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+        r = wl.random_complex((2, O.N_pad), 30 + k)
+        z = S.apply(k, _cuda(r)).cpu().numpy()
+        assert rel(z, O.apply(r.T).T) <= TOL[prec], k
+        bs.append(_cuda(wl.gaussian_sources(P["n"], P["gamma"], P["h"],
+                                            [[0.5, 0.5, 0.5]]).reshape(1, -1)))
+    xs, info = S.solve(bs, rtol=1e-5)
+    for k, P in enumerate(Ps):
+        A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+        b = bs[k].cpu().numpy()[0]
+        x = xs[k].cpu().numpy()[0]
+        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-5
