@@ -86,6 +86,49 @@ struct FrontInst {
     int64_t doff;                // offset of the s reciprocal pivots
 };
 
+// One workgroup of a forward or backward pass of a panel solve.  Offsets are
+// relative to the panel (factors, pivots) or to the panel class (maps, pass
+// vectors), except moff and pmap, which index the concatenated map arrays.
+struct SolveItem {
+    int64_t loff;            // the front's (s+u) x s block of G
+    int32_t n, s, start;     // rows, pivots, first elimination position
+    int32_t blk;             // first row (forward) or column (backward) of the workgroup
+    int32_t moff;            // extend-add maps: 2n entries, position in child 0 / 1 update set or -1
+    int32_t c2;              // the front's child-contribution slots (2n per right-hand side)
+    int32_t push;            // forward: the front's slot in its parent's contributions, -1 at the root
+    int32_t pmap;            // forward: position of each update entry in the parent front
+    int32_t xu;              // the front's update-set values (u per right-hand side)
+    int32_t cxu0, cxu1;      // backward: the children's update-set values, -1 if no child
+    int32_t pad[3];
+};
+static_assert(sizeof(SolveItem) == 64, "SolveItem is one 64-byte scalar load");
+
+// Everything a pass kernel needs besides its work item; passed by value.
+template <typename T>
+struct PassArgs {
+    const SolveItem* items;
+    const Cx<T>* G;            // the panel's factors
+    const Cx<T>* dinv;         // the panel's reciprocal pivots
+    const int* cmap;           // extend-add maps (concatenated)
+    const int* pmap;           // parent positions (concatenated)
+    const int* perm;           // the class's elimination order: position -> box index
+    const Cx<double>* et;      // stretch tables
+    const Cx<double>* src;     // forward: padded-grid input (column r at r * ld)
+    Cx<double>* dst;           // backward: padded-grid output
+    int64_t ld;
+    Cx<T>* xmid;               // D^{-1} L^{-1} x in elimination order, column r at r * naux
+    Cx<T>* c2;                 // child contributions, column r at r * c2ld
+    Cx<T>* xu;                 // update-set values, column r at r * xuld
+    int naux, c2ld, xuld, nrhs;
+    int mode;                  // forward: 0 zero extension of the panel planes, 1 coupling
+                               // J_{i+1,i}^T of the next plane; backward: 0 store, 1 subtract
+    int couple;                // backward, mode 0: also subtract J_{i+1,i} x from the next plane
+    int plane0;                // padded-grid plane held at offset 0 of src / dst
+    int Nx, NxNy, nz, ga, lo, hi;
+    int e1, e2, ie3hi;         // et offsets: e1 and e2 node tables, 1/e3 at the half plane below hi
+    double inv_h2;
+};
+
 struct PanelDev {
     int32_t prob, cls, Nx, Ny, nz, ga, lo, hi;
     int32_t perm_off;    // offset into the elimination-order arrays

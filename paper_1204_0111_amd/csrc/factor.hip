@@ -179,11 +179,19 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
 
 // ---------------------------------------------------------------------------
 // Diagonal block [k, k+b) of the blocked partial LDL^T: one workgroup per
-// front factors the b x b block in LDS (unpivoted, transposes only), then
-// inverts the unit lower factor.  It writes L_kk below the diagonal, the
-// pivots D_kk on it and L_kk^{-1} transposed in the (otherwise unused) strict
-// upper triangle of the block, plus the reciprocal pivots.  A zero or
-// non-finite pivot is reported.
+// front factors the b x b block (unpivoted, transposes only) and inverts the
+// unit lower factor.  It writes L_kk below the diagonal, the pivots D_kk on
+// it and L_kk^{-1} transposed in the (otherwise unused) strict upper
+// triangle of the block, plus the reciprocal pivots.  A zero or non-finite
+// pivot is reported.
+//
+// Register-blocked: thread t owns rows 4(t%16).. and columns 4(t/16).. of
+// the 64 x 64 block and of X = L_kk^{-1}.  Step m broadcasts column m of
+// the partially eliminated block (its pivot d_m and the unscaled entries
+// a_im) and row m of X, which is final by then; every thread then applies
+// A(i,j) -= a_im a_jm / d_m for i >= j > m and X(i,c) -= (a_im / d_m) X(m,c)
+// for i > m >= c to its own tile.  Two LDS buffers alternate, so a step
+// needs one barrier.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work,
                                                    const FrontInst* __restrict__ inst,
@@ -193,53 +201,82 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
-    Cx<T>* L = Lb + f.loff;
-    __shared__ Cx<T> A[NB][NB + 1];  // A[col][row]
-    __shared__ Cx<T> X[NB][NB + 1];  // inverse of the unit lower factor, X[col][row]
-    __shared__ Cx<T> dv[NB];
+    Cx<T>* L = Lb + f.loff + (int64_t)k * n + k;  // block origin, leading dimension n
+    __shared__ Cx<T> colb[2][NB];  // column m of the eliminated block
+    __shared__ Cx<T> rowb[2][NB];  // row m of X
     __shared__ int bad;
     const int tid = threadIdx.x;
+    const int R0 = 4 * (tid & 15), C0 = 4 * (tid >> 4);
     if (tid == 0) bad = -1;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        int row = idx & (NB - 1), col = idx / NB;
-        if (row < b && col < b && row >= col) A[col][row] = L[(int64_t)(k + col) * n + k + row];
-        X[col][row] = cx<T>(row == col ? (T)1 : (T)0, 0);
+    Cx<T> A[4][4], X[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = R0 + r, j = C0 + c;
+            A[r][c] = (i < b && j < b && i >= j) ? L[(int64_t)j * n + i] : cx<T>(0, 0);
+            X[r][c] = cx<T>(i == j ? (T)1 : (T)0, 0);
+        }
+    for (int m = 0; m < b; ++m) {
+        const int p = m & 1;
+        if (C0 <= m && m < C0 + 4) {  // owners of column m
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (C0 + c == m) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) colb[p][R0 + r] = A[r][c];
+                }
+        }
+        if (R0 <= m && m < R0 + 4) {  // owners of row m of X
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (R0 + r == m) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) rowb[p][C0 + c] = X[r][c];
+                }
+        }
+        __syncthreads();
+        const Cx<T> dm = colb[p][m];
+        const Cx<T> idm = crecip(dm);
+        if (tid == 0) {
+            dinv[f.doff + k + m] = idm;
+            const bool finite = isfinite(dm.re) && isfinite(dm.im) && isfinite(idm.re) && isfinite(idm.im);
+            if ((!finite || (dm.re == 0 && dm.im == 0)) && bad < 0) bad = m;
+        }
+        if (R0 + 3 <= m) continue;  // every row of this tile is eliminated already
+        Cx<T> ai[4], lj[4], xr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ai[r] = colb[p][R0 + r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            lj[c] = colb[p][C0 + c] * idm;
+            xr[c] = rowb[p][C0 + c];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = R0 + r;
+            if (i <= m) continue;
+            const Cx<T> li = ai[r] * idm;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = C0 + c;
+                if (j > m && j <= i) cfms(A[r][c], ai[r], lj[c]);
+                if (j <= m) cfms(X[r][c], li, xr[c]);
+                if (j == m) A[r][c] = li;  // column m is final: store l_im
+            }
+        }
     }
     __syncthreads();
-    // Step m: pivot d_m, rank-1 update of the trailing block with the unscaled
-    // column m, and the same elimination applied to X = L_kk^{-1} (rows i > m
-    // lose l_im times row m of X, which is final; only columns c <= m are
-    // nonzero), then column m is scaled to l_im.
-    for (int m = 0; m < b; ++m) {
-        const Cx<T> dm = A[m][m];
-        const Cx<T> idm = crecip(dm);
-        const int jj = tid & 63;
-        if (jj > m && jj < b) {
-            const Cx<T> ljj = A[m][jj] * idm;
-            for (int i = jj + (tid >> 6); i < b; i += 4) cfms(A[jj][i], A[m][i], ljj);
+    // L_kk and D_kk on and below the diagonal; X = L_kk^{-1} transposed above:
+    // block entry (c, i) with c < i holds X(i, c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = R0 + r, j = C0 + c;
+            if (i < b && j < b && i >= j) L[(int64_t)j * n + i] = A[r][c];
+            if (i < b && j < b && i > j) L[(int64_t)i * n + j] = X[r][c];
         }
-        const int nb_ = b - m - 1;
-        for (int idx = tid; idx < nb_ * (m + 1); idx += 256) {
-            const int i = m + 1 + idx % nb_, c = idx / nb_;
-            cfms(X[c][i], A[m][i] * idm, X[c][m]);
-        }
-        if (tid == 0) {
-            dv[m] = idm;
-            bool finite = isfinite(dm.re) && isfinite(dm.im) && isfinite(idm.re) && isfinite(idm.im);
-            if (!finite || (dm.re == 0 && dm.im == 0)) { if (bad < 0) bad = m; }
-        }
-        __syncthreads();
-        if (tid > m && tid < b) A[m][tid] = A[m][tid] * idm;
-        __syncthreads();
-    }
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        int row = idx & (NB - 1), col = idx / NB;
-        if (row < b && col < b) {
-            if (row >= col) L[(int64_t)(k + col) * n + k + row] = A[col][row];
-            else L[(int64_t)(k + col) * n + k + row] = X[row][col];  // (X^T)(row, col), row < col
-        }
-    }
-    if (tid < b) dinv[f.doff + k + tid] = dv[tid];
     if (tid == 0 && bad >= 0) {
         if (atomicCAS(&err[0], -1, w.x) == -1) err[1] = k + bad;
     }

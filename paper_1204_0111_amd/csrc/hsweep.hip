@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -42,13 +43,20 @@ struct DepthSchedule {
     std::vector<Launch> ldlt, panel, trail;  // one per pivot block
 };
 
+// Right-hand-side groups that are tuned separately: 1, 2, 3-4, 5+ columns.
+constexpr int N_RHS_KEYS = 4;
+inline int rhs_key(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
+
 struct SolveLevel {
-    int64_t foff = 0, boff = 0;
-    int fcount = 0, bcount = 0;
+    // work items of every block shape (plan.hpp) of the two passes
+    int64_t foff[N_FWD_SHAPES] = {}, boff[N_BWD_SHAPES] = {};
+    int fcount[N_FWD_SHAPES] = {}, bcount[N_BWD_SHAPES] = {};
+    int fsel[N_RHS_KEYS] = {}, bsel[N_RHS_KEYS] = {};  // shape in use, per right-hand-side group
     int smax = 0, nmax = 0;
-    int rb = SOLVE_RB, cb = SOLVE_CB;  // forward rows / backward columns per workgroup
     // algorithmic traffic in complex entries: factor part, and per right-hand side
-    double g_entries = 0, fwd_vec = 0, bwd_vec = 0, cmac = 0;
+    // algorithmic traffic: G entries, and bytes per right-hand side of the
+    // vectors each pass reads and writes
+    double g_entries = 0, fwd_vec_bytes = 0, bwd_vec_bytes = 0, cmac = 0;
 };
 
 struct KernelTimer {
@@ -80,7 +88,7 @@ struct hsw_ctx {
     std::vector<ProbHost> ph;
     std::vector<LatTree> trees;
     std::vector<PanelClass> classes;
-    std::vector<int> cls_perm_off, cls_ulist_off, cls_cmap_off;
+    std::vector<int> cls_perm_off, cls_ulist_off, cls_cmap_off, cls_pmap_off;
     std::vector<PanelDev> pan_h;
     std::vector<ProbDev> prob_h;
     std::vector<FrontInst> inst_h;
@@ -91,7 +99,7 @@ struct hsw_ctx {
     int64_t ws_size[2] = {0, 0};
     int64_t L_size = 0, D_size = 0;
     int max_naux = 0;
-    int64_t max_wsize = 0;
+    int64_t max_wsize = 0, max_c2 = 0;
     int64_t et_size = 0;
     std::vector<int64_t> et_prob_off, et_panel_off;
 
@@ -101,14 +109,17 @@ struct hsw_ctx {
     ProbDev* d_prob = nullptr;
     int *d_perm = nullptr, *d_iperm = nullptr, *d_ulist = nullptr, *d_cmap = nullptr;
     int2* d_fwork = nullptr;
-    int* d_swork = nullptr;
+    int* d_pmap = nullptr;
+    SolveItem* d_sitems = nullptr;
     Cx<double>* d_et = nullptr;
     double* d_c = nullptr;
     void *d_L = nullptr, *d_G = nullptr, *d_dinv = nullptr, *d_ws[2] = {nullptr, nullptr};
     int* d_err = nullptr;
     // solve workspace (grown on demand)
     int nrhs_cap = 0;
-    void *d_xin = nullptr, *d_xmid = nullptr, *d_xout = nullptr, *d_wv = nullptr;
+    bool autotune = true;
+    bool tuned[N_RHS_KEYS] = {};
+    void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;
 
     KernelTimer timer;
     bool assembled = false, factored = false;
@@ -170,9 +181,9 @@ static hipError_t dalloc(P** p, size_t bytes) {
 
 static void free_all(hsw_ctx* ctx) {
     void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_iperm, ctx->d_ulist,
-                    ctx->d_cmap, ctx->d_fwork, ctx->d_swork, ctx->d_et, ctx->d_c, ctx->d_L,
-                    ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err, ctx->d_xin,
-                    ctx->d_xmid, ctx->d_xout, ctx->d_wv};
+                    ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
+                    ctx->d_L, ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err,
+                    ctx->d_xmid, ctx->d_xu, ctx->d_c2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -230,16 +241,19 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
         ctx->ph.push_back(h);
     }
     // class arrays, concatenated
-    int po = 0, uo = 0, mo = 0;
+    int po = 0, uo = 0, mo = 0, pmo = 0;
     for (auto& c : ctx->classes) {
         ctx->cls_perm_off.push_back(po);
         ctx->cls_ulist_off.push_back(uo);
         ctx->cls_cmap_off.push_back(mo);
+        ctx->cls_pmap_off.push_back(pmo);
         po += c.naux;
         uo += (int)c.ulist.size();
         mo += (int)c.cmap.size();
+        pmo += (int)c.pmap.size();
         ctx->max_naux = std::max(ctx->max_naux, c.naux);
         ctx->max_wsize = std::max(ctx->max_wsize, c.wsize);
+        ctx->max_c2 = std::max(ctx->max_c2, c.c2size);
         ctx->maxdepth = std::max(ctx->maxdepth, c.maxdepth);
     }
     // front instances
@@ -296,7 +310,7 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
     return HSW_OK;
 }
 
-static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int>& swork) {
+static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<SolveItem>& sitems) {
     const int D = ctx->maxdepth;
     std::vector<std::vector<int>> at(D + 1);
     for (size_t i = 0; i < ctx->inst_h.size(); ++i) at[ctx->inst_h[i].depth].push_back((int)i);
@@ -402,14 +416,37 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
         ctx->slevels[ci].assign(c.maxdepth + 1, SolveLevel{});
         for (int d = 0; d <= c.maxdepth; ++d) {
             SolveLevel& sl = ctx->slevels[ci][d];
-            sl.foff = (int64_t)swork.size();
-            swork.insert(swork.end(), c.fwd_work[d].begin(), c.fwd_work[d].end());
-            sl.fcount = (int)c.fwd_work[d].size() / 2;
-            sl.boff = (int64_t)swork.size();
-            swork.insert(swork.end(), c.bwd_work[d].begin(), c.bwd_work[d].end());
-            sl.bcount = (int)c.bwd_work[d].size() / 2;
-            sl.rb = c.fwd_rb[d];
-            sl.cb = c.bwd_cb[d];
+            auto item = [&](int f, int blk) {
+                SolveItem it{};
+                it.loff = c.loff[f];
+                it.n = c.s[f] + c.u[f];
+                it.s = c.s[f];
+                it.start = c.start[f];
+                it.blk = blk;
+                it.moff = ctx->cls_cmap_off[ci] + c.moff[f];
+                it.c2 = c.c2off[f];
+                const int p = c.parent[f];
+                it.push = p < 0 ? -1 : c.c2off[p] + (c.child0[p] == f ? 0 : c.s[p] + c.u[p]);
+                it.pmap = ctx->cls_pmap_off[ci] + c.pmoff[f];
+                it.xu = c.woff[f];
+                it.cxu0 = c.child0[f] >= 0 ? c.woff[c.child0[f]] : -1;
+                it.cxu1 = c.child1[f] >= 0 ? c.woff[c.child1[f]] : -1;
+                return it;
+            };
+            for (int k = 0; k < N_FWD_SHAPES; ++k) {
+                const int rb = FWD_SHAPES[k].block;
+                sl.foff[k] = (int64_t)sitems.size();
+                for (int f : c.at_depth[d])
+                    for (int blk = 0; blk < c.s[f] + c.u[f]; blk += rb) sitems.push_back(item(f, blk));
+                sl.fcount[k] = (int)(sitems.size() - sl.foff[k]);
+            }
+            for (int k = 0; k < N_BWD_SHAPES; ++k) {
+                const int cb = BWD_SHAPES[k].block;
+                sl.boff[k] = (int64_t)sitems.size();
+                for (int f : c.at_depth[d])
+                    for (int blk = 0; blk < c.s[f]; blk += cb) sitems.push_back(item(f, blk));
+                sl.bcount[k] = (int)(sitems.size() - sl.boff[k]);
+            }
             for (int f : c.at_depth[d]) {
                 sl.smax = std::max(sl.smax, c.s[f]);
                 sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
@@ -417,11 +454,18 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<int
                 double uc = 0;
                 for (int ch : {c.child0[f], c.child1[f]})
                     if (ch >= 0) uc += c.u[ch];
-                sl.g_entries += sd * (sd + 1) / 2 + ud * sd;     // lower G_TL and G_BL
-                sl.fwd_vec += 3 * sd + ud + uc;                  // x_in, 1/D, x_mid, w_U, children's w
-                sl.bwd_vec += 2 * sd + ud;                       // x_mid, x_U gathered, x_S written
+                const double es = ctx->esz;
+                sl.g_entries += sd * (sd + 1) / 2 + ud * sd;  // lower G_TL and G_BL
+                // forward: right-hand side (complex128, deepest use), children's
+                // contributions, 1/D, x_mid and the update part written
+                sl.fwd_vec_bytes += 16 * sd + es * (uc + 3 * sd + ud);
+                // backward: x_mid and x_U read, x_S to the grid (complex128) and
+                // to the children's update-set values
+                sl.bwd_vec_bytes += es * (sd + ud + uc) + 16 * sd;
                 sl.cmac += sd * (sd + 1) / 2 + ud * sd;          // per right-hand side
             }
+            const int dflt = sl.nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
+            for (int key = 0; key < N_RHS_KEYS; ++key) sl.fsel[key] = sl.bsel[key] = dflt;
         }
     }
 }
@@ -441,6 +485,7 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     }
     hsw_ctx* ctx = new hsw_ctx();
     ctx->st = (hipStream_t)stream;
+    if (const char* at = std::getenv("HSW_AUTOTUNE")) ctx->autotune = std::string(at) != "0";
     ctx->prec = prec;
     ctx->esz = prec == HSW_C128 ? 16 : 8;
     ctx->probs.assign(p, p + nprob);
@@ -451,8 +496,8 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
         return s;
     }
     std::vector<int2> fwork;
-    std::vector<int> swork;
-    schedule_all(ctx, fwork, swork);
+    std::vector<SolveItem> sitems;
+    schedule_all(ctx, fwork, sitems);
     // stretch tables: per problem 3 axes, per panel one x3 table
     int64_t eo = 0;
     for (size_t k = 0; k < ctx->ph.size(); ++k) {
@@ -489,12 +534,13 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     int64_t nint_total = 0;
     for (auto& h : ctx->ph) nint_total += h.Nint;
     size_t ints = 0;
-    for (auto& c : ctx->classes) ints += 2 * (size_t)c.naux + c.ulist.size() + c.cmap.size();
+    for (auto& c : ctx->classes)
+        ints += 2 * (size_t)c.naux + c.ulist.size() + c.cmap.size() + c.pmap.size();
     const size_t need = (size_t)ctx->esz * (2 * ctx->L_size + ctx->D_size + ctx->ws_size[0] +
                                              ctx->ws_size[1]) +
                         sizeof(FrontInst) * ctx->inst_h.size() + sizeof(PanelDev) * ctx->pan_h.size() +
                         sizeof(ProbDev) * ctx->prob_h.size() + 4 * ints + 8 * fwork.size() +
-                        4 * swork.size() + 16 * (size_t)eo + 8 * (size_t)nint_total;
+                        sizeof(SolveItem) * sitems.size() + 16 * (size_t)eo + 8 * (size_t)nint_total;
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
         g_create_error = "hipMemGetInfo failed (no device?)";
@@ -524,19 +570,21 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ACHK(dalloc(&ctx->d_inst, sizeof(FrontInst) * ctx->inst_h.size()));
     ACHK(dalloc(&ctx->d_pan, sizeof(PanelDev) * ctx->pan_h.size()));
     ACHK(dalloc(&ctx->d_prob, sizeof(ProbDev) * ctx->prob_h.size()));
-    std::vector<int> perm, iperm, ul, cm;
+    std::vector<int> perm, iperm, ul, cm, pm;
     for (auto& c : ctx->classes) {
         perm.insert(perm.end(), c.perm.begin(), c.perm.end());
         iperm.insert(iperm.end(), c.iperm.begin(), c.iperm.end());
         ul.insert(ul.end(), c.ulist.begin(), c.ulist.end());
         cm.insert(cm.end(), c.cmap.begin(), c.cmap.end());
+        pm.insert(pm.end(), c.pmap.begin(), c.pmap.end());
     }
     ACHK(dalloc(&ctx->d_perm, 4 * perm.size()));
     ACHK(dalloc(&ctx->d_iperm, 4 * iperm.size()));
     ACHK(dalloc(&ctx->d_ulist, 4 * std::max<size_t>(ul.size(), 1)));
     ACHK(dalloc(&ctx->d_cmap, 4 * std::max<size_t>(cm.size(), 1)));
     ACHK(dalloc(&ctx->d_fwork, 8 * std::max<size_t>(fwork.size(), 1)));
-    ACHK(dalloc(&ctx->d_swork, 4 * std::max<size_t>(swork.size(), 1)));
+    ACHK(dalloc(&ctx->d_pmap, 4 * std::max<size_t>(pm.size(), 1)));
+    ACHK(dalloc(&ctx->d_sitems, sizeof(SolveItem) * std::max<size_t>(sitems.size(), 1)));
     ACHK(dalloc(&ctx->d_et, 16 * (size_t)eo));
     ACHK(dalloc(&ctx->d_L, (size_t)ctx->esz * ctx->L_size));
     ACHK(dalloc(&ctx->d_G, (size_t)ctx->esz * ctx->L_size));
@@ -559,8 +607,11 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
         ACHK(hipMemcpyAsync(ctx->d_cmap, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice, st));
     if (!fwork.empty())
         ACHK(hipMemcpyAsync(ctx->d_fwork, fwork.data(), 8 * fwork.size(), hipMemcpyHostToDevice, st));
-    if (!swork.empty())
-        ACHK(hipMemcpyAsync(ctx->d_swork, swork.data(), 4 * swork.size(), hipMemcpyHostToDevice, st));
+    if (!pm.empty())
+        ACHK(hipMemcpyAsync(ctx->d_pmap, pm.data(), 4 * pm.size(), hipMemcpyHostToDevice, st));
+    if (!sitems.empty())
+        ACHK(hipMemcpyAsync(ctx->d_sitems, sitems.data(), sizeof(SolveItem) * sitems.size(),
+                            hipMemcpyHostToDevice, st));
     ACHK(hipStreamSynchronize(st));
 #undef ACHK
     *out = ctx;
@@ -683,50 +734,164 @@ template <typename T>
 static hsw_status ensure_solve_ws(hsw_ctx* ctx, int nrhs) {
     if (nrhs <= ctx->nrhs_cap) return HSW_OK;
     HIPCHK(hipStreamSynchronize(ctx->st));
-    for (void** p : {&ctx->d_xin, &ctx->d_xmid, &ctx->d_xout, &ctx->d_wv}) {
+    for (void** p : {&ctx->d_xmid, &ctx->d_xu, &ctx->d_c2}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
-    const size_t xb = sizeof(Cx<T>) * (size_t)ctx->max_naux * nrhs;
-    const size_t wb = sizeof(Cx<T>) * (size_t)std::max<int64_t>(ctx->max_wsize, 1) * nrhs;
-    HIPCHK(hipMalloc(&ctx->d_xin, xb));
-    HIPCHK(hipMalloc(&ctx->d_xmid, xb));
-    HIPCHK(hipMalloc(&ctx->d_xout, xb));
-    HIPCHK(hipMalloc(&ctx->d_wv, wb));
+    const size_t e = sizeof(Cx<T>) * (size_t)nrhs;
+    HIPCHK(hipMalloc(&ctx->d_xmid, e * (size_t)ctx->max_naux));
+    HIPCHK(hipMalloc(&ctx->d_xu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
+    HIPCHK(hipMalloc(&ctx->d_c2, e * (size_t)std::max<int64_t>(ctx->max_c2, 1)));
     ctx->nrhs_cap = nrhs;
     return HSW_OK;
 }
 
-// y (panel planes of dst) := T_i applied to the gathered right-hand side.
+// T_i applied to a right-hand side read from the padded grid `src` (mode 0:
+// the panel's planes, zero-extended; mode 1: J_{i+1,i}^T of the next plane),
+// the result written to the panel's planes of `dst` (emode 0: stored, and
+// with `couple` also J_{i+1,i} applied to the next plane; emode 1: subtracted).
+// Plane `plane0` of the padded grid sits at offset 0 of src and dst.
+// force_f / force_b >= 0 run every depth with that block shape, and `ev`
+// (two events per launch, forward launches first) times each launch: both
+// serve the autotuner.
 template <typename T>
 static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* src, int64_t ld,
-                         int plane0, int emode, int couple, Cx<double>* dst, int nrhs) {
+                         int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
+                         int force_f = -1, int force_b = -1, hipEvent_t* ev = nullptr) {
     hipStream_t st = ctx->st;
     const PanelDev& P = ctx->pan_h[gpanel];
     const ProbDev& Q = ctx->prob_h[P.prob];
     const PanelClass& c = ctx->classes[P.cls];
-    const int naux = c.naux;
-    const int Wld = (int)std::max<int64_t>(c.wsize, 1);
-    Cx<T>* xin = (Cx<T>*)ctx->d_xin;
-    Cx<T>* xmid = (Cx<T>*)ctx->d_xmid;
-    Cx<T>* xout = (Cx<T>*)ctx->d_xout;
-    Cx<T>* wv = (Cx<T>*)ctx->d_wv;
-    const Cx<T>* G = (const Cx<T>*)ctx->d_G;
-    const Cx<T>* dinv = (const Cx<T>*)ctx->d_dinv;
-    launch_gather<T>(gmode, Q, P, ctx->d_perm, ctx->d_et, src, ld, plane0, nrhs, xin, naux, st);
+    const FrontInst& f0 = ctx->inst_h[P.inst_base];
+    PassArgs<T> A{};
+    A.G = (const Cx<T>*)ctx->d_G + f0.loff;
+    A.dinv = (const Cx<T>*)ctx->d_dinv + f0.doff;
+    A.cmap = ctx->d_cmap;
+    A.pmap = ctx->d_pmap;
+    A.perm = ctx->d_perm + P.perm_off;
+    A.et = ctx->d_et;
+    A.src = src;
+    A.dst = dst;
+    A.ld = ld;
+    A.xmid = (Cx<T>*)ctx->d_xmid;
+    A.c2 = (Cx<T>*)ctx->d_c2;
+    A.xu = (Cx<T>*)ctx->d_xu;
+    A.naux = c.naux;
+    A.c2ld = (int)std::max<int64_t>(c.c2size, 1);
+    A.xuld = (int)std::max<int64_t>(c.wsize, 1);
+    A.nrhs = nrhs;
+    A.couple = couple;
+    A.plane0 = plane0;
+    A.Nx = P.Nx;
+    A.NxNy = P.Nx * P.Ny;
+    A.nz = P.nz;
+    A.ga = P.ga;
+    A.lo = P.lo;
+    A.hi = P.hi;
+    A.e1 = Q.e_off[0];
+    A.e2 = Q.e_off[1];
+    A.ie3hi = Q.e_off[2] + Q.N[2] + P.hi;
+    A.inv_h2 = 1.0 / (Q.h * Q.h);
     const auto& lv = ctx->slevels[P.cls];
     const double es = sizeof(Cx<T>);
-    for (int d = c.maxdepth; d >= 0; --d)
-        timed(ctx, "fwd", lv[d].fcount, es * (lv[d].g_entries + nrhs * lv[d].fwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
-            launch_fwd<T>(ctx->d_swork + lv[d].foff, lv[d].fcount, lv[d].rb, P.inst_base, ctx->d_inst,
-                          G, dinv, ctx->d_cmap, xin, xmid, wv, naux, Wld, nrhs, lv[d].smax, lv[d].nmax, st);
-        });
-    for (int d = 0; d <= c.maxdepth; ++d)
-        timed(ctx, "bwd", lv[d].bcount, es * (lv[d].g_entries + nrhs * lv[d].bwd_vec), 8.0 * nrhs * lv[d].cmac, [&] {
-            launch_bwd<T>(ctx->d_swork + lv[d].boff, lv[d].bcount, lv[d].cb, P.inst_base, ctx->d_inst, G,
-                          ctx->d_ulist, xmid, xout, naux, nrhs, lv[d].nmax, st);
-        });
-    launch_extract<T>(emode, couple, Q, P, ctx->d_iperm, ctx->d_et, xout, naux, dst, ld, plane0, nrhs, st);
+    const int key = rhs_key(nrhs);
+    int li = 0;
+    auto run = [&](const char* cls, int count, double bytes, double flops, auto&& launch) {
+        if (ev) {
+            LaunchTiming& lt = launch_timing();
+            lt.start = ev[2 * li];
+            lt.stop = ev[2 * li + 1];
+            launch();
+            lt.start = lt.stop = nullptr;
+        } else {
+            timed(ctx, cls, count, bytes, flops, launch);
+        }
+        ++li;
+    };
+    A.mode = gmode;
+    for (int d = c.maxdepth; d >= 0; --d) {
+        const int k = force_f >= 0 ? force_f : lv[d].fsel[key];
+        A.items = ctx->d_sitems + lv[d].foff[k];
+        run("fwd", lv[d].fcount[k], es * lv[d].g_entries + nrhs * lv[d].fwd_vec_bytes,
+            8.0 * nrhs * lv[d].cmac,
+            [&] { launch_fwd<T>(A, lv[d].fcount[k], k, lv[d].smax, lv[d].nmax, st); });
+    }
+    A.mode = emode;
+    for (int d = 0; d <= c.maxdepth; ++d) {
+        const int k = force_b >= 0 ? force_b : lv[d].bsel[key];
+        A.items = ctx->d_sitems + lv[d].boff[k];
+        run("bwd", lv[d].bcount[k], es * lv[d].g_entries + nrhs * lv[d].bwd_vec_bytes,
+            8.0 * nrhs * lv[d].cmac,
+            [&] { launch_bwd<T>(A, lv[d].bcount[k], k, lv[d].nmax, st); });
+    }
+}
+
+// Autotuner of the solve passes: for every panel class and tree depth, time
+// each block shape of the forward and the backward pass inside whole panel
+// solves (cycling over the class's panels, so the factors are not cache
+// resident more than in a sweep) and keep the fastest, per right-hand-side
+// group.  Runs once per group, at the first solve after a setup; the plan
+// and the factors' values do not affect the choice.
+template <typename T>
+static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
+    const int key = rhs_key(nrhs);
+    if (!ctx->autotune || ctx->tuned[key]) return HSW_OK;
+    constexpr int REPS = 3;
+    const int NS = std::max(N_FWD_SHAPES, N_BWD_SHAPES);
+    int64_t plen = 1;
+    for (const PanelDev& P : ctx->pan_h) plen = std::max<int64_t>(plen, (int64_t)(P.hi - P.lo) * P.Nx * P.Ny);
+    Cx<double>* v = nullptr;
+    const int nl = 2 * (ctx->maxdepth + 1);
+    std::vector<hipEvent_t> ev(2 * nl, nullptr);
+    hsw_status status = HSW_OK;
+    auto cleanup = [&] {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (v) (void)hipFree(v);
+    };
+#define TCHK(expr)                                                                       do {                                                                                     hipError_t e_ = (expr);                                                              if (e_ != hipSuccess) {                                                                  ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                        cleanup();                                                                           return HSW_E_DEVICE;                                                             }                                                                                } while (0)
+    TCHK(hipMalloc(&v, 16 * (size_t)plen * nrhs));
+    TCHK(hipMemsetAsync(v, 0, 16 * (size_t)plen * nrhs, ctx->st));
+    for (hipEvent_t& e : ev) TCHK(hipEventCreate(&e));
+    for (size_t ci = 0; ci < ctx->classes.size(); ++ci) {
+        const PanelClass& c = ctx->classes[ci];
+        std::vector<int> panels;
+        for (size_t g = 0; g < ctx->pan_h.size(); ++g)
+            if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
+        const int D = c.maxdepth;
+        std::vector<std::vector<float>> tf(D + 1, std::vector<float>(N_FWD_SHAPES, 1e30f));
+        std::vector<std::vector<float>> tb(D + 1, std::vector<float>(N_BWD_SHAPES, 1e30f));
+        int run = 0;
+        for (int rep = 0; rep < REPS; ++rep)
+            for (int k = 0; k < NS; ++k, ++run) {
+                const int gp = panels[run % panels.size()];
+                const int kf = k % N_FWD_SHAPES, kb = k % N_BWD_SHAPES;
+                const PanelDev& P = ctx->pan_h[gp];
+                panel_tsolve<T>(ctx, gp, 0, v, plen, P.lo, 0, 0, v, nrhs, kf, kb, ev.data());
+                TCHK(hipGetLastError());
+                TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
+                for (int l = 0; l < 2 * (D + 1); ++l) {
+                    float ms = 0;
+                    TCHK(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
+                    if (l <= D) {
+                        const int d = D - l;
+                        tf[d][kf] = std::min(tf[d][kf], ms);
+                    } else {
+                        const int d = l - (D + 1);
+                        tb[d][kb] = std::min(tb[d][kb], ms);
+                    }
+                }
+            }
+        for (int d = 0; d <= D; ++d) {
+            SolveLevel& sl = ctx->slevels[ci][d];
+            sl.fsel[key] = (int)(std::min_element(tf[d].begin(), tf[d].end()) - tf[d].begin());
+            sl.bsel[key] = (int)(std::min_element(tb[d].begin(), tb[d].end()) - tb[d].begin());
+        }
+    }
+#undef TCHK
+    cleanup();
+    ctx->tuned[key] = true;
+    return status;
 }
 
 // z := M^{-1} r (Alg. 1.5), r may equal z.
@@ -734,6 +899,7 @@ template <typename T>
 static hsw_status sweep_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
                              int64_t ld) {
     hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+    if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
     if (s != HSW_OK) return s;
     const ProbHost& h = ctx->ph[prob];
     if (r != z)

@@ -50,21 +50,9 @@ void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx
 
 // solve.hip
 template <typename T>
-void launch_gather(int mode, const ProbDev& Q, const PanelDev& P, const int* perm,
-                   const Cx<double>* et, const Cx<double>* u, int64_t ld, int plane0, int nrhs,
-                   Cx<T>* xin, int naux, hipStream_t st);
+void launch_fwd(const PassArgs<T>& A, int nwork, int rb, int smax, int nmax, hipStream_t st);
 template <typename T>
-void launch_extract(int mode, int couple, const ProbDev& Q, const PanelDev& P, const int* iperm,
-                    const Cx<double>* et, const Cx<T>* xout, int naux, Cx<double>* u, int64_t ld,
-                    int plane0, int nrhs, hipStream_t st);
-template <typename T>
-void launch_fwd(const int* work, int nwork, int rb, int inst_base, const FrontInst* inst, const Cx<T>* G,
-                const Cx<T>* dinv, const int* cmap, const Cx<T>* xin, Cx<T>* xmid, Cx<T>* wv,
-                int naux, int Wld, int nrhs, int smax, int nmax, hipStream_t st);
-template <typename T>
-void launch_bwd(const int* work, int nwork, int cb, int inst_base, const FrontInst* inst, const Cx<T>* G,
-                const int* ulist, const Cx<T>* xmid, Cx<T>* xout, int naux, int nrhs, int nmax,
-                hipStream_t st);
+void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t st);
 template <typename T>
 int solve_rhs_chunk(int nrhs, int nmax);
 

@@ -140,6 +140,34 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
             if (found != uc) return "child update set not contained in parent front";
         }
     }
+    // push form of the maps: each update entry's position in the parent front,
+    // and the slots a parent keeps for its two children's contributions
+    pc.pmoff.resize(nf);
+    pc.c2off.resize(nf);
+    pc.c2size = 0;
+    for (int k = 0; k < nf; ++k) {
+        pc.c2off[k] = (int)pc.c2size;
+        pc.c2size += 2 * (int64_t)(pc.s[k] + pc.u[k]);
+        pc.pmoff[k] = (int)pc.pmap.size();
+        const int p = pc.parent[k];
+        if (p < 0) {
+            if (pc.u[k] != 0) return "root front with a nonempty update set";
+            continue;
+        }
+        const int* Up = pc.ulist.data() + pc.uoff[p];
+        for (int j = 0; j < pc.u[k]; ++j) {
+            const int e = pc.ulist[pc.uoff[k] + j];
+            int local;
+            if (e >= pc.start[p] && e < pc.start[p] + pc.s[p]) {
+                local = e - pc.start[p];
+            } else {
+                const int* it = std::lower_bound(Up, Up + pc.u[p], e);
+                if (it == Up + pc.u[p] || *it != e) return "update entry missing from the parent front";
+                local = pc.s[p] + (int)(it - Up);
+            }
+            pc.pmap.push_back(local);
+        }
+    }
     // storage offsets and work counts
     pc.loff.resize(nf);
     pc.woff.resize(nf);
@@ -156,30 +184,6 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
         pc.factor_cmac += s * s * s / 6 + s * s * u / 2 + s * u * u / 2;
         pc.inverse_cmac += s * s * s / 6 + u * s * s / 2;
         pc.solve_cmac += s * s + 2 * s * u;
-    }
-    pc.fwd_work.assign(pc.maxdepth + 1, {});
-    pc.bwd_work.assign(pc.maxdepth + 1, {});
-    pc.fwd_rb.assign(pc.maxdepth + 1, SOLVE_RB);
-    pc.bwd_cb.assign(pc.maxdepth + 1, SOLVE_CB);
-    for (int d = 0; d <= pc.maxdepth; ++d) {
-        int nmax = 0;
-        for (int k : pc.at_depth[d]) nmax = std::max(nmax, pc.s[k] + pc.u[k]);
-        if (nmax >= SOLVE_SMALL_BLOCK_N) {
-            pc.fwd_rb[d] = SOLVE_RB_SMALL;
-            pc.bwd_cb[d] = SOLVE_CB_SMALL;
-        }
-        const int rb = pc.fwd_rb[d], cb = pc.bwd_cb[d];
-        for (int k : pc.at_depth[d]) {
-            int n = pc.s[k] + pc.u[k];
-            for (int b = 0; b < (n + rb - 1) / rb; ++b) {
-                pc.fwd_work[d].push_back(k);
-                pc.fwd_work[d].push_back(b);
-            }
-            for (int b = 0; b < (pc.s[k] + cb - 1) / cb; ++b) {
-                pc.bwd_work[d].push_back(k);
-                pc.bwd_work[d].push_back(b);
-            }
-        }
     }
     return "";
 }

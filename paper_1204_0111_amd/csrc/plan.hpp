@@ -21,13 +21,18 @@ namespace hsw {
 
 constexpr int TILE = 64;        // square tile of the front kernels
 constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
-constexpr int SOLVE_RB = 64;    // rows per workgroup in the forward solve
-constexpr int SOLVE_CB = 32;    // columns per workgroup in the backward solve
-// Depths whose largest front has at least this many rows use 16-row forward
-// blocks and 8-column backward blocks, spreading few large fronts over more CUs.
+// Block shapes of the solve passes: rows (forward) or columns (backward) per
+// workgroup and threads per workgroup.  Each tree depth of each panel class
+// uses one shape per pass, picked by timing (autotuning) or by the default
+// rule: the first shape for depths whose largest front has fewer than
+// SOLVE_SMALL_BLOCK_N rows, the second otherwise.
+struct PassShape {
+    int block, threads;
+};
+constexpr int N_FWD_SHAPES = 5, N_BWD_SHAPES = 6;
+constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512}, {16, 512}, {32, 256}};
+constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256}};
 constexpr int SOLVE_SMALL_BLOCK_N = 512;
-constexpr int SOLVE_RB_SMALL = 16;
-constexpr int SOLVE_CB_SMALL = 8;
 
 struct LatNode {
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
@@ -55,15 +60,14 @@ struct PanelClass {
     std::vector<int> start, s, u, parent, child0, child1, depth;
     std::vector<int> uoff, ulist;  // update sets, concatenated (elimination positions)
     std::vector<int> moff, cmap;   // per front 2 (s+u) entries: position in child 0 / 1 update set or -1
+    std::vector<int> pmoff, pmap;  // per front u entries: position of each update entry in the parent front
+    std::vector<int> c2off;        // per front: offset of its 2 (s+u) child-contribution slots
+    int64_t c2size = 0;            // sum 2 (s+u)
     std::vector<int64_t> loff;     // per front: offset of its (s+u) x s block, relative to the panel
     std::vector<int> woff;         // per front: offset of its update vector (u entries per rhs)
     int64_t lsize = 0;             // sum (s+u) s
     int64_t wsize = 0;             // sum u
     std::vector<std::vector<int>> at_depth;
-    // per-depth work lists of the solves: (front, block) pairs, and the block
-    // size (rows of the forward pass, columns of the backward pass) per depth
-    std::vector<std::vector<int>> fwd_work, bwd_work;
-    std::vector<int> fwd_rb, bwd_cb;
     double factor_cmac = 0, inverse_cmac = 0, solve_cmac = 0;  // per panel, per rhs for solves
 };
 
