@@ -11,6 +11,8 @@
 // column-major block (leading dimension s+u); F_BR (u x u, column-major)
 // lives in a workspace indexed by the parity of the depth, kept until the
 // parent has pulled it (extend-add) one level up.
+#include <utility>
+
 #include "devtypes.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -178,105 +180,262 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal block [k, k+b) of the blocked partial LDL^T: one workgroup per
-// front factors the b x b block (unpivoted, transposes only) and inverts the
-// unit lower factor.  It writes L_kk below the diagonal, the pivots D_kk on
-// it and L_kk^{-1} transposed in the (otherwise unused) strict upper
-// triangle of the block, plus the reciprocal pivots.  A zero or non-finite
-// pivot is reported.
-//
-// Register-blocked: thread t owns rows 4(t%16).. and columns 4(t/16).. of
-// the 64 x 64 block and of X = L_kk^{-1}.  Step m broadcasts column m of
-// the partially eliminated block (its pivot d_m and the unscaled entries
-// a_im) and row m of X, which is final by then; every thread then applies
-// A(i,j) -= a_im a_jm / d_m for i >= j > m and X(i,c) -= (a_im / d_m) X(m,c)
-// for i > m >= c to its own tile.  Two LDS buffers alternate, so a step
-// needs one barrier.
+// 16 x 16 complex tile product on the matrix cores, acc += A B over k < K
+// (K <= 16): lane l supplies A(l % 16, k) and B(k, l % 16) for k = kk + l / 16;
+// register r of lane l then holds row mfma_out_row<T>(l / 16, r), column l % 16.
+template <typename T, typename GA, typename GB>
+__device__ inline void cmma16(typename MfmaAcc<T>::type& are, typename MfmaAcc<T>::type& aim, int K,
+                              GA getA, GB getB) {
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, kq = l >> 4;
+    for (int kk = 0; kk < K; kk += 4) {
+        const int kx = kk + kq;
+        const Cx<T> a = kx < K ? getA(i, kx) : cx<T>(0, 0);
+        const Cx<T> b = kx < K ? getB(kx, i) : cx<T>(0, 0);
+        are = mfma4(a.re, b.re, are);
+        are = mfma4(-a.im, b.im, are);
+        aim = mfma4(a.re, b.im, aim);
+        aim = mfma4(a.im, b.re, aim);
+    }
+}
+
+template <typename T>
+__device__ inline Cx<T> shfl_cx(Cx<T> v, int src) {
+    return cx<T>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
+}
+
+// Reciprocal of a pivot: a power-of-two prescale keeps |b|^2 in range; in
+// FP32 the hardware reciprocal (about one ulp) replaces the division.
+__device__ inline Cx<float> pivot_recip(Cx<float> b) {
+    const int e = __builtin_amdgcn_frexp_expf(fmaxf(fabsf(b.re), fabsf(b.im)));
+    const float br = ldexpf(b.re, -e), bi = ldexpf(b.im, -e);
+    const float r = __builtin_amdgcn_rcpf(br * br + bi * bi);
+    return cx<float>(ldexpf(br * r, -e), ldexpf(-bi * r, -e));
+}
+__device__ inline Cx<double> pivot_recip(Cx<double> b) { return crecip(b); }
+
+// Step m of the 16 x 16 sub-block factorisation (see diag16); m is a
+// template parameter so that every register index is static.
+template <int m, typename T>
+__device__ inline void diag16_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, int l, int c0, int w,
+                                   Cx<T>* dv, Cx<T>* __restrict__ dinv, int& first_bad) {
+    constexpr int src = 16 * (m & 3);  // lanes holding column m: l / 16 == m % 4, register m / 4
+    const Cx<T> d = shfl_cx(a[m >> 2], m + src);
+    const Cx<T> idm = pivot_recip(d);
+    const Cx<T> aim = shfl_cx(a[m >> 2], i + src);
+    const Cx<T> li = aim * idm;
+    const bool below = i > m;
+    // every operand is read before any register of this step changes: the
+    // lanes holding column m overwrite it with l_im below
+    Cx<T> ajm[4], xm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ajm[q] = shfl_cx(a[m >> 2], jg + 4 * q + src);  // A(j, m)
+        xm[q] = shfl_cx(x[q], m + 16 * jg);             // X(m, j), final at step m
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        Cx<T> na = a[q], nx = x[q];
+        cfms(na, li, ajm[q]);
+        cfms(nx, li, xm[q]);
+        const bool ua = below && j > m && j <= i, ux = below && j <= m;
+        a[q] = ua ? na : a[q];
+        x[q] = ux ? nx : x[q];
+        a[q] = (below && j == m) ? li : a[q];
+    }
+    if (l == 0 && m < w) {
+        dv[c0 + m] = d;
+        dinv[c0 + m] = idm;
+        const bool finite = isfinite(d.re) && isfinite(d.im) && isfinite(idm.re) && isfinite(idm.im);
+        if ((!finite || (d.re == 0 && d.im == 0)) && first_bad < 0) first_bad = c0 + m;
+    }
+}
+
+template <typename T, int... M>
+__device__ inline void diag16_steps(std::integer_sequence<int, M...>, Cx<T> (&a)[4], Cx<T> (&x)[4], int i,
+                                    int jg, int l, int c0, int w, Cx<T>* dv, Cx<T>* __restrict__ dinv,
+                                    int& first_bad) {
+    (diag16_step<M, T>(a, x, i, jg, l, c0, w, dv, dinv, first_bad), ...);
+}
+
+// One wave factors the 16 x 16 diagonal sub-block at c0 (w <= 16 valid
+// columns; the rest is padded with the identity) and inverts its unit lower
+// factor.  Lane l holds rows i = l % 16 at columns j = l / 16 + 4q of the
+// block and of X; the 16 steps are unrolled and free of branches.
+template <typename T>
+__device__ inline void diag16(T (*Mre)[LDP], T (*Mim)[LDP], Cx<T>* dv, Cx<T>* __restrict__ dinv,
+                              int c0, int w, int* bad) {
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, jg = l >> 4;
+    Cx<T> a[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        const T one = i == j ? (T)1 : (T)0;
+        a[q] = (i >= j && i < w) ? cx<T>(Mre[c0 + j][c0 + i], Mim[c0 + j][c0 + i]) : cx<T>(one, 0);
+        x[q] = cx<T>(one, 0);
+    }
+    int first_bad = -1;
+    diag16_steps<T>(std::make_integer_sequence<int, 16>{}, a, x, i, jg, l, c0, w, dv, dinv, first_bad);
+    if (l == 0 && first_bad >= 0 && *bad < 0) *bad = first_bad;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        if (i < w && j < w && i >= j) {
+            Mre[c0 + j][c0 + i] = a[q].re;
+            Mim[c0 + j][c0 + i] = a[q].im;
+        }
+        if (i < w && j < w && i > j) {  // X(i, j) in the upper triangle: row j, column i
+            Mre[c0 + i][c0 + j] = x[q].re;
+            Mim[c0 + i][c0 + j] = x[q].im;
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work,
                                                    const FrontInst* __restrict__ inst,
                                                    Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ dinv,
                                                    int k, int* __restrict__ err) {
+    typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff + (int64_t)k * n + k;  // block origin, leading dimension n
-    __shared__ Cx<T> colb[2][NB];  // column m of the eliminated block
-    __shared__ Cx<T> rowb[2][NB];  // row m of X
+    __shared__ T Mre[NB][LDP], Mim[NB][LDP];      // M[col][row]
+    __shared__ T Tre[4][16][17], Tim[4][16][17];  // per-wave 16 x 16 scratch
+    __shared__ Cx<T> dv[NB];
     __shared__ int bad;
     const int tid = threadIdx.x;
-    const int R0 = 4 * (tid & 15), C0 = 4 * (tid >> 4);
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     if (tid == 0) bad = -1;
-    Cx<T> A[4][4], X[4][4];
+    constexpr int LB = sizeof(T) == 4 ? 16 : 8;  // loads in flight per thread
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int q0 = 0; q0 < NB * NB / 256; q0 += LB) {
+        Cx<T> v[LB];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = R0 + r, j = C0 + c;
-            A[r][c] = (i < b && j < b && i >= j) ? L[(int64_t)j * n + i] : cx<T>(0, 0);
-            X[r][c] = cx<T>(i == j ? (T)1 : (T)0, 0);
-        }
-    for (int m = 0; m < b; ++m) {
-        const int p = m & 1;
-        if (C0 <= m && m < C0 + 4) {  // owners of column m
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (C0 + c == m) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) colb[p][R0 + r] = A[r][c];
-                }
-        }
-        if (R0 <= m && m < R0 + 4) {  // owners of row m of X
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (R0 + r == m) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) rowb[p][C0 + c] = X[r][c];
-                }
-        }
-        __syncthreads();
-        const Cx<T> dm = colb[p][m];
-        const Cx<T> idm = crecip(dm);
-        if (tid == 0) {
-            dinv[f.doff + k + m] = idm;
-            const bool finite = isfinite(dm.re) && isfinite(dm.im) && isfinite(idm.re) && isfinite(idm.im);
-            if ((!finite || (dm.re == 0 && dm.im == 0)) && bad < 0) bad = m;
-        }
-        if (R0 + 3 <= m) continue;  // every row of this tile is eliminated already
-        Cx<T> ai[4], lj[4], xr[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) ai[r] = colb[p][R0 + r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            lj[c] = colb[p][C0 + c] * idm;
-            xr[c] = rowb[p][C0 + c];
+        for (int q = 0; q < LB; ++q) {
+            const int idx = tid + 256 * (q0 + q), row = idx & (NB - 1), col = idx / NB;
+            const bool in = row < b && col < b && row >= col;
+            v[q] = L[in ? (int64_t)col * n + row : 0];
+            if (!in) v[q] = cx<T>(0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = R0 + r;
-            if (i <= m) continue;
-            const Cx<T> li = ai[r] * idm;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int j = C0 + c;
-                if (j > m && j <= i) cfms(A[r][c], ai[r], lj[c]);
-                if (j <= m) cfms(X[r][c], li, xr[c]);
-                if (j == m) A[r][c] = li;  // column m is final: store l_im
-            }
+        for (int q = 0; q < LB; ++q) {
+            const int idx = tid + 256 * (q0 + q), row = idx & (NB - 1), col = idx / NB;
+            Mre[col][row] = v[q].re;
+            Mim[col][row] = v[q].im;
         }
     }
     __syncthreads();
-    // L_kk and D_kk on and below the diagonal; X = L_kk^{-1} transposed above:
-    // block entry (c, i) with c < i holds X(i, c)
+    const int nJ = (b + 15) / 16;
+    for (int J = 0; J < nJ; ++J) {
+        const int c0 = 16 * J, wj = min(16, b - c0);
+        if (wave == 0) diag16<T>(Mre, Mim, dv, dinv + f.doff + k, c0, wj, &bad);
+        __syncthreads();
+        const int r0 = c0 + wj, nr = b - r0;
+        if (nr <= 0) continue;
+        const int nt = (nr + 15) / 16;
+        // rows below: L(r, c0+j) = dinv_j sum_m A(r, c0+m) X_JJ(j, m)
+        for (int t = wave; t < nt; t += 4) {
+            const int rt = r0 + 16 * t;
+            V4 are = V4{0, 0, 0, 0}, aim = V4{0, 0, 0, 0};
+            cmma16<T>(are, aim, wj,
+                      [&](int ii, int m) { return rt + ii < b ? cx<T>(Mre[c0 + m][rt + ii], Mim[c0 + m][rt + ii]) : cx<T>(0, 0); },
+                      [&](int m, int j) {
+                          if (j >= wj || m > j) return cx<T>(0, 0);
+                          if (m == j) return cx<T>(1, 0);
+                          return cx<T>(Mre[c0 + j][c0 + m], Mim[c0 + j][c0 + m]);
+                      });
+            // all lanes have read their operands before any lane of the wave writes
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = R0 + r, j = C0 + c;
-            if (i < b && j < b && i >= j) L[(int64_t)j * n + i] = A[r][c];
-            if (i < b && j < b && i > j) L[(int64_t)i * n + j] = X[r][c];
+            for (int r = 0; r < 4; ++r) {
+                const int ii = mfma_out_row<T>(lk, r), j = li;
+                if (rt + ii < b && j < wj) {
+                    const Cx<T> v = cx<T>(are[r], aim[r]) * pivot_recip(dv[c0 + j]);
+                    Mre[c0 + j][rt + ii] = v.re;
+                    Mim[c0 + j][rt + ii] = v.im;
+                }
+            }
         }
+        __syncthreads();
+        // trailing lower tiles: A(i, j) -= sum_m L(i, c0+m) d_m L(j, c0+m)
+        for (int t = wave; t < nt * (nt + 1) / 2; t += 4) {
+            int ti, tj;
+            tri_decode_dev(t, ti, tj);
+            const int ri = r0 + 16 * ti, cj = r0 + 16 * tj;
+            V4 are = V4{0, 0, 0, 0}, aim = V4{0, 0, 0, 0};
+            cmma16<T>(are, aim, wj,
+                      [&](int ii, int m) { return ri + ii < b ? cx<T>(Mre[c0 + m][ri + ii], Mim[c0 + m][ri + ii]) : cx<T>(0, 0); },
+                      [&](int m, int j) {
+                          return cj + j < b ? cx<T>(Mre[c0 + m][cj + j], Mim[c0 + m][cj + j]) * dv[c0 + m] : cx<T>(0, 0);
+                      });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = ri + mfma_out_row<T>(lk, r), gj = cj + li;
+                if (gi < b && gj < b && gi >= gj) {
+                    Mre[gj][gi] -= are[r];
+                    Mim[gj][gi] -= aim[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // off-diagonal blocks of X = L^{-1}; X(r, c) with r > c lives at M[r][c]
+    for (int I = 1; I < nJ; ++I) {
+        const int i0 = 16 * I;
+        for (int J = wave; J < I; J += 4) {
+            const int j0 = 16 * J;
+            V4 tre = V4{0, 0, 0, 0}, tim = V4{0, 0, 0, 0};
+            for (int K = J; K < I; ++K) {
+                const int k0 = 16 * K;
+                cmma16<T>(tre, tim, 16,
+                          [&](int ii, int kk) {  // L(i0+ii, k0+kk)
+                              return i0 + ii < b && k0 + kk < b ? cx<T>(Mre[k0 + kk][i0 + ii], Mim[k0 + kk][i0 + ii]) : cx<T>(0, 0);
+                          },
+                          [&](int kk, int j) {  // X(k0+kk, j0+j)
+                              const int r = k0 + kk, c = j0 + j;
+                              if (r >= b || c >= b || r < c) return cx<T>(0, 0);
+                              if (r == c) return cx<T>(1, 0);
+                              return cx<T>(Mre[r][c], Mim[r][c]);
+                          });
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Tre[wave][mfma_out_row<T>(lk, r)][li] = tre[r];
+                Tim[wave][mfma_out_row<T>(lk, r)][li] = tim[r];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            V4 xre = V4{0, 0, 0, 0}, xim = V4{0, 0, 0, 0};
+            cmma16<T>(xre, xim, 16,
+                      [&](int ii, int kk) {  // X(i0+ii, i0+kk)
+                          const int r = i0 + ii, c = i0 + kk;
+                          if (r >= b || c >= b || r < c) return cx<T>(0, 0);
+                          if (r == c) return cx<T>(1, 0);
+                          return cx<T>(Mre[r][c], Mim[r][c]);
+                      },
+                      [&](int kk, int j) { return cx<T>(Tre[wave][kk][j], Tim[wave][kk][j]); });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = i0 + mfma_out_row<T>(lk, r), gc = j0 + li;
+                if (gr < b && gc < b) {
+                    Mre[gr][gc] = -xre[r];
+                    Mim[gr][gc] = -xim[r];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int row = idx & (NB - 1), col = idx / NB;
+        if (row < b && col < b) L[(int64_t)col * n + row] = cx<T>(Mre[col][row], Mim[col][row]);
+    }
     if (tid == 0 && bad >= 0) {
         if (atomicCAS(&err[0], -1, w.x) == -1) err[1] = k + bad;
     }
