@@ -179,6 +179,51 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
     }
 }
 
+// acc += R C^T over k < K for a 64 x 64 tile, R and C read from memory by
+// ldR(k, row) and ldC(k, col) in chunks of KC columns.  Software pipelined:
+// the loads of chunk c + 1 are in flight while chunk c runs on the matrix
+// cores from one of two LDS buffers, so one barrier per chunk suffices.
+// Ends with a barrier; the caller's LDS buffers are free afterwards.
+template <typename T, int KC, typename LR, typename LC>
+__device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
+                                    typename MfmaAcc<T>::type (&aim)[2][2], int K, LR ldR, LC ldC,
+                                    T (*Rre)[KC][LDP], T (*Rim)[KC][LDP], T (*Cre)[KC][LDP],
+                                    T (*Cim)[KC][LDP]) {
+    constexpr int PER = KC * 64 / 256;
+    const int tid = threadIdx.x;
+    const int nch = (K + KC - 1) / KC;
+    if (nch <= 0) return;
+    Cx<T> r[PER], c[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q, a = idx & 63, kk = k0 + (idx >> 6);
+            r[q] = kk < K ? ldR(kk, a) : cx<T>(0, 0);
+            c[q] = kk < K ? ldC(kk, a) : cx<T>(0, 0);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q, a = idx & 63, m = idx >> 6;
+            Rre[buf][m][a] = r[q].re;
+            Rim[buf][m][a] = r[q].im;
+            Cre[buf][m][a] = c[q].re;
+            Cim[buf][m][a] = c[q].im;
+        }
+    };
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) fetch((ch + 1) * KC);
+        tile_cgemm<T, KC>(are, aim, Rre[buf], Rim[buf], Cre[buf], Cim[buf], K - ch * KC);
+        if (ch + 1 < nch) put(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 16 x 16 complex tile product on the matrix cores, acc += A B over k < K
 // (K <= 16): lane l supplies A(l % 16, k) and B(k, l % 16) for k = kk + l / 16;
@@ -456,11 +501,9 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
     const int n = f.s + f.u;
     const int b = min(NB, f.s - k);
     Cx<T>* L = Lb + f.loff;
-    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
-    __shared__ Cx<T> dv[NB];
+    __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
     const int tid = threadIdx.x;
     const int rbeg = k + b + w.y * 64, rend = min(rbeg + 64, n);
-    if (tid < b) dv[tid] = dinv[f.doff + k + tid];
     V4 are[2][2], aim[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -469,28 +512,16 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
-    for (int kc = 0; kc < b; kc += KC) {
-        __syncthreads();
-        for (int idx = tid; idx < KC * 64; idx += 256) {
-            const int a = idx & 63, m = idx / 64;
-            const int mm = kc + m;
-            Cx<T> pv = cx<T>(0, 0), lv = cx<T>(0, 0);
-            if (mm < b) {
-                if (rbeg + a < rend) pv = L[(int64_t)(k + mm) * n + rbeg + a];
-                // L_kk^{-1}(a, mm): 1 on the diagonal, stored at L(k+mm, k+a) when mm < a
-                if (a < b) {
-                    if (mm < a) lv = L[(int64_t)(k + a) * n + k + mm];
-                    else if (mm == a) lv = cx<T>(1, 0);
-                }
-            }
-            Rre[m][a] = pv.re;
-            Rim[m][a] = pv.im;
-            Cre[m][a] = lv.re;
-            Cim[m][a] = lv.im;
-        }
-        __syncthreads();
-        tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, b - kc);
-    }
+    cgemm64_pipe<T, KC>(
+        are, aim, b,
+        [&](int m, int a) { return rbeg + a < rend ? L[(int64_t)(k + m) * n + rbeg + a] : cx<T>(0, 0); },
+        [&](int m, int a) {
+            // L_kk^{-1}(a, m): 1 on the diagonal, stored at L(k + m, k + a) when m < a
+            if (a >= b || m > a) return cx<T>(0, 0);
+            if (m == a) return cx<T>(1, 0);
+            return L[(int64_t)(k + a) * n + k + m];
+        },
+        Rre, Rim, Cre, Cim);
     const int l = tid & 63, wv = tid >> 6;
     const int li = l & 15, lk = l >> 4;
 #pragma unroll
@@ -502,7 +533,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
                 const int row = rbeg + (wv & 1) * 32 + 16 * bi + li;
                 const int j = (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
                 if (row < rend && j < b)
-                    L[(int64_t)(k + j) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]) * dv[j];
+                    L[(int64_t)(k + j) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]) * dinv[f.doff + k + j];
             }
 }
 
@@ -540,9 +571,23 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
     const int r0 = t0 + ti * TILE, c0 = t0 + tj * TILE;
     Cx<T>* L = Lb + f.loff;
     Cx<T>* W = Wcur + f.woff;
-    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
+    __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
     __shared__ Cx<T> dd[NB];
     const int tid = threadIdx.x;
+    const int l = tid & 63, wv = tid >> 6;
+    const int li = l & 15, lk = l >> 4;
+    // the output tile's current values, fetched while the product runs
+    Cx<T> old[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + (wv & 1) * 32 + 16 * bi + li;
+                const int j = c0 + (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
+                old[bi][bj][r] = (i < n && j < n && i >= j) ? *front_at(L, W, n, f.s, f.u, i, j) : cx<T>(0, 0);
+            }
     if (tid < b) dd[tid] = L[(int64_t)(k + tid) * n + k + tid];
     V4 are[2][2], aim[2][2];
 #pragma unroll
@@ -553,31 +598,12 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
     __syncthreads();
-    for (int kc = 0; kc < b; kc += KC) {
-        for (int idx = tid; idx < KC * TILE; idx += 256) {
-            const int l = idx & 63, m = idx / 64;
-            const int km = kc + m;
-            Cx<T> xr = cx<T>(0, 0), xc = cx<T>(0, 0);
-            if (km < b) {
-                const Cx<T>* col = L + (int64_t)(k + km) * n;
-                if (r0 + l < n) xr = col[r0 + l];
-                if (c0 + l < n) xc = col[c0 + l] * dd[km];
-            }
-            if (bf16) {
-                xr = cx<T>(round_bf16(xr.re), round_bf16(xr.im));
-                xc = cx<T>(round_bf16(xc.re), round_bf16(xc.im));
-            }
-            Rre[m][l] = xr.re;
-            Rim[m][l] = xr.im;
-            Cre[m][l] = xc.re;
-            Cim[m][l] = xc.im;
-        }
-        __syncthreads();
-        tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, b - kc);
-        __syncthreads();
-    }
-    const int l = tid & 63, wv = tid >> 6;
-    const int li = l & 15, lk = l >> 4;
+    auto rnd = [&](Cx<T> v) { return bf16 ? cx<T>(round_bf16(v.re), round_bf16(v.im)) : v; };
+    cgemm64_pipe<T, KC>(
+        are, aim, b,
+        [&](int m, int a) { return r0 + a < n ? rnd(L[(int64_t)(k + m) * n + r0 + a]) : cx<T>(0, 0); },
+        [&](int m, int a) { return c0 + a < n ? rnd(L[(int64_t)(k + m) * n + c0 + a] * dd[m]) : cx<T>(0, 0); },
+        Rre, Rim, Cre, Cim);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -586,10 +612,8 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
             for (int r = 0; r < 4; ++r) {
                 const int i = r0 + (wv & 1) * 32 + 16 * bi + li;
                 const int j = c0 + (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
-                if (i < n && j < n && i >= j) {
-                    Cx<T>* p = front_at(L, W, n, f.s, f.u, i, j);
-                    *p = *p - cx<T>(are[bi][bj][r], aim[bi][bj][r]);
-                }
+                if (i < n && j < n && i >= j)
+                    *front_at(L, W, n, f.s, f.u, i, j) = old[bi][bj][r] - cx<T>(are[bi][bj][r], aim[bi][bj][r]);
             }
 }
 
@@ -616,11 +640,12 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
     const int tid = threadIdx.x;
     const int l = tid & 63, wv = tid >> 6;
     const int li = l & 15, lk = l >> 4;
-    __shared__ T Rre[KC][LDP], Rim[KC][LDP], Cre[KC][LDP], Cim[KC][LDP];
+    __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
     __shared__ T Are[64][LDP], Aim[64][LDP];  // the block accumulator [col][row]
     const int ncb = (s + 63) / 64;
     for (int cbk = ncb - 1; cbk >= 0; --cbk) {
         const int c0 = cbk * 64, c1 = min(c0 + 64, s), bw = c1 - c0;
+        __syncthreads();  // the previous block's columns of G, stored by every thread, are read below
         if (r0 + 63 < c0) {  // rows of the identity above the block: zero in L_F^{-1}
             for (int idx = tid; idx < 64 * 64; idx += 256) {
                 const int rr = idx & 63, cc = idx / 64;
@@ -637,25 +662,11 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 aim[bi][bj] = V4{0, 0, 0, 0};
             }
         // sum over the later pivot columns m >= c1: X(rows, m) L(m, blk)
-        for (int mc = c1; mc < s; mc += KC) {
-            __syncthreads();
-            for (int idx = tid; idx < KC * 64; idx += 256) {
-                const int a = idx & 63, m = idx / 64;
-                const int mm = mc + m;
-                Cx<T> x = cx<T>(0, 0), lv = cx<T>(0, 0);
-                if (mm < s) {
-                    if (r0 + a < n) x = G[(int64_t)mm * n + r0 + a];
-                    if (a < bw) lv = L[(int64_t)(c0 + a) * n + mm];  // L(mm, c0 + a)
-                }
-                Rre[m][a] = x.re;
-                Rim[m][a] = x.im;
-                Cre[m][a] = lv.re;
-                Cim[m][a] = lv.im;
-            }
-            __syncthreads();
-            tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, s - mc);
-        }
-        __syncthreads();
+        cgemm64_pipe<T, KC>(
+            are, aim, s - c1,
+            [&](int m, int a) { return r0 + a < n ? G[(int64_t)(c1 + m) * n + r0 + a] : cx<T>(0, 0); },
+            [&](int m, int a) { return a < bw ? L[(int64_t)(c0 + a) * n + c1 + m] : cx<T>(0, 0); },
+            Rre, Rim, Cre, Cim);
         // acc = B_blk - sum, into LDS as [col][row]
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -673,35 +684,20 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                     }
                     Are[cc][rr] = bv.re - are[bi][bj][r];
                     Aim[cc][rr] = bv.im - aim[bi][bj][r];
+                    are[bi][bj][r] = 0;
+                    aim[bi][bj][r] = 0;
                 }
         __syncthreads();
         // X_blk = acc L_blk^{-1}: X(r, j) = sum_{m >= j} acc(r, m) Linv(m, j)
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                are[bi][bj] = V4{0, 0, 0, 0};
-                aim[bi][bj] = V4{0, 0, 0, 0};
-            }
-        for (int mc = 0; mc < bw; mc += KC) {
-            __syncthreads();
-            for (int idx = tid; idx < KC * 64; idx += 256) {
-                const int a = idx & 63, m = idx / 64;
-                const int mm = mc + m;
-                // Linv(mm, a) for mm > a is stored at L(c0 + a, c0 + mm) (upper triangle)
-                Cx<T> lv = cx<T>(0, 0);
-                if (mm < bw && a < bw) {
-                    if (mm > a) lv = L[(int64_t)(c0 + mm) * n + c0 + a];
-                    else if (mm == a) lv = cx<T>(1, 0);
-                }
-                Cre[m][a] = lv.re;
-                Cim[m][a] = lv.im;
-                Rre[m][a] = mm < bw ? Are[mm][a] : (T)0;
-                Rim[m][a] = mm < bw ? Aim[mm][a] : (T)0;
-            }
-            __syncthreads();
-            tile_cgemm<T, KC>(are, aim, Rre, Rim, Cre, Cim, bw - mc);
-        }
+        cgemm64_pipe<T, KC>(
+            are, aim, bw, [&](int m, int a) { return cx<T>(Are[m][a], Aim[m][a]); },
+            [&](int m, int a) {
+                // Linv(m, a) for m > a is stored at L(c0 + a, c0 + m) (upper triangle)
+                if (a >= bw || m < a) return cx<T>(0, 0);
+                if (m == a) return cx<T>(1, 0);
+                return L[(int64_t)(c0 + m) * n + c0 + a];
+            },
+            Rre, Rim, Cre, Cim);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -713,7 +709,6 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                     if (cc < bw && row < n)
                         G[(int64_t)(c0 + cc) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]);
                 }
-        __syncthreads();
     }
 }
 
