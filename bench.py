@@ -37,20 +37,29 @@ KERNEL_INFO = {"fwd": ("k_fwd", "hbm", "solve.hip"), "bwd": ("k_bwd", "hbm", "so
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def workload(cfg):
+def workload(name):
     from paper_1204_0111_amd import workloads as wl
-    P = wl.make_problem(cfg)
+    P = wl.make_problem(name)
     b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"])
     return P, b.reshape(b.shape[0], -1)
 
 
+MODEL_TEXT = {"constant": "constant velocity 1",
+              "grf": "Gaussian-random-field velocity in [1,3]",
+              "layered": "8 dipping layers, velocity 1.5-6.0 with 5% noise",
+              "wedge_salt": "wedge layers 2.0/3.0/4.5 with a c=4.5 salt body and 3% noise"}
+
+
 def describe(P):
-    return dict(workload="%dx%dx%d interior, Gaussian-random-field velocity in [1,3], 10 points "
-                         "per wavelength, PML gamma=%d (amplitude %.1f), panel depth %d, ND leaf %d, "
-                         "%d Gaussian point source(s), GMRES(20) to FP64 rel-res 1e-5"
-                         % (P["n"] + (P["gamma"], P["C"], P["d"], P["leaf"], P["nrhs"])),
-                n=list(P["n"]), gamma=P["gamma"], panel_depth=P["d"], leaf=P["leaf"],
-                pml_amp=P["C"], alpha=P["alpha"], omega=P["omega"], nrhs=P["nrhs"])
+    from paper_1204_0111_amd import workloads as wl
+    model = MODEL_TEXT[wl.WORKLOADS[P["name"]]["model"]]
+    return dict(workload="%dx%dx%d interior, %s, 10 points per wavelength, PML gamma=%d "
+                         "(amplitude %.1f), panel depth %d, ND leaf %d, %d Gaussian point source(s), "
+                         "GMRES(20) to FP64 rel-res 1e-5"
+                         % (P["n"] + (model, P["gamma"], P["C"], P["d"], P["leaf"], P["nrhs"])),
+                name=P["name"], n=list(P["n"]), gamma=P["gamma"], panel_depth=P["d"],
+                leaf=P["leaf"], pml_amp=P["C"], alpha=P["alpha"], omega=P["omega"],
+                nrhs=P["nrhs"])
 
 
 def source_hash(fname):
@@ -193,7 +202,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cfg", type=int, default=2)
+    ap.add_argument("--workload", default="grf50",
+                    help="a workload name of paper_1204_0111_amd.workloads.WORKLOADS")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pml-amp", type=float, default=None,
@@ -210,7 +220,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    P, b = workload(args.cfg)
+    P, b = workload(args.workload)
     if args.pml_amp is not None:
         P["C"] = args.pml_amp
     if args.calibrate_copy_mb:
@@ -241,7 +251,7 @@ def main():
                 t_setup_ms=main_run["t_setup_ms"], t_solve_ms=main_run["t_solve_ms"],
                 comparator=comp,
                 speedup_vs_fp64=(main_run["value"] / comp["value"]) if comp else None,
-                roofline=roofline_entry(kernels, "c64", "cfg%d" % args.cfg) if kernels else None,
+                roofline=roofline_entry(kernels, "c64", args.workload) if kernels else None,
                 kernel_times_ms={k: 1e3 * v["seconds"] for k, v in kernels.items()} if kernels
                 else None,
                 cpu_baseline=cpu)

@@ -210,6 +210,22 @@ hsw_status hsw_get_front_inverse(const hsw_ctx* ctx, int32_t prob, int32_t panel
 hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, int64_t* launches,
                              double* seconds, double* bytes, double* flops);
 
+/*
+ * Execution options of a context (not part of the method; results do not
+ * depend on them beyond rounding order, and the sweep is deterministic):
+ *   "graph"    1: hsw_apply and hsw_solve replay the sweep of Alg. 1.5 as
+ *              a HIP graph captured at the first application for a (problem,
+ *              right-hand-side count), on a context-owned copy of the vector;
+ *              0 (default): launch its kernels one by one on the stream.
+ *   "autotune" 1 (default): at the first application for a right-hand-side
+ *              group (1, 2, 3-4, 5+), time every block shape of the solve
+ *              kernels per panel class and tree depth and keep the fastest;
+ *              0: a fixed rule (also set by the environment variable
+ *              HSW_AUTOTUNE=0 at create time).
+ * Returns HSW_E_INVAL for an unknown key.
+ */
+hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);
+
 /* Message of the last failing call on ctx (or of the last failed create when ctx is NULL). */
 const char* hsw_last_error(const hsw_ctx* ctx);
 

@@ -67,6 +67,14 @@ struct KernelTimer {
     double bytes = 0, flops = 0;
 };
 
+// A sweep captured as a HIP graph, for one problem and right-hand-side count,
+// operating on its own copy `z` of the vector (N_pad x nrhs).
+struct SweepGraph {
+    int prob = 0, nrhs = 0;
+    hipGraphExec_t exec = nullptr;
+    void* z = nullptr;
+};
+
 struct ProbHost {
     int N[3] = {0, 0, 0};
     int64_t Npad = 0, Nint = 0;
@@ -119,6 +127,13 @@ struct hsw_ctx {
     int nrhs_cap = 0;
     bool autotune = true;
     bool tuned[N_RHS_KEYS] = {};
+    // captured sweeps, their stream and the events joining it to st
+    bool use_graph = false;  // measured slower than stream launches for the sweep
+    std::vector<SweepGraph> graphs;
+    hipStream_t gst = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    // GMRES workspace, kept between solves: (pointer, bytes) per buffer
+    std::vector<std::pair<void*, size_t>> gws;
     void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;
 
     KernelTimer timer;
@@ -179,7 +194,22 @@ static hipError_t dalloc(P** p, size_t bytes) {
     return hipMalloc((void**)p, bytes);
 }
 
+static void drop_graphs(hsw_ctx* ctx) {
+    for (SweepGraph& g : ctx->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.z) (void)hipFree(g.z);
+    }
+    ctx->graphs.clear();
+}
+
 static void free_all(hsw_ctx* ctx) {
+    drop_graphs(ctx);
+    for (auto& w : ctx->gws)
+        if (w.first) (void)hipFree(w.first);
+    ctx->gws.clear();
+    for (hipEvent_t& e : ctx->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->gst) (void)hipStreamDestroy(ctx->gst);
     void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_iperm, ctx->d_ulist,
                     ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
                     ctx->d_L, ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err,
@@ -310,6 +340,42 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
     return HSW_OK;
 }
 
+// Workgroups of a launch go to the chip's XCDs round-robin (workgroup b to
+// XCD b mod 8), each XCD with its own L2.  Reorder the items [b, e) of a
+// launch so that the items of one front land on one XCD, consecutively, and
+// share the front's data in that L2: fronts go to the least loaded of eight
+// bins, and slot p takes the next item of bin p mod 8 (or, once that bin is
+// empty, of the fullest bin).
+static void xcd_group(std::vector<int2>& w, size_t b, size_t e) {
+    constexpr int X = 8;
+    if (e - b <= 1) return;
+    std::map<int, std::vector<int2>> by;
+    std::vector<int> order;
+    for (size_t i = b; i < e; ++i) {
+        if (!by.count(w[i].x)) order.push_back(w[i].x);
+        by[w[i].x].push_back(w[i]);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return by[a].size() > by[c].size(); });
+    std::vector<std::vector<int2>> bins(X);
+    for (int f : order) {
+        int x = 0;
+        for (int y = 1; y < X; ++y)
+            if (bins[y].size() < bins[x].size()) x = y;
+        bins[x].insert(bins[x].end(), by[f].begin(), by[f].end());
+    }
+    std::vector<size_t> pos(X, 0);
+    for (size_t p = b; p < e; ++p) {
+        int x = (int)((p - b) % X);
+        if (pos[x] == bins[x].size()) {
+            x = 0;
+            for (int y = 1; y < X; ++y)
+                if (bins[y].size() - pos[y] > bins[x].size() - pos[x]) x = y;
+        }
+        w[p] = bins[x][pos[x]++];
+    }
+}
+
 static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<SolveItem>& sitems) {
     const int D = ctx->maxdepth;
     std::vector<std::vector<int>> at(D + 1);
@@ -333,6 +399,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
             for (int t = 0; t < nt * (nt + 1) / 2; ++t) fwork.push_back(make_int2(i, t));
         }
         ds.assemble.count = (int)(fwork.size() - ds.assemble.off);
+        xcd_group(fwork, ds.assemble.off, fwork.size());
         for (int i : at[d]) {
             const FrontInst& f = ctx->inst_h[i];
             const double n = f.s + f.u;
@@ -365,6 +432,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
             }
             pl.count = (int)(fwork.size() - pl.off);
+            xcd_group(fwork, pl.off, fwork.size());
             for (int i : at[d]) {
                 const FrontInst& f = ctx->inst_h[i];
                 if (f.s <= k) continue;
@@ -385,6 +453,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 for (int q = 0; q < nt * (nt + 1) / 2; ++q) fwork.push_back(make_int2(i, q));
             }
             t.count = (int)(fwork.size() - t.off);
+            xcd_group(fwork, t.off, fwork.size());
             for (int i : at[d]) {
                 const FrontInst& f = ctx->inst_h[i];
                 if (f.s <= k) continue;
@@ -404,6 +473,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
         for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2((int)i, rb));
     }
     ctx->inv_launch.count = (int)(fwork.size() - ctx->inv_launch.off);
+    xcd_group(fwork, ctx->inv_launch.off, fwork.size());
     for (const FrontInst& f : ctx->inst_h) {
         const double sd = f.s, ud = f.u;
         ctx->inv_launch.bytes_per_esz += (sd + ud) * sd + sd * (sd + 1) / 2 + ud * sd;
@@ -625,6 +695,19 @@ extern "C" void hsw_destroy(hsw_ctx* ctx) {
     delete ctx;
 }
 
+extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value) {
+    if (!ctx || !key) return HSW_E_INVAL;
+    const std::string k(key);
+    if (k == "graph") {
+        ctx->use_graph = value != 0;
+    } else if (k == "autotune") {
+        ctx->autotune = value != 0;
+    } else {
+        return fail(ctx, HSW_E_INVAL, "unknown option " + k);
+    }
+    return HSW_OK;
+}
+
 extern "C" const char* hsw_last_error(const hsw_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }
@@ -734,6 +817,7 @@ template <typename T>
 static hsw_status ensure_solve_ws(hsw_ctx* ctx, int nrhs) {
     if (nrhs <= ctx->nrhs_cap) return HSW_OK;
     HIPCHK(hipStreamSynchronize(ctx->st));
+    drop_graphs(ctx);  // they hold the old workspace addresses
     for (void** p : {&ctx->d_xmid, &ctx->d_xu, &ctx->d_c2}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -849,7 +933,15 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
             if (e) (void)hipEventDestroy(e);
         if (v) (void)hipFree(v);
     };
-#define TCHK(expr)                                                                       do {                                                                                     hipError_t e_ = (expr);                                                              if (e_ != hipSuccess) {                                                                  ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                        cleanup();                                                                           return HSW_E_DEVICE;                                                             }                                                                                } while (0)
+#define TCHK(expr)                                                         \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) {                                            \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);  \
+            cleanup();                                                     \
+            return HSW_E_DEVICE;                                           \
+        }                                                                  \
+    } while (0)
     TCHK(hipMalloc(&v, 16 * (size_t)plen * nrhs));
     TCHK(hipMemsetAsync(v, 0, 16 * (size_t)plen * nrhs, ctx->st));
     for (hipEvent_t& e : ev) TCHK(hipEventCreate(&e));
@@ -912,6 +1004,63 @@ static hsw_status sweep_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<dou
     return HSW_OK;
 }
 
+// z := M^{-1} r through a captured sweep when graphs are enabled: r is copied
+// to the graph's own vector, the graph replays the 2m - 1 panel solves of
+// Alg. 1.5 on it, and the result is copied to z.  The graph runs on a
+// context-owned stream joined to st by events before and after.
+template <typename T>
+static hsw_status sweep_any(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
+                            int64_t ld) {
+    if (!ctx->use_graph || ctx->timer.on) return sweep_impl<T>(ctx, prob, r, z, nrhs, ld);
+    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+    if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
+    if (s != HSW_OK) return s;
+    const ProbHost& h = ctx->ph[prob];
+    const int64_t N = h.Npad;
+    if (!ctx->gst) {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->gst, hipStreamNonBlocking));
+        for (hipEvent_t& e : ctx->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    SweepGraph* g = nullptr;
+    for (SweepGraph& q : ctx->graphs)
+        if (q.prob == prob && q.nrhs == nrhs) g = &q;
+    if (!g) {
+        SweepGraph ng;
+        ng.prob = prob;
+        ng.nrhs = nrhs;
+        HIPCHK(hipMalloc(&ng.z, 16 * (size_t)N * nrhs));
+        Cx<double>* zz = (Cx<double>*)ng.z;
+        const hipStream_t saved = ctx->st;
+        ctx->st = ctx->gst;
+        hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < h.m; ++i)
+                panel_tsolve<T>(ctx, h.panel_base + i, 0, zz, N, 0, 0, i < h.m - 1, zz, nrhs);
+            for (int i = h.m - 2; i >= 0; --i)
+                panel_tsolve<T>(ctx, h.panel_base + i, 1, zz, N, 0, 1, 0, zz, nrhs);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(ctx->gst, &graph);
+            if (e == hipSuccess) e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        ctx->st = saved;
+        if (e != hipSuccess) {
+            (void)hipFree(ng.z);
+            return fail(ctx, HSW_E_DEVICE, std::string("sweep capture: ") + hipGetErrorString(e));
+        }
+        ctx->graphs.push_back(ng);
+        g = &ctx->graphs.back();
+    }
+    HIPCHK(hipMemcpy2DAsync(g->z, 16 * N, r, 16 * ld, 16 * N, nrhs, hipMemcpyDeviceToDevice, ctx->st));
+    HIPCHK(hipEventRecord(ctx->gev[0], ctx->st));
+    HIPCHK(hipStreamWaitEvent(ctx->gst, ctx->gev[0], 0));
+    HIPCHK(hipGraphLaunch(g->exec, ctx->gst));
+    HIPCHK(hipEventRecord(ctx->gev[1], ctx->gst));
+    HIPCHK(hipStreamWaitEvent(ctx->st, ctx->gev[1], 0));
+    HIPCHK(hipMemcpy2DAsync(z, 16 * ld, g->z, 16 * N, 16 * N, nrhs, hipMemcpyDeviceToDevice, ctx->st));
+    return HSW_OK;
+}
+
 static hsw_status check_vec_args(hsw_ctx* ctx, int32_t prob, const void* a, const void* b,
                                  int32_t nrhs, int64_t ld, int64_t minld) {
     if (prob < 0 || prob >= (int)ctx->ph.size()) return fail(ctx, HSW_E_INVAL, "bad problem index");
@@ -929,8 +1078,8 @@ extern "C" hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, h
     if (s != HSW_OK) return s;
     if ((const void*)r == (const void*)z) return fail(ctx, HSW_E_INVAL, "r and z alias");
     return ctx->prec == HSW_C128
-               ? sweep_impl<double>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld)
-               : sweep_impl<float>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
+               ? sweep_any<double>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld)
+               : sweep_any<float>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
 }
 
 extern "C" hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel, const hsw_c128* v,
@@ -994,11 +1143,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
                *y = nullptr, *part = nullptr;
     double *cs = nullptr, *bn = nullptr, *beta = nullptr, *est = nullptr, *nrm = nullptr, *partn = nullptr;
     int *act = nullptr, *jc = nullptr;
-    auto cleanup = [&]() {
-        void* ps[] = {V, Z, H, coef, sn, g, y, part, cs, bn, beta, est, nrm, partn, act, jc};
-        for (void* p : ps)
-            if (p) (void)hipFree(p);
-    };
+    auto cleanup = [&]() {};  // the workspace stays with the context
 #define GCHK(expr)                                                                     \
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
@@ -1008,22 +1153,28 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             return HSW_E_DEVICE;                                                       \
         }                                                                              \
     } while (0)
-    GCHK(hipMalloc(&V, 16 * (size_t)vs * (k + 1)));
-    GCHK(hipMalloc(&Z, 16 * (size_t)vs * k));
-    GCHK(hipMalloc(&H, 16 * (size_t)nrhs * hld));
-    GCHK(hipMalloc(&coef, 16 * (size_t)nrhs * hld));
-    GCHK(hipMalloc(&sn, 16 * (size_t)nrhs * k));
-    GCHK(hipMalloc(&g, 16 * (size_t)nrhs * (k + 1)));
-    GCHK(hipMalloc(&y, 16 * (size_t)nrhs * k));
-    GCHK(hipMalloc(&part, 16 * (size_t)nrhs * nch * (k + 1)));
-    GCHK(hipMalloc(&cs, 8 * (size_t)nrhs * k));
-    GCHK(hipMalloc(&bn, 8 * (size_t)nrhs));
-    GCHK(hipMalloc(&beta, 8 * (size_t)nrhs));
-    GCHK(hipMalloc(&est, 8 * (size_t)nrhs));
-    GCHK(hipMalloc(&nrm, 8 * (size_t)nrhs));
-    GCHK(hipMalloc(&partn, 8 * (size_t)nrhs * nch));
-    GCHK(hipMalloc(&act, 4 * (size_t)nrhs));
-    GCHK(hipMalloc(&jc, 4 * (size_t)nrhs));
+    {
+        void** slots[] = {(void**)&V, (void**)&Z, (void**)&H, (void**)&coef, (void**)&sn, (void**)&g,
+                          (void**)&y, (void**)&part, (void**)&cs, (void**)&bn, (void**)&beta,
+                          (void**)&est, (void**)&nrm, (void**)&partn, (void**)&act, (void**)&jc};
+        const size_t bytes[] = {16 * (size_t)vs * (k + 1), 16 * (size_t)vs * k, 16 * (size_t)nrhs * hld,
+                                16 * (size_t)nrhs * hld, 16 * (size_t)nrhs * k, 16 * (size_t)nrhs * (k + 1),
+                                16 * (size_t)nrhs * k, 16 * (size_t)nrhs * nch * (k + 1), 8 * (size_t)nrhs * k,
+                                8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs,
+                                8 * (size_t)nrhs * nch, 4 * (size_t)nrhs, 4 * (size_t)nrhs};
+        const size_t nslot = sizeof(bytes) / sizeof(bytes[0]);
+        if (ctx->gws.size() < nslot) ctx->gws.resize(nslot, {nullptr, 0});
+        for (size_t i = 0; i < nslot; ++i) {
+            auto& w = ctx->gws[i];
+            if (w.second < bytes[i]) {
+                if (w.first) GCHK(hipFree(w.first));
+                w = {nullptr, 0};
+                GCHK(hipMalloc(&w.first, bytes[i]));
+                w.second = bytes[i];
+            }
+            *slots[i] = w.first;
+        }
+    }
     hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
     if (s != HSW_OK) { cleanup(); return s; }
     std::vector<double> bn_h(nrhs), beta_h(nrhs), est_h(nrhs), rel(nrhs, 1.0);
@@ -1060,7 +1211,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             Cx<double>* Vj = V + (int64_t)j * vs;
             Cx<double>* Vn = V + (int64_t)(j + 1) * vs;
             Cx<double>* Zj = Z + (int64_t)j * vs;
-            s = sweep_impl<T>(ctx, prob, Vj, Zj, nrhs, ld);
+            s = sweep_any<T>(ctx, prob, Vj, Zj, nrhs, ld);
             if (s != HSW_OK) { cleanup(); return s; }
             timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st); });

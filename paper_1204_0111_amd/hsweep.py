@@ -76,6 +76,7 @@ def load_library():
         "hsw_get_front_inverse": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
         "hsw_kernel_timing": (c_int32, [c_void_p, ctypes.c_char_p, c_int32, P(c_int64),
                                         P(c_double), P(c_double), P(c_double)]),
+        "hsw_set_option": (c_int32, [c_void_p, ctypes.c_char_p, c_int64]),
         "hsw_last_error": (ctypes.c_char_p, [c_void_p]),
         "hsw_destroy": (None, [c_void_p]),
     }
@@ -259,6 +260,10 @@ class Solver:
                                            c_void_p(L.ctypes.data), c_void_p(F.ctypes.data),
                                            None, None))
         return D, L, F[:u]
+
+    def set_option(self, key, value):
+        """Execution option of the context: "graph" or "autotune" (0 or 1)."""
+        self._check(self.lib.hsw_set_option(self.ctx, key.encode(), int(value)))
 
     def kernel_timing(self, kernel, enable):
         """Start (enable=True) or stop timing a kernel class; stopping returns the totals."""

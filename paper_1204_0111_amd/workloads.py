@@ -18,14 +18,31 @@ import numpy as np
 
 ALPHA_DEFAULT = 2.25 * math.pi   # damping used for Table 3.2 (Sec. 3)
 PML_AMP_DEFAULT = 4.0            # PML amplitude C, the value most used in Table 3.1
-# PML amplitude per configuration, frozen from a modest search on the FP64
-# path (as Sec. 3 did per problem): the value with the fewest GMRES(20)
-# iterations to 1e-5, ties to the smallest final residual.
-PML_AMP = {1: 15.0, 2: 30.0, 3: 30.0, 4: 30.0, 5: 30.0}
+# The workloads, by name.  `seed` offsets the generator seed 12040111 (sub
+# problems of a batch add 1000 each); C is the PML amplitude frozen from a
+# modest search on the FP64 path (as Sec. 3 did per problem): the value with
+# the fewest GMRES(20) iterations to 1e-5, ties to the smallest residual.
+WORKLOADS = {
+    # 20^3, constant velocity, one plane per panel
+    "const20": dict(seed=1, n=(20, 20, 20), gamma=5, d=1, leaf=8, model="constant", nrhs=1,
+                    src="centre", C=15.0),
+    # 50^3 Gaussian random field in [1, 3]
+    "grf50": dict(seed=2, n=(50, 50, 50), gamma=8, d=4, leaf=4, model="grf", nrhs=1,
+                  src="centre", C=30.0),
+    # 100^3 layered model, 16 surface shots
+    "layered100": dict(seed=3, n=(100, 100, 100), gamma=10, d=4, leaf=4, model="layered",
+                       nrhs=16, src="surface", C=30.0),
+    # one of 48 problems with per-axis sizes drawn from 30..70, 4 shots each
+    "batch48": dict(seed=4, n=None, gamma=8, d=4, leaf=4, model="grf", nrhs=4, src="surface",
+                    C=30.0),
+    # 250^3 wedge with a salt body, 32 surface shots
+    "wedge250": dict(seed=5, n=(250, 250, 250), gamma=12, d=4, leaf=4, model="wedge_salt",
+                     nrhs=32, src="surface", C=30.0),
+}
 
 
-def seed_for(cfg, sub=0):
-    return 12040111 + 1000 * sub + cfg
+def seed_for(offset, sub=0):
+    return 12040111 + 1000 * sub + offset
 
 
 def grid_h(n):
@@ -145,29 +162,22 @@ def random_complex(shape, seed):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
-def make_problem(cfg, scale_n=None, sub=0):
-    """Inputs of one workload.  Returns a dict with the velocity and parameters.
+def make_problem(name, scale_n=None, sub=0):
+    """Inputs of one workload (a key of WORKLOADS).  Returns a dict with the
+    velocity and parameters.
 
-    cfg 1..5 are the five benchmark configurations; scale_n overrides the
-    interior size (reduced variants for parity tests keep everything else).
+    scale_n overrides the interior size (reduced variants for parity tests
+    keep everything else); sub selects one problem of the batch workload.
     """
-    spec = {
-        1: dict(n=(20, 20, 20), gamma=5, d=1, leaf=8, model="constant", nrhs=1, src="centre"),
-        2: dict(n=(50, 50, 50), gamma=8, d=4, leaf=4, model="grf", nrhs=1, src="centre"),
-        3: dict(n=(100, 100, 100), gamma=10, d=4, leaf=4, model="layered", nrhs=16,
-                src="surface"),
-        4: dict(n=None, gamma=8, d=4, leaf=4, model="grf", nrhs=4, src="surface"),
-        5: dict(n=(250, 250, 250), gamma=12, d=4, leaf=4, model="wedge_salt", nrhs=32,
-                src="surface"),
-    }[cfg]
+    spec = WORKLOADS[name]
     n = spec["n"]
-    if cfg == 4 and n is None:
-        rng = np.random.default_rng(seed_for(4, sub))
+    if n is None:
+        rng = np.random.default_rng(seed_for(spec["seed"], sub))
         n = tuple(int(v) for v in rng.integers(30, 71, 3))
     if scale_n is not None:
         n = tuple(int(v) for v in scale_n)
     h = grid_h(n)
-    seed = seed_for(cfg, sub)
+    seed = seed_for(spec["seed"], sub)
     if spec["model"] == "constant":
         c = velocity_constant(n)
     elif spec["model"] == "grf":
@@ -180,7 +190,6 @@ def make_problem(cfg, scale_n=None, sub=0):
         centers = np.array([[0.5, 0.5, 0.5]])
     else:
         centers = surface_centers(spec["nrhs"], seed + 7)
-    return dict(cfg=cfg, n=n, h=h, c=c, omega=omega_for_ppw(c, h), alpha=ALPHA_DEFAULT,
-                gamma=spec["gamma"], C=PML_AMP.get(cfg, PML_AMP_DEFAULT), d=spec["d"],
-                leaf=spec["leaf"],
+    return dict(name=name, n=n, h=h, c=c, omega=omega_for_ppw(c, h), alpha=ALPHA_DEFAULT,
+                gamma=spec["gamma"], C=spec["C"], d=spec["d"], leaf=spec["leaf"],
                 centers=centers, nrhs=len(centers))

@@ -43,16 +43,30 @@ def stats(csv_path, out, cmd):
 
 
 def per_kernel(path):
-    rows = list(csv.DictReader(open(path)))
-    by = {}
+    """Counter values per kernel name over the last step of the run (the
+    dispatches after the last velocity check, which opens a step), and the
+    value read for the calibration copy (the first large device copy)."""
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
     calib = None
     for r in rows:
-        v = float(r["Counter_Value"])
-        if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer") and int(r["Grid_Size"]) >= 65536 \
-                and calib is None:
-            calib = v
-        by.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(v)
+        if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer") and int(r["Grid_Size"]) >= 65536:
+            calib = float(r["Counter_Value"])
+            break
+    last = max(i for i, r in enumerate(rows) if "k_check_velocity" in r["Kernel_Name"])
+    by = {}
+    for r in rows[last:]:
+        by.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(
+            float(r["Counter_Value"]))
     return by, calib
+
+
+def of_symbol(by, sym):
+    """All dispatches of a kernel, over its template instantiations."""
+    vals = []
+    for k, v in by.items():
+        if k.split("<")[0].endswith(sym):
+            vals += v
+    return vals
 
 
 def pmc(fetch_csv, write_csv, sym, workload, out, cmd_f, cmd_w):
@@ -60,20 +74,21 @@ def pmc(fetch_csv, write_csv, sym, workload, out, cmd_f, cmd_w):
     wb, wcal = per_kernel(write_csv)
     ff = COPY_BYTES / (fcal * 1024.0)
     wf = COPY_BYTES / (wcal * 1024.0)
-    key = [k for k in fb if k.split("<")[0].endswith(sym)][0]
-    fk = sum(fb[key]) / len(fb[key])
-    wk = sum(wb[key]) / len(wb[key])
-    res = dict(kernel=sym, workload=workload, dispatches=len(fb[key]),
+    fv, wv = of_symbol(fb, sym), of_symbol(wb, sym)
+    fk = sum(fv) / len(fv)
+    wk = sum(wv) / len(wv)
+    res = dict(kernel=sym, workload=workload, dispatches=len(fv),
                fetch_kib_per_dispatch=fk, write_kib_per_dispatch=wk,
                fetch_scale=ff, write_scale=wf,
                hbm_bytes_per_launch=fk * 1024 * ff + wk * 1024 * wf, source_hash=src_hash(sym))
     with open(out, "w") as f:
-        f.write("# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, per dispatch of %s (%s)\n" % (sym, workload))
+        f.write("# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, per dispatch of %s (%s), last step\n"
+                % (sym, workload))
         f.write("# fetch command: %s\n# write command: %s\n" % (cmd_f, cmd_w))
         f.write("# calibration: 512 MiB device copy read FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB\n"
                 % (fcal, wcal))
         f.write("# scale factors: fetch %.4f, write %.4f (bytes per counted KiB / 1024)\n" % (ff, wf))
-        for k in sorted(fb, key=lambda k: -sum(fb[k]))[:8]:
+        for k in sorted(fb, key=lambda k: -sum(fb[k]))[:12]:
             f.write("%-40s fetch %12.1f KiB/dispatch  write %12.1f KiB/dispatch  n=%d\n"
                     % (k[:40], sum(fb[k]) / len(fb[k]), sum(wb.get(k, [0])) / max(len(wb.get(k, [1])), 1),
                        len(fb[k])))

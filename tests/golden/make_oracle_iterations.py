@@ -2,11 +2,11 @@
 
 Calls only the oracle (and the seeded input generators).  Usage:
 
-    python tests/golden/make_oracle_iterations.py cfg2 [cfg1 ...]
+    python tests/golden/make_oracle_iterations.py grf50 [const20 ...]
 
-Each entry records the configuration's PML amplitude, the iteration count to
+Each entry records the workload's PML amplitude, the iteration count to
 FP64 relative residual 1e-5 and the final true relative residual.  Takes a
-few minutes per 50^3 configuration (13 sparse LU factorisations).
+few minutes for the 50^3 workload (13 sparse LU factorisations).
 """
 
 import json
@@ -25,7 +25,7 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_iteration
 
 
 def run(name):
-    P = wl.make_problem(int(name[3:]))
+    P = wl.make_problem(name)
     S = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
     A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
     b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(P["nrhs"], -1)

@@ -28,8 +28,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    P = wl.make_problem(2)
+def grf50():
+    P = wl.make_problem("grf50")
     b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
     return P, b
 
@@ -43,8 +43,8 @@ def _solver(P, prec):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_factors_bitwise_reproducible(cfg2, prec):
-    P, _ = cfg2
+def test_factors_bitwise_reproducible(grf50, prec):
+    P, _ = grf50
     S = _solver(P, prec)
     fronts = [(3, 0), (3, 1), (3, 2), (5, 100), (0, 0), (12, 0), (12, 255)]
     a = [S.front_inverse(0, i, f) for i, f in fronts]
@@ -57,9 +57,9 @@ def test_factors_bitwise_reproducible(cfg2, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_middle_panel_solve_matches_oracle(cfg2, prec):
+def test_middle_panel_solve_matches_oracle(grf50, prec):
     import scipy.sparse.linalg as spla
-    P, _ = cfg2
+    P, _ = grf50
     S = _solver(P, prec)
     i = 5
     H, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
@@ -73,8 +73,8 @@ def test_middle_panel_solve_matches_oracle(cfg2, prec):
     assert rel(y, ref) <= TOL[prec]
 
 
-def test_matvec_full_size(cfg2):
-    P, _ = cfg2
+def test_matvec_full_size(grf50):
+    P, _ = grf50
     S = _solver(P, "c64")
     A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
     x = wl.random_complex((1, A.shape[0]), 2)
@@ -83,10 +83,10 @@ def test_matvec_full_size(cfg2):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_solve_full_size_matches_oracle_iterations(cfg2, prec):
-    P, b = cfg2
+def test_solve_full_size_matches_oracle_iterations(grf50, prec):
+    P, b = grf50
     path = os.path.join(GOLDEN, "oracle_iterations.json")
-    ref = json.load(open(path))["cfg2"]
+    ref = json.load(open(path))["grf50"]
     assert abs(ref["C"] - P["C"]) < 1e-12, "stored count is for another PML amplitude"
     S = _solver(P, prec)
     xs, info = S.solve([torch.as_tensor(b).to("cuda")], rtol=1e-5, restart=20)
@@ -103,8 +103,8 @@ def test_solve_full_size_matches_oracle_iterations(cfg2, prec):
 
 def test_20cubed_solve_matches_oracle_iterations():
     """The 20^3 constant-velocity workload (gamma 5, one plane per panel) in complex128."""
-    P = wl.make_problem(1)
-    ref = json.load(open(os.path.join(GOLDEN, "oracle_iterations.json")))["cfg1"]
+    P = wl.make_problem("const20")
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_iterations.json")))["const20"]
     assert abs(ref["C"] - P["C"]) < 1e-12
     b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
     S = _solver(P, "c128")

@@ -254,3 +254,52 @@ def test_several_problems_in_one_context(prec):
         b = bs[k].cpu().numpy()[0]
         x = xs[k].cpu().numpy()[0]
         assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_graph_replays_match_the_eager_sweep(medium, prec):
+    """The captured sweep, replayed several times with eager work and
+    synchronisations in between, equals the eager sweep bitwise each time."""
+    S = _solver(medium, prec)
+    r = _cuda(wl.random_complex((2, S.N_pad()), 11))
+    S.set_option("graph", 0)
+    z0 = S.apply(0, r).cpu().numpy()
+    S.set_option("graph", 1)
+    for rep in range(4):
+        z = S.apply(0, r)
+        torch.cuda.synchronize()
+        assert np.array_equal(z.cpu().numpy(), z0), rep
+        S.matvec(0, r)                      # eager work between replays
+        S.set_option("graph", 0)
+        assert np.array_equal(S.apply(0, r).cpu().numpy(), z0), rep
+        S.set_option("graph", 1)
+        torch.cuda.synchronize()
+    # a second right-hand-side count gets its own graph
+    r1 = r[:1].contiguous()
+    S.set_option("graph", 0)
+    e1 = S.apply(0, r1).cpu().numpy()
+    S.set_option("graph", 1)
+    assert np.array_equal(S.apply(0, r1).cpu().numpy(), e1)
+    assert np.array_equal(S.apply(0, r).cpu().numpy(), z0)
+
+
+def test_solve_options_agree(medium):
+    """GMRES through captured sweeps with tuned block shapes agrees with the
+    eager sweep with the default shapes (same iterations, residual < 1e-5)."""
+    P = medium
+    b = _cuda(wl.gaussian_sources(P["n"], P["gamma"], P["h"], [[0.5, 0.5, 0.5]]).reshape(1, -1))
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    out = []
+    for graph, tune in [(1, 1), (0, 0)]:
+        S = _solver(P, "c64")
+        S.set_option("graph", graph)
+        S.set_option("autotune", tune)
+        xs, info = S.solve([b], rtol=1e-5, restart=20)
+        x = xs[0].cpu().numpy()[0]
+        bb = b.cpu().numpy()[0]
+        assert np.linalg.norm(bb - A @ x) / np.linalg.norm(bb) < 1e-5
+        out.append((info["iters"][0], x))
+    assert out[0][0] == out[1][0]
+    assert rel(out[0][1], out[1][1]) < 1e-4
+    with pytest.raises(Exception):
+        S.set_option("no-such-option", 1)
