@@ -254,6 +254,12 @@ def main():
                 roofline=roofline_entry(kernels, "c64", args.workload) if kernels else None,
                 kernel_times_ms={k: 1e3 * v["seconds"] for k, v in kernels.items()} if kernels
                 else None,
+                # per kernel class over one step: launches, summed time, and the
+                # algorithmic rate against the class's roofline
+                kernel_classes={k: dict(launches=v["launches"], ms=1e3 * v["seconds"],
+                                        gbs=v["bytes"] / max(v["seconds"], 1e-30) / 1e9,
+                                        tflops=v["flops"] / max(v["seconds"], 1e-30) / 1e12)
+                                for k, v in kernels.items()} if kernels else None,
                 cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 

@@ -222,7 +222,13 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              kernels per panel class and tree depth and keep the fastest;
  *              0: a fixed rule (also set by the environment variable
  *              HSW_AUTOTUNE=0 at create time).
- * Returns HSW_E_INVAL for an unknown key.
+ *   "update_order" order of the Schur-complement updates in hsw_setup:
+ *              0 right-looking (each pivot block updates everything after
+ *              it); 1 left-looking (each block column receives all earlier
+ *              pivots before it is factored, F_BR once at the end); 2 or -1
+ *              (default) hybrid: right-looking over the pivot columns, F_BR
+ *              once at the end.  The factors agree to rounding.
+ * Returns HSW_E_INVAL for an unknown key or value.
  */
 hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);
 

@@ -99,7 +99,10 @@ struct SolveItem {
     int32_t pmap;            // forward: position of each update entry in the parent front
     int32_t xu;              // the front's update-set values (u per right-hand side)
     int32_t cxu0, cxu1;      // backward: the children's update-set values, -1 if no child
-    int32_t pad[3];
+    // the front's cells, a rectangle: (x0 | y0 << 16) and (cells per row |
+    // cells << 16); pivot e is cell e mod cells (row-major) on aux plane e / cells
+    int32_t cell0, cellw;
+    int32_t pad;
 };
 static_assert(sizeof(SolveItem) == 64, "SolveItem is one 64-byte scalar load");
 
@@ -111,7 +114,6 @@ struct PassArgs {
     const Cx<T>* dinv;         // the panel's reciprocal pivots
     const int* cmap;           // extend-add maps (concatenated)
     const int* pmap;           // parent positions (concatenated)
-    const int* perm;           // the class's elimination order: position -> box index
     const Cx<double>* et;      // stretch tables
     const Cx<double>* src;     // forward: padded-grid input (column r at r * ld)
     Cx<double>* dst;           // backward: padded-grid output

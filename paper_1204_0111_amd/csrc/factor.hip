@@ -52,8 +52,7 @@ __device__ inline Cx<double> aux_entry(const ProbDev& Q, const PanelDev& P, cons
     int ax = d1 != 0 ? 0 : (d2 != 0 ? 1 : 2);
     int sgn = d1 + d2 + d3;  // +1: i is the upper node
     int la1 = sgn > 0 ? a1j : a1i, la2 = sgn > 0 ? a2j : a2i, lq = sgn > 0 ? qj : qi;
-    NodeStretch st = node_stretch(Q, et, la1, la2, e3n, ie3, lq);
-    return upper_coupling(st, ax, inv_h2);
+    return coupling_entry(Q, et, e3n, ie3, la1, la2, lq, ax, inv_h2);
 }
 
 // ---------------------------------------------------------------------------
@@ -167,13 +166,20 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
             rr[q] = Rre[kk + lk][wr + 16 * q + li];
             ri[q] = Rim[kk + lk][wr + 16 * q + li];
         }
+        // four rounds of eight independent products, so that no product
+        // waits for the previous one on the same accumulator
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
                 are[bi][bj] = mfma4(cr[bj], rr[bi], are[bi][bj]);
-                are[bi][bj] = mfma4(-ci[bj], ri[bi], are[bi][bj]);
                 aim[bi][bj] = mfma4(cr[bj], ri[bi], aim[bi][bj]);
+            }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                are[bi][bj] = mfma4(-ci[bj], ri[bi], are[bi][bj]);
                 aim[bi][bj] = mfma4(ci[bj], rr[bi], aim[bi][bj]);
             }
     }
@@ -238,8 +244,8 @@ __device__ inline void cmma16(typename MfmaAcc<T>::type& are, typename MfmaAcc<T
         const Cx<T> a = kx < K ? getA(i, kx) : cx<T>(0, 0);
         const Cx<T> b = kx < K ? getB(kx, i) : cx<T>(0, 0);
         are = mfma4(a.re, b.re, are);
-        are = mfma4(-a.im, b.im, are);
         aim = mfma4(a.re, b.im, aim);
+        are = mfma4(-a.im, b.im, are);
         aim = mfma4(a.im, b.re, aim);
     }
 }
@@ -538,11 +544,21 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update of pivot block [k, k+b): F[i,j] -= sum_m X[i,m] d_m X[j,m]
-// over the lower triangle of rows/columns [k+b, s+u) -- the F_BR := F_BR -
-// Z F_BL^T Schur update of Sec. 2.2 applied blockwise, plus the update of
-// the remaining pivot columns.  One workgroup per 64 x 64 output tile, on
-// the matrix cores.
+// Schur-complement updates of the fronts on the matrix cores (Sec. 2.2:
+// F_BR := F_BR - Z F_BL^T, applied blockwise), F[i,j] -= sum_m L[i,m] d_m L[j,m]
+// over the lower triangle, m in [kbeg, kbeg + K).  One workgroup per 64 x 64
+// output tile; the modes differ in which tiles and which pivots:
+//   UPD_TRAIL  right-looking: pivot block [k, k+b) into every later row and
+//              column (tiles of the triangle from t0 = k + b), K = b;
+//   UPD_LEFT   left-looking: every earlier pivot into block column [k, k+b)
+//              (row tiles from k), K = k;
+//   UPD_SCHUR  every pivot into F_BR (tiles of the triangle from s), K = s;
+//   UPD_PIVOTS as UPD_TRAIL but only into the pivot columns (< s): F_BR is
+//              left to one UPD_SCHUR at the end (the hybrid order).
+// With bf16 != 0 the inputs are rounded to bfloat16 (a bf16-input,
+// FP32-accumulate product).
+enum { UPD_TRAIL = 0, UPD_LEFT = 1, UPD_SCHUR = 2, UPD_PIVOTS = 3 };
+
 // Round to the nearest bfloat16 (ties to even), kept in an FP32 register:
 // products of two such values are exact in FP32, so the matrix cores then
 // compute a bf16-input, FP32-accumulate product.
@@ -555,24 +571,38 @@ __device__ inline float round_bf16(float x) {
 __device__ inline double round_bf16(double x) { return x; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
-                                                  const FrontInst* __restrict__ inst,
-                                                  Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
-                                                  int k, int bf16) {
+__global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
+                                                const FrontInst* __restrict__ inst,
+                                                Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
+                                                int k, int mode, int bf16) {
     constexpr int KC = 16;
     typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
     const FrontInst f = inst[w.x];
     const int n = f.s + f.u;
-    const int b = min(NB, f.s - k);
-    const int t0 = k + b;
-    int ti, tj;
-    tri_decode_dev(w.y, ti, tj);
-    const int r0 = t0 + ti * TILE, c0 = t0 + tj * TILE;
+    int kbeg, K, r0, c0, cend;
+    if (mode == UPD_LEFT) {
+        const int b = min(NB, f.s - k);
+        kbeg = 0;
+        K = k;
+        r0 = k + 64 * w.y;
+        c0 = k;
+        cend = k + b;
+    } else {
+        const bool blockwise = mode != UPD_SCHUR;
+        const int b = blockwise ? min(NB, f.s - k) : f.s;
+        const int t0 = blockwise ? k + b : f.s;
+        kbeg = blockwise ? k : 0;
+        K = b;
+        int ti, tj;
+        tri_decode_dev(w.y, ti, tj);
+        r0 = t0 + ti * TILE;
+        c0 = t0 + tj * TILE;
+        cend = mode == UPD_PIVOTS ? f.s : n;
+    }
     Cx<T>* L = Lb + f.loff;
     Cx<T>* W = Wcur + f.woff;
     __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
-    __shared__ Cx<T> dd[NB];
     const int tid = threadIdx.x;
     const int l = tid & 63, wv = tid >> 6;
     const int li = l & 15, lk = l >> 4;
@@ -586,9 +616,9 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
             for (int r = 0; r < 4; ++r) {
                 const int i = r0 + (wv & 1) * 32 + 16 * bi + li;
                 const int j = c0 + (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
-                old[bi][bj][r] = (i < n && j < n && i >= j) ? *front_at(L, W, n, f.s, f.u, i, j) : cx<T>(0, 0);
+                old[bi][bj][r] = (i < n && j < cend && i >= j) ? *front_at(L, W, n, f.s, f.u, i, j)
+                                                               : cx<T>(0, 0);
             }
-    if (tid < b) dd[tid] = L[(int64_t)(k + tid) * n + k + tid];
     V4 are[2][2], aim[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -597,12 +627,17 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
-    __syncthreads();
     auto rnd = [&](Cx<T> v) { return bf16 ? cx<T>(round_bf16(v.re), round_bf16(v.im)) : v; };
     cgemm64_pipe<T, KC>(
-        are, aim, b,
-        [&](int m, int a) { return r0 + a < n ? rnd(L[(int64_t)(k + m) * n + r0 + a]) : cx<T>(0, 0); },
-        [&](int m, int a) { return c0 + a < n ? rnd(L[(int64_t)(k + m) * n + c0 + a] * dd[m]) : cx<T>(0, 0); },
+        are, aim, K,
+        [&](int m, int a) {
+            const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
+            return r0 + a < n ? rnd(col[r0 + a]) : cx<T>(0, 0);
+        },
+        [&](int m, int a) {
+            const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
+            return c0 + a < cend ? rnd(col[c0 + a] * col[kbeg + m]) : cx<T>(0, 0);  // L[j,m] d_m
+        },
         Rre, Rim, Cre, Cim);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -612,7 +647,7 @@ __global__ __launch_bounds__(256) void k_trailing(const int2* __restrict__ work,
             for (int r = 0; r < 4; ++r) {
                 const int i = r0 + (wv & 1) * 32 + 16 * bi + li;
                 const int j = c0 + (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
-                if (i < n && j < n && i >= j)
+                if (i < n && j < cend && i >= j)
                     *front_at(L, W, n, f.s, f.u, i, j) = old[bi][bj][r] - cx<T>(are[bi][bj][r], aim[bi][bj][r]);
             }
 }
@@ -735,10 +770,10 @@ void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>
     HSW_LAUNCH(k_panel_trsm<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, dinv, k);
 }
 template <typename T>
-void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
-                     int k, int bf16, hipStream_t st) {
+void launch_update(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur, int k,
+                   int mode, int bf16, hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH(k_trailing<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, bf16);
+    HSW_LAUNCH(k_update<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, mode, bf16);
 }
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
@@ -756,8 +791,8 @@ void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx
                                       int*, hipStream_t);                                       \
     template void launch_panel_trsm<T>(const int2*, int, const FrontInst*, Cx<T>*, const Cx<T>*, \
                                        int, hipStream_t);                                       \
-    template void launch_trailing<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int,    \
-                                     int, hipStream_t);                                         \
+    template void launch_update<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int, int,  \
+                                   int, hipStream_t);                                           \
     template void launch_inverse<T>(const int2*, int, const FrontInst*, const Cx<T>*, Cx<T>*,    \
                                     hipStream_t);
 HSW_INST(float)

@@ -41,6 +41,14 @@ struct Launch {
 struct DepthSchedule {
     Launch assemble;
     std::vector<Launch> ldlt, panel, trail;  // one per pivot block
+    // left-looking alternative: update of block column k before its pivots
+    // are factored (empty launch for k = 0), and one final Schur update of F_BR
+    std::vector<Launch> left;
+    Launch schur;
+    // hybrid: the right-looking update restricted to the pivot columns,
+    // with F_BR left to the final Schur update
+    std::vector<Launch> pivots;
+    int nfronts = 0;
 };
 
 // Right-hand-side groups that are tuned separately: 1, 2, 3-4, 5+ columns.
@@ -115,7 +123,7 @@ struct hsw_ctx {
     FrontInst* d_inst = nullptr;
     PanelDev* d_pan = nullptr;
     ProbDev* d_prob = nullptr;
-    int *d_perm = nullptr, *d_iperm = nullptr, *d_ulist = nullptr, *d_cmap = nullptr;
+    int *d_perm = nullptr, *d_ulist = nullptr, *d_cmap = nullptr;
     int2* d_fwork = nullptr;
     int* d_pmap = nullptr;
     SolveItem* d_sitems = nullptr;
@@ -129,6 +137,7 @@ struct hsw_ctx {
     bool tuned[N_RHS_KEYS] = {};
     // captured sweeps, their stream and the events joining it to st
     bool use_graph = false;  // measured slower than stream launches for the sweep
+    int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -210,7 +219,7 @@ static void free_all(hsw_ctx* ctx) {
     for (hipEvent_t& e : ctx->gev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->gst) (void)hipStreamDestroy(ctx->gst);
-    void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_iperm, ctx->d_ulist,
+    void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist,
                     ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
                     ctx->d_L, ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err,
                     ctx->d_xmid, ctx->d_xu, ctx->d_c2};
@@ -464,7 +473,56 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 t.cmac += tr * (tr + 1) / 2 * b;
             }
             ds.trail.push_back(t);
+            Launch pv{(int64_t)fwork.size(), 0, k};
+            for (int i : at[d]) {
+                const FrontInst& f = ctx->inst_h[i];
+                if (f.s <= k) continue;
+                const int b = std::min(NB, f.s - k);
+                const int tr = f.s + f.u - k - b, tc = f.s - k - b;
+                if (tr <= 0 || tc <= 0) continue;
+                const int nt = (tr + TILE - 1) / TILE, ntc = (tc + TILE - 1) / TILE;
+                for (int q = 0; q < nt * (nt + 1) / 2; ++q) {
+                    int ti, tj;
+                    tri_decode(q, ti, tj);
+                    if (tj < ntc) fwork.push_back(make_int2(i, q));
+                }
+                const double bd = b, trd = tr, tcd = tc;
+                const double ent = tcd * (tcd + 1) / 2 + (trd - tcd) * tcd;  // lower part of the pivot columns
+                pv.bytes_per_esz += 2 * ent + trd * bd + tcd * bd;
+                pv.cmac += ent * bd;
+            }
+            pv.count = (int)(fwork.size() - pv.off);
+            xcd_group(fwork, pv.off, fwork.size());
+            ds.pivots.push_back(pv);
+            Launch lf{(int64_t)fwork.size(), 0, k};
+            if (k > 0) {
+                for (int i : at[d]) {
+                    const FrontInst& f = ctx->inst_h[i];
+                    if (f.s <= k) continue;
+                    const int nrt = (f.s + f.u - k + TILE - 1) / TILE;
+                    for (int q = 0; q < nrt; ++q) fwork.push_back(make_int2(i, q));
+                    const double b = std::min(NB, f.s - k), rows = f.s + f.u - k;
+                    lf.bytes_per_esz += 2 * (rows * b - b * (b - 1) / 2) + (rows + b) * k;
+                    lf.cmac += (rows * b - b * (b - 1) / 2) * k;
+                }
+            }
+            lf.count = (int)(fwork.size() - lf.off);
+            xcd_group(fwork, lf.off, fwork.size());
+            ds.left.push_back(lf);
         }
+        ds.schur = Launch{(int64_t)fwork.size(), 0, 0};
+        for (int i : at[d]) {
+            const FrontInst& f = ctx->inst_h[i];
+            if (f.u <= 0) continue;
+            const int nt = (f.u + TILE - 1) / TILE;
+            for (int q = 0; q < nt * (nt + 1) / 2; ++q) fwork.push_back(make_int2(i, q));
+            const double sd = f.s, ud = f.u;
+            ds.schur.bytes_per_esz += ud * (ud + 1) + ud * sd;  // F_BR lower read + written, F_BL read
+            ds.schur.cmac += ud * (ud + 1) / 2 * sd;
+        }
+        ds.schur.count = (int)(fwork.size() - ds.schur.off);
+        xcd_group(fwork, ds.schur.off, fwork.size());
+        ds.nfronts = (int)at[d].size();
     }
     ctx->inv_launch.off = (int64_t)fwork.size();
     for (size_t i = 0; i < ctx->inst_h.size(); ++i) {
@@ -501,6 +559,8 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 it.xu = c.woff[f];
                 it.cxu0 = c.child0[f] >= 0 ? c.woff[c.child0[f]] : -1;
                 it.cxu1 = c.child1[f] >= 0 ? c.woff[c.child1[f]] : -1;
+                it.cell0 = c.cell0[f];
+                it.cellw = c.cellw[f];
                 return it;
             };
             for (int k = 0; k < N_FWD_SHAPES; ++k) {
@@ -605,7 +665,7 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     for (auto& h : ctx->ph) nint_total += h.Nint;
     size_t ints = 0;
     for (auto& c : ctx->classes)
-        ints += 2 * (size_t)c.naux + c.ulist.size() + c.cmap.size() + c.pmap.size();
+        ints += (size_t)c.naux + c.ulist.size() + c.cmap.size() + c.pmap.size();
     const size_t need = (size_t)ctx->esz * (2 * ctx->L_size + ctx->D_size + ctx->ws_size[0] +
                                              ctx->ws_size[1]) +
                         sizeof(FrontInst) * ctx->inst_h.size() + sizeof(PanelDev) * ctx->pan_h.size() +
@@ -640,16 +700,14 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ACHK(dalloc(&ctx->d_inst, sizeof(FrontInst) * ctx->inst_h.size()));
     ACHK(dalloc(&ctx->d_pan, sizeof(PanelDev) * ctx->pan_h.size()));
     ACHK(dalloc(&ctx->d_prob, sizeof(ProbDev) * ctx->prob_h.size()));
-    std::vector<int> perm, iperm, ul, cm, pm;
+    std::vector<int> perm, ul, cm, pm;
     for (auto& c : ctx->classes) {
         perm.insert(perm.end(), c.perm.begin(), c.perm.end());
-        iperm.insert(iperm.end(), c.iperm.begin(), c.iperm.end());
         ul.insert(ul.end(), c.ulist.begin(), c.ulist.end());
         cm.insert(cm.end(), c.cmap.begin(), c.cmap.end());
         pm.insert(pm.end(), c.pmap.begin(), c.pmap.end());
     }
     ACHK(dalloc(&ctx->d_perm, 4 * perm.size()));
-    ACHK(dalloc(&ctx->d_iperm, 4 * iperm.size()));
     ACHK(dalloc(&ctx->d_ulist, 4 * std::max<size_t>(ul.size(), 1)));
     ACHK(dalloc(&ctx->d_cmap, 4 * std::max<size_t>(cm.size(), 1)));
     ACHK(dalloc(&ctx->d_fwork, 8 * std::max<size_t>(fwork.size(), 1)));
@@ -670,7 +728,6 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ACHK(hipMemcpyAsync(ctx->d_prob, ctx->prob_h.data(), sizeof(ProbDev) * ctx->prob_h.size(),
                         hipMemcpyHostToDevice, st));
     ACHK(hipMemcpyAsync(ctx->d_perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice, st));
-    ACHK(hipMemcpyAsync(ctx->d_iperm, iperm.data(), 4 * iperm.size(), hipMemcpyHostToDevice, st));
     if (!ul.empty())
         ACHK(hipMemcpyAsync(ctx->d_ulist, ul.data(), 4 * ul.size(), hipMemcpyHostToDevice, st));
     if (!cm.empty())
@@ -702,6 +759,9 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->use_graph = value != 0;
     } else if (k == "autotune") {
         ctx->autotune = value != 0;
+    } else if (k == "update_order") {
+        if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
+        ctx->update_order = (int)value;
     } else {
         return fail(ctx, HSW_E_INVAL, "unknown option " + k);
     }
@@ -762,7 +822,16 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                                ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap,
                                ctx->d_et, L, ws[d & 1], ws[(d + 1) & 1], st);
         });
+        const int bf16 = ctx->prec == HSW_C64_BF16GEMM;
+        const int order = ctx->update_order;
+        const bool left = order == 1;
+        const bool hybrid = order == 2 || (order < 0);
         for (size_t s = 0; s < ds.ldlt.size(); ++s) {
+            if (left)
+                timed(ctx, "trailing", ds.left[s].count, es * ds.left[s].bytes_per_esz, 8 * ds.left[s].cmac, [&] {
+                    launch_update<T>(ctx->d_fwork + ds.left[s].off, ds.left[s].count, ctx->d_inst, L,
+                                     ws[d & 1], ds.left[s].k, 1, bf16, st);
+                });
             timed(ctx, "diag", ds.ldlt[s].count, es * ds.ldlt[s].bytes_per_esz, 8 * ds.ldlt[s].cmac, [&] {
                 launch_ldlt_diag<T>(ctx->d_fwork + ds.ldlt[s].off, ds.ldlt[s].count, ctx->d_inst, L,
                                     dinv, ds.ldlt[s].k, ctx->d_err, st);
@@ -771,11 +840,22 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                 launch_panel_trsm<T>(ctx->d_fwork + ds.panel[s].off, ds.panel[s].count, ctx->d_inst,
                                      L, dinv, ds.panel[s].k, st);
             });
-            timed(ctx, "trailing", ds.trail[s].count, es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
-                launch_trailing<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
-                                   ws[d & 1], ds.trail[s].k, ctx->prec == HSW_C64_BF16GEMM, st);
-            });
+            if (hybrid)
+                timed(ctx, "trailing", ds.pivots[s].count, es * ds.pivots[s].bytes_per_esz, 8 * ds.pivots[s].cmac, [&] {
+                    launch_update<T>(ctx->d_fwork + ds.pivots[s].off, ds.pivots[s].count, ctx->d_inst, L,
+                                     ws[d & 1], ds.pivots[s].k, 3, bf16, st);
+                });
+            else if (!left)
+                timed(ctx, "trailing", ds.trail[s].count, es * ds.trail[s].bytes_per_esz, 8 * ds.trail[s].cmac, [&] {
+                    launch_update<T>(ctx->d_fwork + ds.trail[s].off, ds.trail[s].count, ctx->d_inst, L,
+                                     ws[d & 1], ds.trail[s].k, 0, bf16, st);
+                });
         }
+        if (left || hybrid)
+            timed(ctx, "trailing", ds.schur.count, es * ds.schur.bytes_per_esz, 8 * ds.schur.cmac, [&] {
+                launch_update<T>(ctx->d_fwork + ds.schur.off, ds.schur.count, ctx->d_inst, L, ws[d & 1],
+                                 0, 2, bf16, st);
+            });
     }
     timed(ctx, "inverse", ctx->inv_launch.count, sizeof(Cx<T>) * ctx->inv_launch.bytes_per_esz, 8 * ctx->inv_launch.cmac, [&] {
         launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L,
@@ -852,7 +932,6 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
     A.dinv = (const Cx<T>*)ctx->d_dinv + f0.doff;
     A.cmap = ctx->d_cmap;
     A.pmap = ctx->d_pmap;
-    A.perm = ctx->d_perm + P.perm_off;
     A.et = ctx->d_et;
     A.src = src;
     A.dst = dst;

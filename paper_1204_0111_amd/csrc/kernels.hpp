@@ -41,9 +41,11 @@ void launch_ldlt_diag(const int2* work, int nwork, const FrontInst* inst, Cx<T>*
 template <typename T>
 void launch_panel_trsm(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb,
                        const Cx<T>* dinv, int k, hipStream_t st);
+// mode: 0 right-looking trailing update of pivot block k, 1 left-looking
+// update of block column k, 2 final Schur update of F_BR (see factor.hip)
 template <typename T>
-void launch_trailing(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur,
-                     int k, int bf16, hipStream_t st);
+void launch_update(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur, int k,
+                   int mode, int bf16, hipStream_t st);
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
                     hipStream_t st);

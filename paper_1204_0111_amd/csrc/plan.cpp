@@ -19,6 +19,9 @@ LatTree build_lateral_tree(int Nx, int Ny, int leaf) {
         if (w <= leaf && h <= leaf) {
             for (int a2 = y0; a2 < y1; ++a2)
                 for (int a1 = x0; a1 < x1; ++a1) nd.cells.push_back(a1 + a2 * Nx);
+            nd.cx0 = x0;
+            nd.cy0 = y0;
+            nd.cw = w;
             t.nodes.push_back(nd);
             return (int)t.nodes.size() - 1;
         }
@@ -28,11 +31,17 @@ LatTree build_lateral_tree(int Nx, int Ny, int leaf) {
             l = rec(x0, cut, y0, y1);
             r = rec(cut + 1, x1, y0, y1);
             for (int a2 = y0; a2 < y1; ++a2) nd.cells.push_back(cut + a2 * Nx);
+            nd.cx0 = cut;
+            nd.cy0 = y0;
+            nd.cw = 1;
         } else {
             int cut = y0 + h / 2;
             l = rec(x0, x1, y0, cut);
             r = rec(x0, x1, cut + 1, y1);
             for (int a1 = x0; a1 < x1; ++a1) nd.cells.push_back(a1 + cut * Nx);
+            nd.cx0 = x0;
+            nd.cy0 = cut;
+            nd.cw = w;
         }
         nd.child[0] = l;
         nd.child[1] = r;
@@ -88,6 +97,24 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
             }
     }
     if (pos != pc.naux) return "elimination order does not cover the panel";
+    // the solves compute box indices from the cell rectangle: check that
+    // closed form against the elimination order
+    pc.cell0.resize(nf);
+    pc.cellw.resize(nf);
+    for (int k = 0; k < nf; ++k) {
+        const LatNode& nd = lt.nodes[k];
+        const int nc = (int)nd.cells.size();
+        if (nd.cw < 1 || nc % nd.cw != 0 || nd.cx0 >= (1 << 16) || nd.cy0 >= (1 << 16) ||
+            nd.cw >= (1 << 16) || nc >= (1 << 16))
+            return "supernode cells do not form a rectangle";
+        for (int e = 0; e < pc.s[k]; ++e) {
+            const int cell = e % nc, q = e / nc;
+            const int b = nd.cx0 + cell % nd.cw + (nd.cy0 + cell / nd.cw) * Nx + q * Nx * Ny;
+            if (pc.perm[pc.start[k] + e] != b) return "supernode order is not the cell rectangle";
+        }
+        pc.cell0[k] = nd.cx0 | (nd.cy0 << 16);
+        pc.cellw[k] = nd.cw | (nc << 16);
+    }
     // update sets: lateral neighbours of the subtree box, every plane
     auto elim = [&](int cell, int q) {
         int k = lt.owner[cell];

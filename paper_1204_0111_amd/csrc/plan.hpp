@@ -33,10 +33,18 @@ constexpr int N_FWD_SHAPES = 5, N_BWD_SHAPES = 6;
 constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512}, {16, 512}, {32, 256}};
 constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256}};
 constexpr int SOLVE_SMALL_BLOCK_N = 512;
+// Depths with at least this many fronts (over all panels and problems) apply
+// the Schur updates left-looking: each block column once, before its pivots
+// are factored, and F_BR once at the end -- every entry is read and written
+// once instead of once per earlier pivot block.  Shallower depths, with few
+// large fronts, keep the right-looking order, which has more tiles per launch.
+constexpr int LEFT_LOOKING_MIN_FRONTS = 64;
 
 struct LatNode {
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     std::vector<int> cells;  // lateral index a1 + a2 * Nx, a1 fastest
+    // the cells form a rectangle: first cell (cx0, cy0), cw cells per row
+    int cx0 = 0, cy0 = 0, cw = 0;
     int child[2] = {-1, -1};
     int parent = -1;
     int depth = 0;
@@ -57,6 +65,10 @@ struct PanelClass {
     int Nx = 0, Ny = 0, nz = 0, leaf = 0;
     int naux = 0, nfront = 0, maxdepth = 0;
     std::vector<int> perm, iperm;  // elimination position <-> box index a1 + a2 Nx + q Nx Ny
+    // per front, its cell rectangle packed in 16-bit halves: (x0 | y0 << 16)
+    // and (cells per row | cells << 16); pivot e of the front is cell e mod
+    // cells of that rectangle (row-major) on plane e / cells
+    std::vector<int> cell0, cellw;
     std::vector<int> start, s, u, parent, child0, child1, depth;
     std::vector<int> uoff, ulist;  // update sets, concatenated (elimination positions)
     std::vector<int> moff, cmap;   // per front 2 (s+u) entries: position in child 0 / 1 update set or -1

@@ -32,6 +32,15 @@ __device__ inline Cx<double> plane_coupling(const PassArgs<T>& A, int lat) {
     return scale(c, -A.inv_h2);
 }
 
+// Box index (a1 + a2 Nx + q Nx Ny) of pivot e of a front from its cell rectangle.
+__device__ inline int pivot_box(const SolveItem& it, int Nx, int NxNy, int e) {
+    const int x0 = it.cell0 & 0xffff, y0 = it.cell0 >> 16;
+    const int cw = it.cellw & 0xffff, nc = it.cellw >> 16;
+    const int q = e / nc, cell = e - q * nc;
+    const int r = cell / cw;
+    return x0 + (cell - r * cw) + (y0 + r) * Nx + q * NxNy;
+}
+
 template <typename T>
 __device__ inline Cx<T> keep(bool on, Cx<T> v) {
     return cx<T>(on ? v.re : (T)0, on ? v.im : (T)0);
@@ -92,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     // front vector: right-hand side on the panel plus the children's slots;
     // slots a child does not cover hold stale values and are masked out
     for (int k = tid; k < s; k += NT) {
-        const int b = A.perm[it.start + k];
+        const int b = pivot_box(it, A.Nx, A.NxNy, k);
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
         const bool h0 = map0[k] >= 0, h1 = map1[k] >= 0;
         bool live;
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
     bool oplane = false, onext = false;
     Cx<double> ocf = cx<double>(0, 0);
     if (own) {
-        const int b = A.perm[it.start + jl];
+        const int b = pivot_box(it, A.Nx, A.NxNy, jl);
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
         oplane = q >= A.ga;
         ogi = (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;

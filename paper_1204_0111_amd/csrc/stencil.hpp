@@ -64,10 +64,21 @@ __device__ inline Cx<double> diag_entry(const NodeStretch& s, double c, Cx<doubl
     return d;
 }
 
-// Coupling between a node and its upper neighbour along axis j (the node
-// holding s is the lower one): -P_j ie_j^+ / h^2.
-__device__ inline Cx<double> upper_coupling(const NodeStretch& s, int j, double inv_h2) {
-    return scale(axis_weight(s, j) * s.ip[j], -inv_h2);
+// Coupling between a node (a1, a2, q) and its upper neighbour along axis ax:
+// -P_ax ie_ax^+ / h^2, from the two other axes' node stretches and the
+// inverse half-node stretch above the node along ax.  The three table entries
+// are picked by pointer, so nothing is indexed at run time (a run-time index
+// into a local array would be placed in scratch memory).
+__device__ inline Cx<double> coupling_entry(const ProbDev& Q, const Cx<double>* et,
+                                            const Cx<double>* e3n, const Cx<double>* ie3h, int a1,
+                                            int a2, int q, int ax, double inv_h2) {
+    const Cx<double>* t1 = et + Q.e_off[0];
+    const Cx<double>* t2 = et + Q.e_off[1];
+    const Cx<double>* pa = ax == 0 ? t2 + a2 : t1 + a1;
+    const Cx<double>* pb = ax == 2 ? t2 + a2 : e3n + q;
+    const Cx<double>* pc = ax == 0 ? t1 + Q.N[0] + a1 + 1
+                                   : (ax == 1 ? t2 + Q.N[1] + a2 + 1 : ie3h + q + 1);
+    return scale((*pa * *pb) * *pc, -inv_h2);
 }
 
 __device__ inline Cx<double> kappa_sq(const ProbDev& Q, double alpha) {

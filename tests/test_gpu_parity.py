@@ -48,8 +48,13 @@ def medium():
 
 
 @pytest.fixture(scope="module")
-def small_oracle_factors(small):
-    P = small
+def wide():
+    # 7 x 7-cell leaves: fronts of up to ~200 pivots (several 64-pivot blocks)
+    # with nonempty update sets
+    return case(n=(10, 10, 4), gamma=2, d=2, leaf=7)
+
+
+def _oracle_factors(P):
     out = {}
     N = hz.padded_shape(P["n"], P["gamma"])
     nodes = nd.nested_dissection(N[0], N[1], P["leaf"])
@@ -63,6 +68,16 @@ def small_oracle_factors(small):
         L, d = ld.ldlt_unpivoted(Hp.toarray())
         out[i] = (perm, U, ld.front_blocks(L, d, nodes, U), [x.start for x in nodes])
     return out
+
+
+@pytest.fixture(scope="module")
+def small_oracle_factors(small):
+    return _oracle_factors(small)
+
+
+@pytest.fixture(scope="module")
+def wide_oracle_factors(wide):
+    return _oracle_factors(wide)
 
 
 def test_plan_matches_oracle_nested_dissection(small, small_oracle_factors):
@@ -96,6 +111,30 @@ def test_front_factors_match_dense_ldlt(small, small_oracle_factors, prec):
             assert rel(L, LF) <= TOL[prec], (i, f)
             if len(U[f]):
                 assert rel(F, FBL) <= TOL[prec], (i, f)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_update_orders_match_dense_ldlt(wide, wide_oracle_factors, prec, order):
+    """Right-looking (0) and left-looking (1) Schur updates over several 64-pivot
+    blocks both reproduce the oracle's factors and inverted fronts."""
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(wide, precision=prec)
+    S.set_option("update_order", order)
+    S.assemble(wide["c"])
+    S.setup()
+    multi = 0
+    for i, (perm, U, blocks, starts) in wide_oracle_factors.items():
+        for f, (dF, LF, FBL) in enumerate(blocks):
+            D, L, F = S.front(0, i, f)
+            multi += len(dF) > 64 and len(U[f]) > 0
+            assert rel(D, dF) <= TOL[prec], (i, f)
+            assert rel(L, LF) <= TOL[prec], (i, f)
+            if len(U[f]):
+                assert rel(F, FBL) <= TOL[prec], (i, f)
+            GT, GB = ld.selective_inverse(LF, FBL)
+            assert rel(S.front_inverse(0, i, f), np.vstack([GT, GB])) <= TOL[prec], (i, f)
+    assert multi > 0
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
