@@ -1,7 +1,7 @@
 """Benchmark: unknowns/s to FP64 relative residual 1e-5, complex64 sweep vs complex128 sweep.
 
-A step is one whole solve of the 50^3 workload (second benchmark
-configuration): assembly, setup (factor and invert every panel) and
+A step is one whole solve of the 50^3 Gaussian-random-field workload
+(workload "grf50"): assembly, setup (factor and invert every panel) and
 flexible GMRES(20) in FP64 until the true relative residual is below 1e-5,
 with the fronts and the sweep in complex64.  The velocity and the
 right-hand side are resident on the device before timing starts.
@@ -30,7 +30,7 @@ KERNEL_CLASSES = ["fwd", "bwd", "diag", "panel", "trailing", "assemble", "invers
 KERNEL_INFO = {"fwd": ("k_fwd", "hbm", "solve.hip"), "bwd": ("k_bwd", "hbm", "solve.hip"),
                "diag": ("k_ldlt_diag", "hbm", "factor.hip"),
                "panel": ("k_panel_trsm", "hbm", "factor.hip"),
-               "trailing": ("k_trailing", "mfma", "factor.hip"),
+               "trailing": ("k_update", "mfma", "factor.hip"),
                "assemble": ("k_assemble", "hbm", "factor.hip"),
                "inverse": ("k_inverse", "mfma", "factor.hip"),
                "matvec": ("k_matvec", "hbm", "krylov.hip")}

@@ -18,7 +18,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = {"k_fwd": "solve.hip", "k_bwd": "solve.hip", "k_trailing": "factor.hip",
-       "k_inverse": "factor.hip", "k_panel_trsm": "factor.hip", "k_ldlt_diag": "factor.hip",
+       "k_update": "factor.hip", "k_inverse": "factor.hip", "k_panel_trsm": "factor.hip", "k_ldlt_diag": "factor.hip",
        "k_assemble": "factor.hip", "k_matvec": "krylov.hip"}
 COPY_BYTES = 512 * (1 << 20)
 
