@@ -15,6 +15,7 @@
 
 #include "devtypes.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 #include "stencil.hpp"
 
 namespace hsw {
@@ -117,30 +118,7 @@ __global__ __launch_bounds__(256) void k_assemble(const int2* __restrict__ work,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Matrix-core helpers.  A complex 64 x 64 tile product is four real products
-// per 16 x 16 x 4 step (no complex MFMA exists), FP32 MFMA for complex64 and
-// FP64 MFMA for complex128, accumulating in the same precision.
-typedef float mf4 __attribute__((ext_vector_type(4)));
-typedef double md4 __attribute__((ext_vector_type(4)));
-template <typename T> struct MfmaAcc;
-template <> struct MfmaAcc<float> { typedef mf4 type; };
-template <> struct MfmaAcc<double> { typedef md4 type; };
-__device__ inline mf4 mfma4(float a, float b, mf4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ inline md4 mfma4(double a, double b, md4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 constexpr int LDP = 64 + 4;  // padded row length of the planar LDS tiles
-
-// Output row of a 16 x 16 x 4 MFMA held by lane group lk = lane / 16 in register
-// r: FP32 places four consecutive rows per lane group, FP64 interleaves them
-// (row lk + 4 r); both hold column lane % 16.
-template <typename T> __device__ inline int mfma_out_row(int lk, int r);
-template <> __device__ inline int mfma_out_row<float>(int lk, int r) { return 4 * lk + r; }
-template <> __device__ inline int mfma_out_row<double>(int lk, int r) { return lk + 4 * r; }
 
 // acc += R C^T over KC columns for the 64 x 64 tile rows x cols: R (rows) and
 // C (cols) are planar LDS tiles [k][row]; wave w owns the 32 x 32 quadrant

@@ -971,6 +971,22 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
         }
         ++li;
     };
+    if (nrhs >= MM_MIN_RHS && force_f < 0) {  // matrix-core passes, 16 right-hand sides per group
+        A.mode = gmode;
+        for (int d = c.maxdepth; d >= 0; --d) {
+            const int fs = mm_fwd_shape<T>();
+            A.items = ctx->d_sitems + lv[d].foff[fs];
+            run("fwd", lv[d].fcount[fs], es * lv[d].g_entries * ((nrhs + 15) / 16) + nrhs * lv[d].fwd_vec_bytes,
+                8.0 * nrhs * lv[d].cmac, [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], st); });
+        }
+        A.mode = emode;
+        for (int d = 0; d <= c.maxdepth; ++d) {
+            A.items = ctx->d_sitems + lv[d].boff[MM_BWD_SHAPE];
+            run("bwd", lv[d].bcount[MM_BWD_SHAPE], es * lv[d].g_entries * ((nrhs + 15) / 16) + nrhs * lv[d].bwd_vec_bytes,
+                8.0 * nrhs * lv[d].cmac, [&] { launch_bwd_mm<T>(A, lv[d].bcount[MM_BWD_SHAPE], st); });
+        }
+        return;
+    }
     A.mode = gmode;
     for (int d = c.maxdepth; d >= 0; --d) {
         const int k = force_f >= 0 ? force_f : lv[d].fsel[key];
@@ -998,7 +1014,7 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
 template <typename T>
 static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     const int key = rhs_key(nrhs);
-    if (!ctx->autotune || ctx->tuned[key]) return HSW_OK;
+    if (!ctx->autotune || ctx->tuned[key] || nrhs >= MM_MIN_RHS) return HSW_OK;
     constexpr int REPS = 3;
     const int NS = std::max(N_FWD_SHAPES, N_BWD_SHAPES);
     int64_t plen = 1;

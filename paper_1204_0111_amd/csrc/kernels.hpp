@@ -56,6 +56,10 @@ void launch_fwd(const PassArgs<T>& A, int nwork, int rb, int smax, int nmax, hip
 template <typename T>
 void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t st);
 template <typename T>
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
+template <typename T>
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
+template <typename T>
 int solve_rhs_chunk(int nrhs, int nmax);
 
 // assemble.hip

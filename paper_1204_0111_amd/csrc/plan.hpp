@@ -29,9 +29,18 @@ constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
 struct PassShape {
     int block, threads;
 };
-constexpr int N_FWD_SHAPES = 5, N_BWD_SHAPES = 6;
+constexpr int N_FWD_SHAPES = 5, N_BWD_SHAPES = 7;
 constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512}, {16, 512}, {32, 256}};
-constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256}};
+constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256},
+                                                {64, 256}};
+// Groups of at least this many right-hand sides use the matrix-core passes,
+// 16 right-hand sides per group: forward 64 rows per workgroup in complex64
+// (shape 0), 16 in complex128 (shape 1, fewer registers); backward 16
+// columns (shape 4).
+constexpr int MM_MIN_RHS = 16;
+constexpr int MM_BWD_SHAPE = 4;
+template <typename T> struct MmFwdTiles { static constexpr int value = sizeof(T) == 4 ? 4 : 1; };
+template <typename T> constexpr int mm_fwd_shape() { return MmFwdTiles<T>::value == 4 ? 0 : 1; }
 constexpr int SOLVE_SMALL_BLOCK_N = 512;
 // Depths with at least this many fronts (over all panels and problems) apply
 // the Schur updates left-looking: each block column once, before its pivots

@@ -20,6 +20,7 @@
 // receiver's order, so no pass reads through an index it has to load first.
 #include "devtypes.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace hsw {
 
@@ -348,6 +349,267 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Passes for groups of 16 right-hand sides on the matrix cores: the products
+// G v_S and G^T [x_S; -x_U] of the panel solves become GEMMs with 16 columns
+// (the sweeps of many sources applied at once).  A workgroup covers 64 rows
+// (forward) or 16 columns (backward) of one front for 16 right-hand sides;
+// its four waves split the contraction into interleaved 16-entry chunks, each
+// wave with its own LDS staging and the next chunk's loads in flight, and
+// their partial 16 x 16 blocks are summed through LDS at the end.  Complex
+// products are four real 16 x 16 x 4 products (FP32 for complex64, FP64 for
+// complex128).  Inputs, outputs and the exchanges between fronts are those of
+// k_fwd / k_bwd.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// RT row tiles of 16 per workgroup: each wave updates all of them over its
+// quarter of the contraction (the front vector is staged once per RT tiles).
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
+    typedef typename MfmaAcc<T>::type V4;
+    constexpr int KC = 16;
+    const SolveItem it = A.items[blockIdx.x];  // items of 16 RT rows
+    const int n = it.n, s = it.s;
+    const int rhs0 = blockIdx.y * 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int kend = (it.blk + 16 * RT <= s) ? it.blk + 16 * RT : s;
+    __shared__ T Vre[4][KC][17], Vim[4][KC][17];  // per wave: front-vector chunk [entry][rhs]
+    __shared__ T Yre[16 * RT][17], Yim[16 * RT][17];  // the block's sum [row][rhs]
+    const int* map0 = A.cmap + it.moff;
+    const int* map1 = map0 + n;
+    auto vget = [&](int k, int r) -> Cx<T> {
+        const int64_t rr = rhs0 + r;
+        if (k >= kend || rr >= A.nrhs) return cx<T>(0, 0);
+        const int b = pivot_box(it, A.Nx, A.NxNy, k);
+        const int q = b / A.NxNy, lat = b - q * A.NxNy;
+        const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
+        Cx<T> v = keep(map0[k] >= 0, cc[k]) + keep(map1[k] >= 0, cc[n + k]);
+        if (A.mode == 0) {
+            if (q >= A.ga)
+                v = v + ccast<T>(A.src[rr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat]);
+        } else if (q == A.nz - 1) {
+            v = v + ccast<T>(plane_coupling(A, lat) * A.src[rr * A.ld + (int64_t)(A.hi - A.plane0) * A.NxNy + lat]);
+        }
+        return v;
+    };
+    // this lane feeds rows blk + 16 t + li (t < RT) to the products
+    const Cx<T>* g = A.G + it.loff;
+    auto gget = [&](int t, int k) -> Cx<T> {
+        const int row = it.blk + 16 * t + li;
+        return (row < n && k < kend) ? g[(int64_t)k * n + row] : cx<T>(0, 0);
+    };
+    Cx<T> ga[RT][4], gn[RT][4], vv[4], vn[4];
+    auto load = [&](int c, Cx<T>(&gx)[RT][4], Cx<T>(&vx)[4]) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gx[t][q] = gget(t, c + 4 * q + lk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = lane + 64 * j;
+            vx[j] = vget(c + (e >> 4), e & 15);
+        }
+    };
+    V4 are[RT], aim[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        are[t] = V4{0, 0, 0, 0};
+        aim[t] = V4{0, 0, 0, 0};
+    }
+    const int nch = (kend + KC - 1) / KC;
+    int ch = wave;
+    if (ch < nch) load(ch * KC, ga, vv);
+    for (; ch < nch; ch += 4) {
+        const bool more = ch + 4 < nch;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = lane + 64 * j;
+            Vre[wave][e >> 4][e & 15] = vv[j].re;
+            Vim[wave][e >> 4][e & 15] = vv[j].im;
+        }
+        wave_lds_sync();
+        if (more) load((ch + 4) * KC, gn, vn);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T br = Vre[wave][4 * q + lk][li], bi = Vim[wave][4 * q + lk][li];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                are[t] = mfma4(ga[t][q].re, br, are[t]);
+                aim[t] = mfma4(ga[t][q].re, bi, aim[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                are[t] = mfma4(-ga[t][q].im, bi, are[t]);
+                aim[t] = mfma4(ga[t][q].im, br, aim[t]);
+            }
+        }
+        wave_lds_sync();
+        if (more) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ga[t][q] = gn[t][q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vv[j] = vn[j];
+        }
+    }
+    // sum the four waves' partial blocks in LDS, one wave at a time
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + mfma_out_row<T>(lk, r);
+                    if (w == 0) {
+                        Yre[row][li] = are[t][r];
+                        Yim[row][li] = aim[t][r];
+                    } else {
+                        Yre[row][li] += are[t][r];
+                        Yim[row][li] += aim[t][r];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    // thread tid: rows blk + tid / 16 + 16 t, right-hand side rhs0 + tid % 16
+    const int64_t orr = rhs0 + (tid & 15);
+    if (orr >= A.nrhs) return;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int lrow = (tid >> 4) + 16 * t, row = it.blk + lrow;
+        if (row >= n) continue;
+        const Cx<T> y = cx<T>(Yre[lrow][tid & 15], Yim[lrow][tid & 15]);
+        if (row < s) {
+            A.xmid[orr * A.naux + it.start + row] = y * A.dinv[it.start + row];
+        } else {
+            const Cx<T>* cc = A.c2 + orr * A.c2ld + it.c2;
+            const Cx<T> pre = keep(map0[row] >= 0, cc[row]) + keep(map1[row] >= 0, cc[n + row]);
+            A.c2[orr * A.c2ld + it.push + A.pmap[it.pmap + row - s]] = pre - y;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
+    typedef typename MfmaAcc<T>::type V4;
+    constexpr int KC = 16;
+    const SolveItem it = A.items[blockIdx.x];  // items of 16 columns
+    const int n = it.n, s = it.s;
+    const int rhs0 = blockIdx.y * 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int c0 = it.blk;
+    __shared__ T Gre[4][KC][17], Gim[4][KC][17];  // per wave: G chunk [row][column]
+    __shared__ T Rre[4][KC][17], Rim[4][KC][17];  // per wave: [x_S; -x_U] chunk [row][rhs]
+    __shared__ T Yre[4][16][17], Yim[4][16][17];  // per wave: partial block [column][rhs]
+    // the first column block hands the update-set values on to the children
+    if (c0 == 0 && (it.cxu0 >= 0 || it.cxu1 >= 0)) {
+        for (int idx = tid; idx < (n - s) * 16; idx += 256) {
+            const int i = s + (idx >> 4);
+            const int64_t rr = rhs0 + (idx & 15);
+            if (rr >= A.nrhs) continue;
+            const Cx<T> xv = A.xu[rr * A.xuld + it.xu + i - s];
+            if (it.cxu0 >= 0) {
+                const int p0 = A.cmap[it.moff + i];
+                if (p0 >= 0) A.xu[rr * A.xuld + it.cxu0 + p0] = xv;
+            }
+            if (it.cxu1 >= 0) {
+                const int p1 = A.cmap[it.moff + n + i];
+                if (p1 >= 0) A.xu[rr * A.xuld + it.cxu1 + p1] = xv;
+            }
+        }
+    }
+    const Cx<T>* gb = A.G + it.loff;
+    auto rget = [&](int i, int r) -> Cx<T> {
+        const int64_t rr = rhs0 + r;
+        if (i >= n || rr >= A.nrhs) return cx<T>(0, 0);
+        return i < s ? A.xmid[rr * A.naux + it.start + i] : -A.xu[rr * A.xuld + it.xu + i - s];
+    };
+    auto gget = [&](int i, int j) -> Cx<T> { return (i < n && j < s) ? gb[(int64_t)j * n + i] : cx<T>(0, 0); };
+    Cx<T> gv[4], gn[4], rv[4], rn[4];
+    auto load = [&](int i0, Cx<T>(&gx)[4], Cx<T>(&rx)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = lane + 64 * j;
+            gx[j] = gget(i0 + (e & 15), c0 + (e >> 4));  // 16 consecutive rows of a column
+            rx[j] = rget(i0 + (e >> 4), e & 15);
+        }
+    };
+    V4 are = V4{0, 0, 0, 0}, aim = V4{0, 0, 0, 0};
+    const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
+    int ch = wave;
+    if (ch < nch) load(c0 + ch * KC, gv, rv);
+    for (; ch < nch; ch += 4) {
+        const bool more = ch + 4 < nch;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = lane + 64 * j;
+            Gre[wave][e & 15][e >> 4] = gv[j].re;
+            Gim[wave][e & 15][e >> 4] = gv[j].im;
+            Rre[wave][e >> 4][e & 15] = rv[j].re;
+            Rim[wave][e >> 4][e & 15] = rv[j].im;
+        }
+        wave_lds_sync();
+        if (more) load(c0 + (ch + 4) * KC, gn, rn);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = 4 * q + lk;
+            const T ar = Gre[wave][kk][li], ai = Gim[wave][kk][li];
+            const T br = Rre[wave][kk][li], bi = Rim[wave][kk][li];
+            are = mfma4(ar, br, are);
+            aim = mfma4(ar, bi, aim);
+            are = mfma4(-ai, bi, are);
+            aim = mfma4(ai, br, aim);
+        }
+        wave_lds_sync();
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                gv[j] = gn[j];
+                rv[j] = rn[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Yre[wave][mfma_out_row<T>(lk, r)][li] = are[r];
+        Yim[wave][mfma_out_row<T>(lk, r)][li] = aim[r];
+    }
+    __syncthreads();
+    // thread tid: column c0 + tid / 16, right-hand side rhs0 + tid % 16
+    const int j = c0 + (tid >> 4);
+    const int64_t orr = rhs0 + (tid & 15);
+    if (j >= s || orr >= A.nrhs) return;
+    Cx<T> x = cx<T>(0, 0);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) x = x + cx<T>(Yre[w][tid >> 4][tid & 15], Yim[w][tid >> 4][tid & 15]);
+    if (it.cxu0 >= 0) {
+        const int o0 = A.cmap[it.moff + j];
+        if (o0 >= 0) A.xu[orr * A.xuld + it.cxu0 + o0] = x;
+    }
+    if (it.cxu1 >= 0) {
+        const int o1 = A.cmap[it.moff + n + j];
+        if (o1 >= 0) A.xu[orr * A.xuld + it.cxu1 + o1] = x;
+    }
+    const int b = pivot_box(it, A.Nx, A.NxNy, j);
+    const int q = b / A.NxNy, lat = b - q * A.NxNy;
+    if (q < A.ga) return;
+    Cx<double>* up = A.dst + orr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
+    const Cx<double> xd = ccast<double>(x);
+    if (A.mode == 0) {
+        *up = xd;
+        if (A.couple && q == A.nz - 1) up[A.NxNy] = up[A.NxNy] - plane_coupling(A, lat) * xd;
+    } else {
+        *up = *up - xd;
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T, int RC, int RB, int NT>
 static void fwd_rc(const PassArgs<T>& A, int nwork, int smax, hipStream_t st) {
     size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + (size_t)(NT / 64) * RB * RC);
@@ -412,13 +674,27 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t 
         case 2: bwd_cfg<T, BWD_SHAPES[2].block, BWD_SHAPES[2].threads>(A, nwork, nmax, st); break;
         case 3: bwd_cfg<T, BWD_SHAPES[3].block, BWD_SHAPES[3].threads>(A, nwork, nmax, st); break;
         case 4: bwd_cfg<T, BWD_SHAPES[4].block, BWD_SHAPES[4].threads>(A, nwork, nmax, st); break;
-        default: bwd_cfg<T, BWD_SHAPES[5].block, BWD_SHAPES[5].threads>(A, nwork, nmax, st); break;
+        case 5: bwd_cfg<T, BWD_SHAPES[5].block, BWD_SHAPES[5].threads>(A, nwork, nmax, st); break;
+        default: bwd_cfg<T, BWD_SHAPES[6].block, BWD_SHAPES[6].threads>(A, nwork, nmax, st); break;
     }
+}
+
+template <typename T>
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
+    if (nwork <= 0) return;
+    HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value>), dim3(nwork, (A.nrhs + 15) / 16), dim3(256), 0, st, A);
+}
+template <typename T>
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
+    if (nwork <= 0) return;
+    HSW_LAUNCH(k_bwd_mm<T>, dim3(nwork, (A.nrhs + 15) / 16), dim3(256), 0, st, A);
 }
 
 #define HSW_INST(T)                                                                          \
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
+    template void launch_fwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
+    template void launch_bwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
     template int solve_rhs_chunk<T>(int, int);
 HSW_INST(float)
 HSW_INST(double)

@@ -114,3 +114,23 @@ def test_20cubed_solve_matches_oracle_iterations():
     x = xs[0].cpu().numpy()[0]
     assert np.linalg.norm(b[0] - A @ x) / np.linalg.norm(b[0]) < 1e-5
     assert abs(info["iters"][0] - ref["iters"]) <= 1, (info["iters"][0], ref["iters"])
+
+
+def test_layered100_sixteen_shots_as_one_block():
+    """The 100^3 layered workload, 16 surface shots solved as one block (the
+    matrix-core passes): every shot reaches the FP64 true residual 1e-5 with
+    the oracle's operator, and complex64 needs at most 1.2x the complex128
+    iterations (plus one)."""
+    P = wl.make_problem("layered100")
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(P["nrhs"], -1)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    its = {}
+    for prec in ["c128", "c64"]:
+        S = _solver(P, prec)
+        xs, info = S.solve([torch.as_tensor(b).to("cuda")], rtol=1e-5, restart=20)
+        x = xs[0].cpu().numpy()
+        S.close()
+        for r in range(P["nrhs"]):
+            assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5, (prec, r)
+        its[prec] = max(info["iters"])
+    assert its["c64"] <= 1.2 * its["c128"] + 1, its

@@ -162,7 +162,7 @@ def test_panel_solve_matches_oracle(medium, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("nrhs", [1, 5, 17])
 def test_sweep_matches_oracle(medium, prec, nrhs):
     P = medium
     S = _solver(P, prec)
