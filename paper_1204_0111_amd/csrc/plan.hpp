@@ -29,10 +29,11 @@ constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
 struct PassShape {
     int block, threads;
 };
-constexpr int N_FWD_SHAPES = 5, N_BWD_SHAPES = 7;
-constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512}, {16, 512}, {32, 256}};
+constexpr int N_FWD_SHAPES = 8, N_BWD_SHAPES = 9;
+constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512}, {16, 512}, {32, 256},
+                                                {8, 256},  {8, 512},  {32, 512}};
 constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256},
-                                                {64, 256}};
+                                                {64, 256}, {2, 128}, {4, 128}};
 // Groups of at least this many right-hand sides use the matrix-core passes,
 // 16 right-hand sides per group: forward 64 rows per workgroup in complex64
 // (shape 0), 16 in complex128 (shape 1, fewer registers); backward 16

@@ -662,7 +662,10 @@ void launch_fwd(const PassArgs<T>& A, int nwork, int cfg, int smax, int nmax, hi
         case 1: fwd_cfg<T, FWD_SHAPES[1].block, FWD_SHAPES[1].threads>(A, nwork, smax, nmax, st); break;
         case 2: fwd_cfg<T, FWD_SHAPES[2].block, FWD_SHAPES[2].threads>(A, nwork, smax, nmax, st); break;
         case 3: fwd_cfg<T, FWD_SHAPES[3].block, FWD_SHAPES[3].threads>(A, nwork, smax, nmax, st); break;
-        default: fwd_cfg<T, FWD_SHAPES[4].block, FWD_SHAPES[4].threads>(A, nwork, smax, nmax, st); break;
+        case 4: fwd_cfg<T, FWD_SHAPES[4].block, FWD_SHAPES[4].threads>(A, nwork, smax, nmax, st); break;
+        case 5: fwd_cfg<T, FWD_SHAPES[5].block, FWD_SHAPES[5].threads>(A, nwork, smax, nmax, st); break;
+        case 6: fwd_cfg<T, FWD_SHAPES[6].block, FWD_SHAPES[6].threads>(A, nwork, smax, nmax, st); break;
+        default: fwd_cfg<T, FWD_SHAPES[7].block, FWD_SHAPES[7].threads>(A, nwork, smax, nmax, st); break;
     }
 }
 template <typename T>
@@ -675,7 +678,9 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t 
         case 3: bwd_cfg<T, BWD_SHAPES[3].block, BWD_SHAPES[3].threads>(A, nwork, nmax, st); break;
         case 4: bwd_cfg<T, BWD_SHAPES[4].block, BWD_SHAPES[4].threads>(A, nwork, nmax, st); break;
         case 5: bwd_cfg<T, BWD_SHAPES[5].block, BWD_SHAPES[5].threads>(A, nwork, nmax, st); break;
-        default: bwd_cfg<T, BWD_SHAPES[6].block, BWD_SHAPES[6].threads>(A, nwork, nmax, st); break;
+        case 6: bwd_cfg<T, BWD_SHAPES[6].block, BWD_SHAPES[6].threads>(A, nwork, nmax, st); break;
+        case 7: bwd_cfg<T, BWD_SHAPES[7].block, BWD_SHAPES[7].threads>(A, nwork, nmax, st); break;
+        default: bwd_cfg<T, BWD_SHAPES[8].block, BWD_SHAPES[8].threads>(A, nwork, nmax, st); break;
     }
 }
 
