@@ -167,8 +167,11 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
 // ldR(k, row) and ldC(k, col) in chunks of KC columns.  Software pipelined:
 // the loads of chunk c + 1 are in flight while chunk c runs on the matrix
 // cores from one of two LDS buffers, so one barrier per chunk suffices.
-// Ends with a barrier; the caller's LDS buffers are free afterwards.
-template <typename T, int KC, typename LR, typename LC>
+// CT picks the thread mapping of the C loads: false, consecutive threads read
+// consecutive cols (contiguous when C is stored [k][col]); true, consecutive
+// k (contiguous when C is stored [col][k]).  Ends with a barrier; the
+// caller's LDS buffers are free afterwards.
+template <typename T, int KC, bool CT = false, typename LR, typename LC>
 __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
                                     typename MfmaAcc<T>::type (&aim)[2][2], int K, LR ldR, LC ldC,
                                     T (*Rre)[KC][LDP], T (*Rim)[KC][LDP], T (*Cre)[KC][LDP],
@@ -178,12 +181,23 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
     const int nch = (K + KC - 1) / KC;
     if (nch <= 0) return;
     Cx<T> r[PER], c[PER];
+    auto cmap_ = [](int idx, int& a, int& m) {
+        if (CT) {
+            m = idx % KC;
+            a = idx / KC;
+        } else {
+            a = idx & 63;
+            m = idx >> 6;
+        }
+    };
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + 256 * q, a = idx & 63, kk = k0 + (idx >> 6);
             r[q] = kk < K ? ldR(kk, a) : cx<T>(0, 0);
-            c[q] = kk < K ? ldC(kk, a) : cx<T>(0, 0);
+            int ca, cm;
+            cmap_(idx, ca, cm);
+            c[q] = k0 + cm < K ? ldC(k0 + cm, ca) : cx<T>(0, 0);
         }
     };
     auto put = [&](int buf) {
@@ -192,8 +206,10 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
             const int idx = tid + 256 * q, a = idx & 63, m = idx >> 6;
             Rre[buf][m][a] = r[q].re;
             Rim[buf][m][a] = r[q].im;
-            Cre[buf][m][a] = c[q].re;
-            Cim[buf][m][a] = c[q].im;
+            int ca, cm;
+            cmap_(idx, ca, cm);
+            Cre[buf][cm][ca] = c[q].re;
+            Cim[buf][cm][ca] = c[q].im;
         }
     };
     fetch(0);
@@ -496,7 +512,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
-    cgemm64_pipe<T, KC>(
+    cgemm64_pipe<T, KC, true>(  // L_kk^{-1}(a, m) is contiguous in m: transposed C loads
         are, aim, b,
         [&](int m, int a) { return rbeg + a < rend ? L[(int64_t)(k + m) * n + rbeg + a] : cx<T>(0, 0); },
         [&](int m, int a) {
@@ -674,8 +690,9 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 are[bi][bj] = V4{0, 0, 0, 0};
                 aim[bi][bj] = V4{0, 0, 0, 0};
             }
-        // sum over the later pivot columns m >= c1: X(rows, m) L(m, blk)
-        cgemm64_pipe<T, KC>(
+        // sum over the later pivot columns m >= c1: X(rows, m) L(m, blk); L(m, c0 + a)
+        // is contiguous in m, so its loads use the transposed mapping
+        cgemm64_pipe<T, KC, true>(
             are, aim, s - c1,
             [&](int m, int a) { return r0 + a < n ? G[(int64_t)(c1 + m) * n + r0 + a] : cx<T>(0, 0); },
             [&](int m, int a) { return a < bw ? L[(int64_t)(c0 + a) * n + c1 + m] : cx<T>(0, 0); },
