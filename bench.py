@@ -40,23 +40,28 @@ PROFILES = os.path.join(ROOT, "profiles")
 def workload(name):
     from paper_1204_0111_amd import workloads as wl
     P = wl.make_problem(name)
-    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"])
-    return P, b.reshape(b.shape[0], -1)
+    return P, wl.sources(P)
 
 
 MODEL_TEXT = {"constant": "constant velocity 1",
               "grf": "Gaussian-random-field velocity in [1,3]",
               "layered": "8 dipping layers, velocity 1.5-6.0 with 5% noise",
-              "wedge_salt": "wedge layers 2.0/3.0/4.5 with a c=4.5 salt body and 3% noise"}
+              "wedge_salt": "wedge layers 2.0/3.0/4.5 with a c=4.5 salt body and 3% noise",
+              "barrier": "unit velocity with a c=1e10 barrier slab (Sec. 3)",
+              "wedge_paper": "three-layer wedge 2/1.5/3 (Sec. 3)",
+              "two_layer": "two layers 4/1 split at x2=0.5 (Sec. 3)",
+              "waveguide": "Gaussian waveguide 1.25(1-0.4exp(-32r^2)) (Sec. 3)"}
 
 
 def describe(P):
     from paper_1204_0111_amd import workloads as wl
     model = MODEL_TEXT[wl.WORKLOADS[P["name"]]["model"]]
+    src = ("the four forcings f0-f3 of Sec. 3" if P["src"] == "paper"
+           else "%d Gaussian point source(s)" % P["nrhs"])
     return dict(workload="%dx%dx%d interior, %s, 10 points per wavelength, PML gamma=%d "
-                         "(amplitude %.1f), panel depth %d, ND leaf %d, %d Gaussian point source(s), "
+                         "(amplitude %.1f), panel depth %d, ND leaf %d, %s, "
                          "GMRES(20) to FP64 rel-res 1e-5"
-                         % (P["n"] + (model, P["gamma"], P["C"], P["d"], P["leaf"], P["nrhs"])),
+                         % (P["n"] + (model, P["gamma"], P["C"], P["d"], P["leaf"], src)),
                 name=P["name"], n=list(P["n"]), gamma=P["gamma"], panel_depth=P["d"],
                 leaf=P["leaf"], pml_amp=P["C"], alpha=P["alpha"], omega=P["omega"],
                 nrhs=P["nrhs"])

@@ -38,6 +38,17 @@ WORKLOADS = {
     # 250^3 wedge with a salt body, 32 surface shots
     "wedge250": dict(seed=5, n=(250, 250, 250), gamma=12, d=4, leaf=4, model="wedge_salt",
                      nrhs=32, src="surface", C=30.0),
+    # the analytic models of Sec. 3 at 50^3 (5 PML points, 4 planes per panel
+    # as in Table 3.1), each with the four forcings f0..f3 as one block; C is
+    # the amplitude the search over {2,3,4,7.5,10,15,20,30,45,60} picked
+    "barrier50": dict(seed=6, n=(50, 50, 50), gamma=5, d=4, leaf=4, model="barrier", nrhs=4,
+                      src="paper", C=15.0),
+    "wedge50": dict(seed=7, n=(50, 50, 50), gamma=5, d=4, leaf=4, model="wedge_paper", nrhs=4,
+                    src="paper", C=20.0),
+    "twolayer50": dict(seed=8, n=(50, 50, 50), gamma=5, d=4, leaf=4, model="two_layer", nrhs=4,
+                       src="paper", C=15.0),
+    "waveguide50": dict(seed=9, n=(50, 50, 50), gamma=5, d=4, leaf=4, model="waveguide", nrhs=4,
+                        src="paper", C=15.0),
 }
 
 
@@ -125,6 +136,53 @@ def velocity_waveguide(n, h):
     return 1.25 * (1.0 - 0.4 * np.exp(-32.0 * ((X1 - 0.5) ** 2 + (X2 - 0.5) ** 2)))
 
 
+def velocity_wedge_paper(n, h):
+    """Sec. 3 wedge model over the unit cube: c = 2 where x3 <= 0.4 + 0.1 x2,
+    else 1.5 where x3 <= 0.8 - 0.2 x2, else 3."""
+    X1, X2, X3 = _mesh(n, h)
+    return np.where(X3 <= 0.4 + 0.1 * X2, 2.0, np.where(X3 <= 0.8 - 0.2 * X2, 1.5, 3.0))
+
+
+def velocity_two_layer(n, h):
+    """Sec. 3 two-layer model: c = 4 where x2 < 0.5, else 1."""
+    X1, X2, X3 = _mesh(n, h)
+    return np.where(X2 < 0.5, 4.0, 1.0)
+
+
+# Points and direction of the four forcings of Sec. 3.
+FORCING_X0 = (0.5, 0.5, 0.1)
+FORCING_X1 = (0.25, 0.25, 0.1)
+FORCING_X2 = (0.75, 0.75, 0.5)
+FORCING_D = tuple(np.array([1.0, 1.0, -1.0]) / np.sqrt(3.0))
+
+
+def paper_forcings(n, gamma, h, omega):
+    """The four right-hand sides of Sec. 3 on the padded grid, zero outside
+    the interior (the PML padding carries no source):
+      f0 = m exp(-10 m |x - x0|^2)                  a shot,
+      f1 = sum over x0, x1, x2 of the same shot     three shots,
+      f2 = exp(i w x.d) exp(-4 w |x - x2|^2)        a Gaussian beam,
+      f3 = exp(i w x.d)                             a plane wave,
+    with m the number of interior points per axis (the largest axis).
+    Returns (4, N3, N2, N1) complex128."""
+    X1, X2, X3 = padded_coords(n, gamma, h)
+    g = int(gamma)
+    inside = np.zeros(X1.shape, dtype=bool)
+    inside[g:g + int(n[2]), g:g + int(n[1]), g:g + int(n[0])] = True
+    m = float(max(int(v) for v in n))
+
+    def r2(p):
+        return (X1 - p[0]) ** 2 + (X2 - p[1]) ** 2 + (X3 - p[2]) ** 2
+
+    def shot(p):
+        return m * np.exp(-10.0 * m * r2(p))
+
+    phase = np.exp(1j * omega * (X1 * FORCING_D[0] + X2 * FORCING_D[1] + X3 * FORCING_D[2]))
+    f = [shot(FORCING_X0), shot(FORCING_X0) + shot(FORCING_X1) + shot(FORCING_X2),
+         phase * np.exp(-4.0 * omega * r2(FORCING_X2)), phase]
+    return np.stack([np.where(inside, v, 0.0).astype(np.complex128) for v in f])
+
+
 def padded_coords(n, gamma, h):
     """Coordinates of the padded nodes (x_j = (a_j - gamma + 1) h), numpy shape (N3, N2, N1)."""
     g = int(gamma)
@@ -178,18 +236,27 @@ def make_problem(name, scale_n=None, sub=0):
         n = tuple(int(v) for v in scale_n)
     h = grid_h(n)
     seed = seed_for(spec["seed"], sub)
-    if spec["model"] == "constant":
-        c = velocity_constant(n)
-    elif spec["model"] == "grf":
-        c = velocity_grf(n, h, seed)
-    elif spec["model"] == "layered":
-        c = velocity_layered(n, h, seed)
-    else:
-        c = velocity_wedge_salt(n, h, seed)
+    c = {"constant": lambda: velocity_constant(n), "grf": lambda: velocity_grf(n, h, seed),
+         "layered": lambda: velocity_layered(n, h, seed),
+         "wedge_salt": lambda: velocity_wedge_salt(n, h, seed),
+         "barrier": lambda: velocity_barrier(n, h), "wedge_paper": lambda: velocity_wedge_paper(n, h),
+         "two_layer": lambda: velocity_two_layer(n, h),
+         "waveguide": lambda: velocity_waveguide(n, h)}[spec["model"]]()
     if spec["src"] == "centre":
         centers = np.array([[0.5, 0.5, 0.5]])
+    elif spec["src"] == "paper":
+        centers = None  # the four forcings of Sec. 3 (sources())
     else:
         centers = surface_centers(spec["nrhs"], seed + 7)
     return dict(name=name, n=n, h=h, c=c, omega=omega_for_ppw(c, h), alpha=ALPHA_DEFAULT,
                 gamma=spec["gamma"], C=spec["C"], d=spec["d"], leaf=spec["leaf"],
-                centers=centers, nrhs=len(centers))
+                centers=centers, src=spec["src"], nrhs=spec["nrhs"] if centers is None else len(centers))
+
+
+def sources(P):
+    """Right-hand sides of a workload made by make_problem: (nrhs, N_pad) complex128."""
+    if P["src"] == "paper":
+        f = paper_forcings(P["n"], P["gamma"], P["h"], P["omega"])
+    else:
+        f = gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"])
+    return f.reshape(f.shape[0], -1)

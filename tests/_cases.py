@@ -8,13 +8,14 @@ from paper_1204_0111_amd import workloads as wl
 def case(n=(14, 12, 13), gamma=3, d=3, leaf=4, model="grf", seed=5, C=4.0, alpha=None):
     n = tuple(int(v) for v in n)
     h = wl.grid_h(n)
-    if model == "grf":
-        c = wl.velocity_grf(n, h, seed)
-    elif model == "layered":
-        c = wl.velocity_layered(n, h, seed)
-    else:
-        c = wl.velocity_constant(n)
-    return dict(n=n, h=h, c=c, omega=wl.omega_for_ppw(c, h),
+    c = {"grf": lambda: wl.velocity_grf(n, h, seed),
+         "layered": lambda: wl.velocity_layered(n, h, seed),
+         "constant": lambda: wl.velocity_constant(n),
+         "barrier": lambda: wl.velocity_barrier(n, h),
+         "wedge_paper": lambda: wl.velocity_wedge_paper(n, h),
+         "two_layer": lambda: wl.velocity_two_layer(n, h),
+         "waveguide": lambda: wl.velocity_waveguide(n, h)}[model]()
+    return dict(name=model, src="paper", n=n, h=h, c=c, omega=wl.omega_for_ppw(c, h),
                 alpha=wl.ALPHA_DEFAULT if alpha is None else alpha, gamma=gamma, C=C, d=d,
                 leaf=leaf)
 

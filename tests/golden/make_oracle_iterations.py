@@ -28,7 +28,7 @@ def run(name):
     P = wl.make_problem(name)
     S = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
     A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
-    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(P["nrhs"], -1)
+    b = wl.sources(P)
     its, rrs = [], []
     for r in range(P["nrhs"]):
         _, it, rr, _ = gm.gmres(lambda v: A @ v, S.apply, b[r], k=20, tol=1e-5, maxit=400)

@@ -30,8 +30,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 @pytest.fixture(scope="module")
 def grf50():
     P = wl.make_problem("grf50")
-    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
-    return P, b
+    return P, wl.sources(P)
 
 
 def _solver(P, prec):
@@ -106,7 +105,7 @@ def test_20cubed_solve_matches_oracle_iterations():
     P = wl.make_problem("const20")
     ref = json.load(open(os.path.join(GOLDEN, "oracle_iterations.json")))["const20"]
     assert abs(ref["C"] - P["C"]) < 1e-12
-    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(1, -1)
+    b = wl.sources(P)
     S = _solver(P, "c128")
     assert S.query(0, "m") == 20 and S.query(0, "fronts") == 31
     xs, info = S.solve([torch.as_tensor(b).to("cuda")], rtol=1e-5, restart=20)
@@ -122,7 +121,7 @@ def test_layered100_sixteen_shots_as_one_block():
     the oracle's operator, and complex64 needs at most 1.2x the complex128
     iterations (plus one)."""
     P = wl.make_problem("layered100")
-    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"], P["centers"]).reshape(P["nrhs"], -1)
+    b = wl.sources(P)
     A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
     its = {}
     for prec in ["c128", "c64"]:

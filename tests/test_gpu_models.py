@@ -1,0 +1,121 @@
+"""GPU parity on the analytic models and the four forcings of Sec. 3.
+
+At sizes the oracle finishes in seconds: the HIP sweep applied to f0..f3
+against the oracle's sweep, right-hand side by right-hand side (1e-12 in
+complex128, 1e-4 in complex64), and the GMRES iteration counts against the
+oracle's GMRES with the oracle's sweep (within one iteration in complex128).
+The PML studies run every candidate as one problem of a single context; their
+per-candidate iteration counts must match the oracle's, candidate by
+candidate.  At the 50^3 size of the model workloads: the FP64 true residual of
+every forcing with the oracle's operator, and the iteration count against the
+oracle's stored count (tests/golden/make_oracle_iterations.py, oracle only).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gmres as gm
+from oracle import helmholtz as hz
+from oracle import sweep as sw
+from paper_1204_0111_amd import workloads as wl
+from tests._cases import TOL, case, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MODELS = ["barrier", "wedge_paper", "two_layer", "waveguide"]
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solver(P, prec):
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(P, precision=prec)
+    S.assemble(P["c"])
+    S.setup()
+    return S
+
+
+def _small(model, **kw):
+    args = dict(n=(13, 12, 11), gamma=3, d=3, leaf=4, model=model, C=15.0)
+    args.update(kw)
+    return case(**args)
+
+
+def _oracle_iters(P, b):
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    return [gm.gmres(lambda v: A @ v, O.apply, b[r], k=20, tol=1e-5, maxit=400)[1]
+            for r in range(b.shape[0])]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("model", MODELS)
+def test_sweep_on_the_forcings_matches_oracle(model, prec):
+    P = _small(model)
+    f = wl.sources(P)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    S = _solver(P, prec)
+    z = S.apply(0, _cuda(f)).cpu().numpy()
+    ref = O.apply(f.T).T
+    for r in range(4):
+        assert rel(z[r], ref[r]) <= TOL[prec], (model, r)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_gmres_on_the_forcings_matches_oracle(model):
+    P = _small(model)
+    b = wl.sources(P)
+    S = _solver(P, "c128")
+    xs, info = S.solve([_cuda(b)], rtol=1e-5, restart=20)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    x = xs[0].cpu().numpy()
+    ref = _oracle_iters(P, b)
+    for r in range(4):
+        assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5, (model, r)
+        assert abs(info["iters"][r] - ref[r]) <= 1, (model, r, info["iters"], ref)
+
+
+@pytest.mark.parametrize("key,values", [("C", [2.0, 8.0, 30.0]), ("gamma", [2, 4])])
+def test_pml_study_counts_match_oracle(key, values):
+    from paper_1204_0111_amd import studies
+    P = _small("waveguide", n=(12, 11, 10))
+    out = studies.study(P, key, values, precision="c128")
+    assert [c["value"] for c in out["candidates"]] == values
+    for cand in out["candidates"]:
+        Q = dict(P, **{key: cand["value"]})
+        ref = _oracle_iters(Q, wl.sources(Q))
+        assert cand["converged"]
+        for a, b in zip(cand["iters_per_rhs"], ref):
+            assert abs(a - b) <= 1, (key, cand["value"], cand["iters_per_rhs"], ref)
+    assert out["best"] == studies.choose(out["candidates"])
+
+
+@pytest.mark.parametrize("name", ["barrier50", "wedge50", "twolayer50", "waveguide50"])
+def test_model_workload_full_size(name):
+    """Each 50^3 model workload, all four forcings as one block, in both
+    precisions: FP64 true residual below 1e-5 for every forcing, and the
+    iteration count against the oracle's stored count."""
+    P = wl.make_problem(name)
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_iterations.json")))[name]
+    assert abs(ref["C"] - P["C"]) < 1e-12, "stored count is for another PML amplitude"
+    b = wl.sources(P)
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    for prec in ["c128", "c64"]:
+        S = _solver(P, prec)
+        xs, info = S.solve([_cuda(b)], rtol=1e-5, restart=20)
+        x = xs[0].cpu().numpy()
+        S.close()
+        for r in range(4):
+            assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5, (prec, r)
+        it = max(info["iters"])
+        if prec == "c128":
+            assert abs(it - ref["iters"]) <= 1, (it, ref)
+        else:
+            assert it <= 1.2 * ref["iters"] + 1, (it, ref)
