@@ -95,3 +95,85 @@ def gmres(matvec, precond, b, k=20, tol=1e-5, maxit=1000):
         if np.linalg.norm(r) / bnorm < tol or iters >= maxit:
             break
     return x, iters, np.linalg.norm(r) / bnorm, history
+
+
+def block_gmres(matvec, precond, B, k=20, tol=1e-5, maxit=1000):
+    """Block GMRES(k): the columns of B share one block Krylov space (Sec. 2.4
+    names block variants as a way to lower the iteration count).
+
+    matvec and precond act on blocks (N x q arrays).  B is N x p.  Returns
+    (X, iters per column, relres per column, history of the largest in-cycle
+    estimate per iteration).
+
+    Readings (the paper only names the method):
+    * Right preconditioning and a zero initial guess, as for GMRES(k); one
+      iteration is one application of M^{-1} to the block of still active
+      columns, and a column's count is the number of iterations it took part in.
+    * Each cycle starts from the true residual block of the columns whose true
+      relative residual is still >= tol (converged columns leave the block at
+      a restart).  The residual block is split as R0 = V_0 S by a reduced QR.
+    * Arnoldi step j: W = A M^{-1} V_j; block modified Gram-Schmidt against
+      V_0..V_j (H_ij = V_i^H W, W -= V_i H_ij); reduced QR W = V_{j+1} H_{j+1,j}.
+    * The block least-squares problem min ||E_1 S - H_j Y|| (Frobenius norm,
+      which decouples by column) is solved by a library least-squares routine
+      after every step; column c's estimate is the norm of its residual
+      column, relative to ||b_c||.  The cycle ends when every active estimate
+      is below tol, after k steps, or when a diagonal entry of H_{j+1,j} falls
+      below 1e-14 times the largest one seen (the block Krylov space has
+      become invariant: rank breakdown).
+    * X += M^{-1} [V_0 .. V_j] Y, then the true residual decides.
+    """
+    B = np.asarray(B, dtype=np.complex128)
+    N, p = B.shape
+    bn = np.linalg.norm(B, axis=0)
+    X = np.zeros_like(B)
+    its = np.zeros(p, dtype=int)
+    rel = np.where(bn > 0, 1.0, 0.0)
+    history = []
+    total = 0
+    while True:
+        R = B - matvec(X)
+        for c in range(p):
+            if bn[c] > 0:
+                rel[c] = np.linalg.norm(R[:, c]) / bn[c]
+        act = [c for c in range(p) if bn[c] > 0 and rel[c] >= tol]
+        if not act or total >= maxit:
+            break
+        q = len(act)
+        V0, S = np.linalg.qr(R[:, act])
+        V = [V0]
+        Hcols = []  # block column j: ((j+2) q) x q
+        scale = np.max(np.abs(np.diag(S)))
+        jdone = 0
+        Y = None
+        for j in range(k):
+            W = matvec(precond(V[j]))
+            total += 1
+            its[act] += 1
+            col = np.zeros(((j + 2) * q, q), dtype=np.complex128)
+            for i in range(j + 1):
+                Hij = V[i].conj().T @ W
+                W = W - V[i] @ Hij
+                col[i * q:(i + 1) * q] = Hij
+            Vn, Rn = np.linalg.qr(W)
+            col[(j + 1) * q:] = Rn
+            Hcols.append(col)
+            jdone = j + 1
+            Hbar = np.zeros(((j + 2) * q, (j + 1) * q), dtype=np.complex128)
+            for jj, cj in enumerate(Hcols):
+                Hbar[:cj.shape[0], jj * q:(jj + 1) * q] = cj
+            E = np.zeros(((j + 2) * q, q), dtype=np.complex128)
+            E[:q] = S
+            Y = np.linalg.lstsq(Hbar, E, rcond=None)[0]
+            res = np.linalg.norm(E - Hbar @ Y, axis=0) / bn[act]
+            history.append(float(res.max()))
+            d = np.abs(np.diag(Rn))
+            scale = max(scale, float(d.max()))
+            if res.max() < tol or total >= maxit or d.min() <= 1e-14 * scale:
+                break
+            V.append(Vn)
+        VY = np.zeros((N, q), dtype=np.complex128)
+        for i in range(jdone):
+            VY = VY + V[i] @ Y[i * q:(i + 1) * q]
+        X[:, act] = X[:, act] + precond(VY)
+    return X, its, rel, history

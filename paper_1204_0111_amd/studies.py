@@ -5,9 +5,9 @@ each problem by a small search, and reports that one more PML grid point
 lowers the waveguide problem's iteration count sharply, so that the best PML
 size grows slowly with the frequency.  Both studies are loops of ordinary
 solves.  Here every candidate of a study is one problem of a single context:
-the candidates share every setup launch and every GMRES iteration (each
-right-hand side keeps its own Krylov basis), so a study costs about one
-batched solve instead of one solve per candidate.
+the candidates share every setup launch (each launch covers the fronts of one
+tree depth over all candidates), and their GMRES solves follow one another on
+the same factors' context.
 
 Usage (one JSON line per study on stdout):
 

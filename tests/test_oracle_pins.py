@@ -412,6 +412,69 @@ def test_gmres_restarted_converges_to_direct_solution():
     assert np.linalg.norm(x - ref) <= 1e-7 * np.linalg.norm(ref)
 
 
+def _dense_case(n, p, seed):
+    rng = np.random.default_rng(seed)
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Minv = np.diag(1.0 / np.diag(A))
+    B = rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p))
+    return A, Minv, B
+
+
+def test_block_gmres_with_one_column_is_gmres():
+    A, Minv, B = _dense_case(40, 1, 7)
+    x, it, rr, hist = gm.gmres(lambda v: A @ v, lambda v: Minv @ v, B[:, 0], k=5, tol=1e-9,
+                               maxit=60)
+    X, its, rel, bh = gm.block_gmres(lambda V: A @ V, lambda V: Minv @ V, B, k=5, tol=1e-9,
+                                     maxit=60)
+    assert its[0] == it and abs(rel[0] - rr) <= 1e-12
+    assert np.allclose(hist, bh, rtol=1e-9, atol=0)
+    assert np.linalg.norm(X[:, 0] - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_block_gmres_residual_is_minimal_over_block_krylov_space():
+    """Each in-cycle estimate equals, for the worst column, min ||r0_c - A M^{-1} K_j y||
+    over the block Krylov space K_j = [R0, (AM) R0, ..., (AM)^{j-1} R0] (brute force)."""
+    A, Minv, B = _dense_case(36, 3, 8)
+    X, its, rel, hist = gm.block_gmres(lambda V: A @ V, lambda V: Minv @ V, B, k=20,
+                                       tol=1e-14, maxit=8)
+    AM = A @ Minv
+    bn = np.linalg.norm(B, axis=0)
+    K = [B]
+    for j in range(1, 9):
+        Kj = np.column_stack(K)
+        worst = 0.0
+        for c in range(3):
+            y = np.linalg.lstsq(AM @ Kj, B[:, c], rcond=None)[0]
+            worst = max(worst, np.linalg.norm(B[:, c] - AM @ Kj @ y) / bn[c])
+        assert abs(hist[j - 1] - worst) <= 1e-8 * max(worst, 1e-12), (j, hist[j - 1], worst)
+        K.append(AM @ K[-1])
+    for c in range(3):
+        assert abs(rel[c] - np.linalg.norm(B[:, c] - A @ X[:, c]) / bn[c]) < 1e-14
+
+
+def test_block_gmres_terminates_in_n_over_p_steps():
+    """The block Krylov space of p columns reaches dimension n after n/p steps."""
+    A, Minv, B = _dense_case(24, 4, 9)
+    X, its, rel, _ = gm.block_gmres(lambda V: A @ V, lambda V: Minv @ V, B, k=10, tol=1e-10)
+    assert max(its) <= 6 and max(rel) < 1e-10
+
+
+def test_block_gmres_needs_no_more_iterations_than_gmres_per_column():
+    """K_j(AM, r_c) lies in the block space, so without restarts the block
+    method never needs more steps than any column's own GMRES; on the sweep
+    preconditioned Helmholtz problem it converges to the direct solution."""
+    n, h, c, om = _small(n=(6, 5, 5))
+    A = hz.helmholtz_operator(c, h, om, 2, 4.0)
+    S = sw.Sweep(c, h, om, wl.ALPHA_DEFAULT, 2, 4.0, d=2)
+    B = wl.random_complex((A.shape[0], 3), 11)
+    X, its, rel, _ = gm.block_gmres(lambda V: A @ V, S.apply, B, k=60, tol=1e-10, maxit=60)
+    for col in range(3):
+        _, it, _, _ = gm.gmres(lambda v: A @ v, S.apply, B[:, col], k=60, tol=1e-10, maxit=60)
+        assert its[col] <= it
+        ref = spla.spsolve(A.tocsc(), B[:, col])
+        assert np.linalg.norm(X[:, col] - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
 def test_givens_zeroes_subdiagonal():
     for a, b in [(1 + 2j, 0.5), (0.0, 2.0), (3 - 1j, 0.0), (1e-3j, 7.0)]:
         c, s = gm.givens(a, b)
