@@ -211,8 +211,9 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
                              double* seconds, double* bytes, double* flops);
 
 /*
- * Execution options of a context (not part of the method; results do not
- * depend on them beyond rounding order, and the sweep is deterministic):
+ * Options of a context.  All but "block_gmres" are execution options (not
+ * part of the method; results do not depend on them beyond rounding order,
+ * and the sweep is deterministic):
  *   "graph"    1: hsw_apply and hsw_solve replay the sweep of Alg. 1.5 as
  *              a HIP graph captured at the first application for a (problem,
  *              right-hand-side count), on a context-owned copy of the vector;
@@ -228,6 +229,16 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              pivots before it is factored, F_BR once at the end); 2 or -1
  *              (default) hybrid: right-looking over the pivot columns, F_BR
  *              once at the end.  The factors agree to rounding.
+ *   "block_gmres" 1: hsw_solve runs block GMRES(k) (Sec. 2.4 names block
+ *              variants of GMRES as a way to lower the iteration count): the
+ *              right-hand sides of a problem, in groups of at most 16, share
+ *              one block Krylov space; each iteration applies the sweep to
+ *              the group's still unconverged columns at once, and a column
+ *              leaves the block at a restart once its true relative residual
+ *              is below rtol.  iters[r] counts the iterations column r took
+ *              part in.  A group whose residual block is rank deficient
+ *              (dependent right-hand sides) is solved by GMRES(k) per column.
+ *              0 (default): GMRES(k) per right-hand side.
  * Returns HSW_E_INVAL for an unknown key or value.
  */
 hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);

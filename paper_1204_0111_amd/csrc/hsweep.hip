@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -138,6 +139,7 @@ struct hsw_ctx {
     // captured sweeps, their stream and the events joining it to st
     bool use_graph = false;  // measured slower than stream launches for the sweep
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
+    bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -759,6 +761,8 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->use_graph = value != 0;
     } else if (k == "autotune") {
         ctx->autotune = value != 0;
+    } else if (k == "block_gmres") {
+        ctx->block_gmres = value != 0;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
         ctx->update_order = (int)value;
@@ -1348,6 +1352,295 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
     return ok ? HSW_OK : HSW_E_NOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// Block flexible GMRES(k) (Sec. 2.4 names block variants of GMRES as a way to
+// lower the iteration count): the right-hand sides of one group (at most
+// BLOCK_KRYLOV_MAX) share one block Krylov space.  Each step applies the
+// sweep to the whole block, orthogonalises the new block against the basis
+// by block classical Gram-Schmidt applied twice (C = V^H W on the matrix
+// cores, W -= V C), and orthonormalises it by Cholesky QR applied twice
+// (W^H W = S^H S, W := W S^{-1}).  The small block least-squares problem is
+// reduced by complex Givens rotations on the host, which gives every
+// column's residual estimate after every step.  Columns whose true relative
+// residual is below rtol leave the block at a restart.
+namespace {
+using zc = std::complex<double>;
+
+// G = S^H S for a q x q Hermitian G (row-major); S upper triangular
+// (row-major).  Returns false if a pivot is not positive.
+bool chol_upper(const std::vector<zc>& G, int q, std::vector<zc>& S) {
+    S.assign((size_t)q * q, zc(0, 0));
+    for (int i = 0; i < q; ++i) {
+        double d = G[(size_t)i * q + i].real();
+        for (int k = 0; k < i; ++k) d -= std::norm(S[(size_t)k * q + i]);
+        if (!(d > 0)) return false;
+        const double sii = std::sqrt(d);
+        S[(size_t)i * q + i] = sii;
+        for (int j = i + 1; j < q; ++j) {
+            zc t = G[(size_t)i * q + j];
+            for (int k = 0; k < i; ++k) t -= std::conj(S[(size_t)k * q + i]) * S[(size_t)k * q + j];
+            S[(size_t)i * q + j] = t / sii;
+        }
+    }
+    return true;
+}
+
+// inverse of an upper triangular q x q matrix (row-major)
+std::vector<zc> inv_upper(const std::vector<zc>& S, int q) {
+    std::vector<zc> X((size_t)q * q, zc(0, 0));
+    for (int j = 0; j < q; ++j) {
+        X[(size_t)j * q + j] = 1.0 / S[(size_t)j * q + j];
+        for (int i = j - 1; i >= 0; --i) {
+            zc t = 0;
+            for (int k = i + 1; k <= j; ++k) t += S[(size_t)i * q + k] * X[(size_t)k * q + j];
+            X[(size_t)i * q + j] = -t / S[(size_t)i * q + i];
+        }
+    }
+    return X;
+}
+
+std::vector<zc> mul_upper(const std::vector<zc>& A, const std::vector<zc>& B, int q) {
+    std::vector<zc> C((size_t)q * q, zc(0, 0));
+    for (int i = 0; i < q; ++i)
+        for (int j = i; j < q; ++j) {
+            zc t = 0;
+            for (int k = i; k <= j; ++k) t += A[(size_t)i * q + k] * B[(size_t)k * q + j];
+            C[(size_t)i * q + j] = t;
+        }
+    return C;
+}
+
+// (c, s), c real, with [[c, s], [-conj(s), c]] [a, b]^T = [r, 0]^T
+void givens_cs(zc a, zc b, double& c, zc& s) {
+    const double aa = std::abs(a), ab = std::abs(b);
+    if (ab == 0) {
+        c = 1.0;
+        s = 0.0;
+    } else if (aa == 0) {
+        c = 0.0;
+        s = std::conj(b) / ab;
+    } else {
+        const double r = std::hypot(aa, ab);
+        c = aa / r;
+        s = (a / aa) * std::conj(b) / r;
+    }
+}
+
+struct Rot {
+    int a, b;
+    double c;
+    zc s;
+};
+inline void apply_rot(const Rot& R, zc* x) {
+    const zc t = R.c * x[R.a] + R.s * x[R.b];
+    x[R.b] = -std::conj(R.s) * x[R.a] + R.c * x[R.b];
+    x[R.a] = t;
+}
+}  // namespace
+
+template <typename T>
+static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x,
+                                    int64_t ld, int p, const hsw_solve_opts& o, int* iters_out,
+                                    double* relres_out) {
+    hipStream_t st = ctx->st;
+    const ProbHost& hp = ctx->ph[prob];
+    const ProbDev& Q = ctx->prob_h[prob];
+    const int64_t N = hp.Npad;
+    const int k = o.restart_k;
+    const int LDH = (k + 1) * p;  // rows of the block Hessenberg matrix
+    Cx<double> *V = nullptr, *Z = nullptr, *Cd = nullptr, *part = nullptr, *Sd = nullptr;
+    double *bn = nullptr, *partn = nullptr;
+    int* actd = nullptr;
+    {
+        const int nchb = bdots_chunks(N), nchn = dots_chunks(N);
+        void** slots[] = {(void**)&V, (void**)&Z, (void**)&Cd, (void**)&part, (void**)&Sd,
+                          (void**)&bn, (void**)&partn, (void**)&actd};
+        const size_t bytes[] = {16 * (size_t)N * LDH, 16 * (size_t)N * k * p, 16 * (size_t)LDH * p,
+                                16 * (size_t)nchb * LDH * p, 16 * (size_t)k * p * p, 8 * (size_t)p,
+                                8 * (size_t)p * nchn, 4 * (size_t)p};
+        const size_t nslot = sizeof(bytes) / sizeof(bytes[0]), base = 16;
+        if (ctx->gws.size() < base + nslot) ctx->gws.resize(base + nslot, {nullptr, 0});
+        for (size_t i = 0; i < nslot; ++i) {
+            auto& w = ctx->gws[base + i];
+            if (w.second < bytes[i]) {
+                if (w.first) HIPCHK(hipFree(w.first));
+                w = {nullptr, 0};
+                HIPCHK(hipMalloc(&w.first, bytes[i]));
+                w.second = bytes[i];
+            }
+            *slots[i] = w.first;
+        }
+    }
+    hsw_status s = ensure_solve_ws<T>(ctx, p);
+    if (s != HSW_OK) return s;
+    std::vector<double> bn_h(p), nrm_h(p), rel(p, 1.0);
+    std::vector<int> its(p, 0);
+    HIPCHK(hipMemset2DAsync(x, 16 * ld, 0, 16 * N, p, st));
+    launch_norm(b, ld, N, p, nullptr, partn, bn, nullptr, 0, st);
+    HIPCHK(hipMemcpyAsync(bn_h.data(), bn, 8 * p, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int c = 0; c < p; ++c)
+        if (!(bn_h[c] > 0)) rel[c] = 0.0;
+    int total = 0;
+    std::vector<zc> H, Gr, Cs, Gm, S1, S2, Sh;
+    // Cholesky QR of the q vectors at W (in place); false on breakdown.
+    auto cholqr = [&](Cx<double>* W, int q, std::vector<zc>& S) -> int {
+        std::vector<zc> Sp[2];
+        for (int pass = 0; pass < 2; ++pass) {
+            launch_bdots(W, N, q, W, N, q, N, part, Cd, st);
+            Gm.assign((size_t)q * q, 0);
+            if (hipMemcpyAsync(Gm.data(), Cd, 16 * (size_t)q * q, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return -1;
+            if (!chol_upper(Gm, q, Sp[pass])) return 0;
+            const std::vector<zc> Si = inv_upper(Sp[pass], q);
+            if (hipMemcpyAsync(Sd, Si.data(), 16 * (size_t)q * q, hipMemcpyHostToDevice, st) != hipSuccess)
+                return -1;
+            launch_bcombine(W, N, q, Sd, q, W, N, nullptr, N, 1.0, 0.0, st);
+        }
+        S = mul_upper(Sp[1], Sp[0], q);
+        return 1;
+    };
+    while (true) {
+        // true residual block of every column into V, its norms
+        launch_matvec(Q, ctx->d_et, x, V, b, ld, p, 1, st);
+        launch_norm(V, N, N, p, nullptr, partn, bn + 0, nullptr, 0, st);
+        HIPCHK(hipMemcpyAsync(nrm_h.data(), bn, 8 * p, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<int> act;
+        for (int c = 0; c < p; ++c) {
+            if (!(bn_h[c] > 0)) continue;
+            rel[c] = nrm_h[c] / bn_h[c];
+            if (rel[c] >= o.rtol) act.push_back(c);
+        }
+        if (act.empty() || total >= o.maxit) break;
+        const int q = (int)act.size();
+        for (int u = 0; u < q; ++u)  // act is increasing: each source lies at or after its target
+            if (act[u] != u)
+                HIPCHK(hipMemcpyAsync(V + (int64_t)u * N, V + (int64_t)act[u] * N, 16 * (size_t)N,
+                                      hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(actd, act.data(), 4 * q, hipMemcpyHostToDevice, st));
+        std::vector<zc> S0;
+        const int ok0 = cholqr(V, q, S0);
+        if (ok0 < 0) return fail(ctx, HSW_E_DEVICE, "block GMRES transfer failed");
+        if (ok0 == 0) return HSW_E_BREAKDOWN;  // rank-deficient residual block: the caller falls back
+        double scale = 0;
+        for (int u = 0; u < q; ++u) scale = std::max(scale, std::abs(S0[(size_t)u * q + u]));
+        const int ldh = (k + 1) * q;
+        H.assign((size_t)ldh * k * q, zc(0, 0));  // column-major, leading dimension ldh
+        Gr.assign((size_t)ldh * q, zc(0, 0));     // column c at c * ldh
+        for (int c = 0; c < q; ++c)
+            for (int r = 0; r <= c; ++r) Gr[(size_t)c * ldh + r] = S0[(size_t)r * q + c];
+        std::vector<Rot> rots;
+        int jdone = 0;
+        for (int j = 0; j < k; ++j) {
+            Cx<double>* Vj = V + (int64_t)j * q * N;
+            Cx<double>* W = V + (int64_t)(j + 1) * q * N;
+            Cx<double>* Zj = Z + (int64_t)j * q * N;
+            s = sweep_any<T>(ctx, prob, Vj, Zj, q, N);
+            if (s != HSW_OK) return s;
+            timed(ctx, "matvec", 1, (double)N * (32.0 * q + 8.0), 56.0 * (double)N * q,
+                  [&] { launch_matvec(Q, ctx->d_et, Zj, W, nullptr, N, q, 0, st); });
+            total += 1;
+            for (int c : act) its[c] += 1;
+            const int m = (j + 1) * q;
+            Cs.assign((size_t)m * q, zc(0, 0));
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_bdots(V, N, m, W, N, q, N, part, Cd, st);
+                launch_bcombine(V, N, m, Cd, q, W, N, nullptr, N, -1.0, 1.0, st);
+                std::vector<zc> Cp((size_t)m * q);
+                HIPCHK(hipMemcpyAsync(Cp.data(), Cd, 16 * (size_t)m * q, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (size_t e = 0; e < Cp.size(); ++e) Cs[e] += Cp[e];
+            }
+            std::vector<zc> Sj;
+            const int okj = cholqr(W, q, Sj);
+            if (okj < 0) return fail(ctx, HSW_E_DEVICE, "block GMRES transfer failed");
+            bool breakdown = okj == 0;
+            if (!breakdown) {
+                double dmin = 1e300, dmax = 0;
+                for (int u = 0; u < q; ++u) {
+                    const double d = std::abs(Sj[(size_t)u * q + u]);
+                    dmin = std::min(dmin, d);
+                    dmax = std::max(dmax, d);
+                }
+                scale = std::max(scale, dmax);
+                breakdown = dmin <= 1e-14 * scale;
+            }
+            // block column j of H: the Gram-Schmidt coefficients over the
+            // subdiagonal block Sj (zero on breakdown)
+            for (int u = 0; u < q; ++u) {
+                zc* col = H.data() + (size_t)(j * q + u) * ldh;
+                for (int i = 0; i < m; ++i) col[i] = Cs[(size_t)i * q + u];
+                if (!breakdown)
+                    for (int v = 0; v <= u; ++v) col[m + v] = Sj[(size_t)v * q + u];
+            }
+            // the rotations of earlier blocks, then new ones that zero the
+            // block's subdiagonal part column by column (each also applied to
+            // the block's later columns and to the right-hand side)
+            const size_t nold = rots.size();
+            for (int u = 0; u < q; ++u)
+                for (size_t i = 0; i < nold; ++i) apply_rot(rots[i], H.data() + (size_t)(j * q + u) * ldh);
+            for (int u = 0; u < q; ++u) {
+                const int t = j * q + u;
+                zc* col = H.data() + (size_t)t * ldh;
+                for (int r = t + 1; r <= m + u; ++r) {
+                    Rot R{t, r, 1.0, 0.0};
+                    givens_cs(col[t], col[r], R.c, R.s);
+                    for (int u2 = u; u2 < q; ++u2) apply_rot(R, H.data() + (size_t)(j * q + u2) * ldh);
+                    for (int c = 0; c < q; ++c) apply_rot(R, Gr.data() + (size_t)c * ldh);
+                    col[r] = 0;
+                    rots.push_back(R);
+                }
+            }
+            jdone = j + 1;
+            bool conv = true;
+            for (int u = 0; u < q; ++u) {
+                double r2 = 0;
+                for (int r = m; r < m + q; ++r) r2 += std::norm(Gr[(size_t)u * ldh + r]);
+                if (!(std::sqrt(r2) / bn_h[act[u]] < o.rtol)) conv = false;
+            }
+            if (conv || breakdown || total >= o.maxit) break;
+        }
+        // Y = R^{-1} Gr over the first jdone * q rows; x[act] += Z Y
+        const int m = jdone * q;
+        std::vector<zc> Y((size_t)m * q, zc(0, 0));  // row-major (i, c)
+        for (int c = 0; c < q; ++c)
+            for (int i = m - 1; i >= 0; --i) {
+                zc t = Gr[(size_t)c * ldh + i];
+                for (int l = i + 1; l < m; ++l) t -= H[(size_t)l * ldh + i] * Y[(size_t)l * q + c];
+                Y[(size_t)i * q + c] = t / H[(size_t)i * ldh + i];
+            }
+        HIPCHK(hipMemcpyAsync(Cd, Y.data(), 16 * (size_t)m * q, hipMemcpyHostToDevice, st));
+        launch_bcombine(Z, N, m, Cd, q, x, ld, actd, N, 1.0, 1.0, st);
+        HIPCHK(hipGetLastError());
+    }
+    bool okc = true;
+    for (int c = 0; c < p; ++c) {
+        if (iters_out) iters_out[c] = its[c];
+        if (relres_out) relres_out[c] = rel[c];
+        okc = okc && rel[c] < o.rtol;
+    }
+    return okc ? HSW_OK : HSW_E_NOCONV;
+}
+
+template <typename T>
+static hsw_status block_gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x, int nrhs,
+                                   const hsw_solve_opts& o, int* iters_out, double* relres_out) {
+    const int64_t ld = ctx->ph[prob].Npad;
+    hsw_status worst = HSW_OK;
+    for (int g0 = 0; g0 < nrhs; g0 += BLOCK_KRYLOV_MAX) {
+        const int ng = std::min(BLOCK_KRYLOV_MAX, nrhs - g0);
+        hsw_status s = block_gmres_group<T>(ctx, prob, b + g0 * ld, x + g0 * ld, ld, ng, o,
+                                            iters_out + g0, relres_out + g0);
+        if (s == HSW_E_BREAKDOWN)  // dependent right-hand sides: one Krylov space per column
+            s = gmres_impl<T>(ctx, prob, b + g0 * ld, x + g0 * ld, ng, o, iters_out + g0, relres_out + g0);
+        if (s != HSW_OK && s != HSW_E_NOCONV) return s;
+        if (s == HSW_E_NOCONV) worst = s;
+    }
+    return worst;
+}
+
 extern "C" hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128* const* x,
                                 const int32_t* nrhs, const hsw_solve_opts* opts, hsw_solve_info* info) {
     if (!ctx) return HSW_E_INVAL;
@@ -1367,11 +1660,15 @@ extern "C" hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128
         if (!b[k] || !x[k] || nrhs[k] < 1) return fail(ctx, HSW_E_INVAL, "bad right-hand side block");
         std::vector<int> it(nrhs[k]);
         std::vector<double> rr(nrhs[k]);
-        hsw_status s = ctx->prec == HSW_C128
-                           ? gmres_impl<double>(ctx, (int)k, (const Cx<double>*)b[k], (Cx<double>*)x[k],
-                                                nrhs[k], o, it.data(), rr.data())
-                           : gmres_impl<float>(ctx, (int)k, (const Cx<double>*)b[k], (Cx<double>*)x[k],
-                                               nrhs[k], o, it.data(), rr.data());
+        const Cx<double>* bk = (const Cx<double>*)b[k];
+        Cx<double>* xk = (Cx<double>*)x[k];
+        hsw_status s;
+        if (ctx->block_gmres)
+            s = ctx->prec == HSW_C128 ? block_gmres_impl<double>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data())
+                                      : block_gmres_impl<float>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data());
+        else
+            s = ctx->prec == HSW_C128 ? gmres_impl<double>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data())
+                                      : gmres_impl<float>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data());
         if (s != HSW_OK && s != HSW_E_NOCONV) return s;
         if (s == HSW_E_NOCONV) worst = s;
         for (int r = 0; r < nrhs[k]; ++r) {

@@ -91,4 +91,13 @@ void launch_lsq(int k, int nrhs, const Cx<double>* H, const Cx<double>* g, const
 void launch_cycle_init(int k, int nrhs, const double* beta, Cx<double>* g, const int* active,
                        hipStream_t st);
 
+// bkrylov.hip (block GMRES; blocks of at most 16 vectors)
+constexpr int BLOCK_KRYLOV_MAX = 16;
+int bdots_chunks(int64_t N);
+void launch_bdots(const Cx<double>* Q, int64_t qld, int m, const Cx<double>* W, int64_t wld, int q,
+                  int64_t N, Cx<double>* partial, Cx<double>* out, hipStream_t st);
+void launch_bcombine(const Cx<double>* Q, int64_t qld, int m, const Cx<double>* C, int q,
+                     Cx<double>* X, int64_t ld, const int* col, int64_t N, double alpha, double beta,
+                     hipStream_t st);
+
 }  // namespace hsw

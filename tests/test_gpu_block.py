@@ -1,0 +1,103 @@
+"""GPU parity of block GMRES (the "block_gmres" option) against the oracle's block GMRES.
+
+Every column must reach the FP64 true relative residual 1e-5 (checked with
+the oracle's operator).  In complex128 each column's iteration count must be
+within one of the oracle's block GMRES with the oracle's sweep; in complex64
+at most 1.2 times it plus one.  Groups of more than 16 right-hand sides are
+split; dependent right-hand sides fall back to GMRES per column; a zero
+right-hand side returns zero.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import gmres as gm
+from oracle import helmholtz as hz
+from oracle import sweep as sw
+from paper_1204_0111_amd import workloads as wl
+from tests._cases import case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solve(P, prec, b, block=True, restart=20):
+    from paper_1204_0111_amd.hsweep import Solver
+    S = Solver(P, precision=prec)
+    S.set_option("block_gmres", 1 if block else 0)
+    S.assemble(P["c"])
+    S.setup()
+    xs, info = S.solve([_cuda(b)], rtol=1e-5, restart=restart)
+    x = xs[0].cpu().numpy()
+    S.close()
+    return x, info
+
+
+def _true(P, b, x):
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    return [np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) for r in range(b.shape[0])]
+
+
+def _oracle(P, b, restart=20):
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    _, its, rel, _ = gm.block_gmres(lambda V: A @ V, O.apply, b.T, k=restart, tol=1e-5, maxit=400)
+    return its
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("model", ["waveguide", "two_layer"])
+def test_block_gmres_on_the_forcings_matches_oracle(model, prec):
+    P = case(n=(13, 12, 11), gamma=3, d=3, leaf=4, model=model, C=15.0)
+    b = wl.sources(P)
+    x, info = _solve(P, prec, b)
+    assert max(_true(P, b, x)) < 1e-5
+    ref = _oracle(P, b)
+    for r in range(4):
+        if prec == "c128":
+            assert abs(info["iters"][r] - ref[r]) <= 1, (info["iters"], list(ref))
+        else:
+            assert info["iters"][r] <= 1.2 * ref[r] + 1, (info["iters"], list(ref))
+
+
+def test_block_gmres_with_restarts_matches_oracle():
+    """A short restart length forces several cycles (and columns leaving the block)."""
+    P = case(n=(14, 12, 13), gamma=3, d=3, leaf=4, seed=5)
+    b = wl.random_complex((5, int(np.prod(hz.padded_shape(P["n"], P["gamma"])))), 41)
+    x, info = _solve(P, "c128", b, restart=3)
+    assert max(_true(P, b, x)) < 1e-5
+    ref = _oracle(P, b, restart=3)
+    for r in range(5):
+        assert abs(info["iters"][r] - ref[r]) <= 1, (info["iters"], list(ref))
+
+
+def test_block_gmres_groups_dependent_and_zero_columns():
+    """17 columns: a group of 16 and one of 1.  Column 3 repeats column 2 (the
+    first group falls back to GMRES per column) and column 5 is zero."""
+    P = case(n=(10, 9, 8), gamma=2, d=2, leaf=3, seed=9)
+    N = int(np.prod(hz.padded_shape(P["n"], P["gamma"])))
+    b = wl.random_complex((17, N), 43)
+    b[3] = b[2]
+    b[5] = 0
+    x, info = _solve(P, "c64", b)
+    assert np.all(x[5] == 0) and info["iters"][5] == 0 and info["relres"][5] == 0
+    rr = _true(P, np.delete(b, 5, axis=0), np.delete(x, 5, axis=0))
+    assert max(rr) < 1e-5
+
+
+def test_block_gmres_independent_columns_in_two_groups():
+    P = case(n=(10, 9, 8), gamma=2, d=2, leaf=3, seed=10)
+    N = int(np.prod(hz.padded_shape(P["n"], P["gamma"])))
+    b = wl.random_complex((18, N), 44)
+    x, info = _solve(P, "c128", b)
+    assert max(_true(P, b, x)) < 1e-5
+    ref16 = _oracle(P, b[:16])
+    ref2 = _oracle(P, b[16:])
+    for r in range(16):
+        assert abs(info["iters"][r] - ref16[r]) <= 1
+    for r in range(2):
+        assert abs(info["iters"][16 + r] - ref2[r]) <= 1
