@@ -25,12 +25,13 @@ sys.path.insert(0, ROOT)
 METRIC = "unknowns/s to FP64 rel-res 1e-5: batched FP32-MFMA sweep vs plain FP64 sweep"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector_nonpacked": 78.6}
-KERNEL_CLASSES = ["fwd", "bwd", "diag", "panel", "trailing", "assemble", "inverse", "matvec"]
+KERNEL_CLASSES = ["fwd", "bwd", "diag", "panel", "trailing", "schur", "assemble", "inverse", "matvec"]
 # kernel class -> (symbol in rocprof output, bound, source file holding it)
 KERNEL_INFO = {"fwd": ("k_fwd", "hbm", "solve.hip"), "bwd": ("k_bwd", "hbm", "solve.hip"),
                "diag": ("k_ldlt_diag", "hbm", "factor.hip"),
                "panel": ("k_panel_trsm", "hbm", "factor.hip"),
                "trailing": ("k_update", "mfma", "factor.hip"),
+               "schur": ("k_update", "mfma", "factor.hip"),
                "assemble": ("k_assemble", "hbm", "factor.hip"),
                "inverse": ("k_inverse", "mfma", "factor.hip"),
                "matvec": ("k_matvec", "hbm", "krylov.hip")}

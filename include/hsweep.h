@@ -199,7 +199,8 @@ hsw_status hsw_get_front_inverse(const hsw_ctx* ctx, int32_t prob, int32_t panel
 /*
  * Measurement aid (not part of the method).  enable != 0 starts timing the
  * named kernel class -- "fwd" / "bwd" (the two passes of the panel solves),
- * "diag", "panel", "trailing", "assemble", "inverse" (setup) or "matvec" --
+ * "diag", "panel", "trailing" (Schur updates inside the pivot columns),
+ * "schur" (the update of F_BR), "assemble", "inverse" (setup) or "matvec" --
  * and resets the totals: every later launch of that class on the context's
  * stream is bracketed by a pair of HIP events, and the algorithmic bytes
  * (factor blocks and vectors the launch must move, from the plan) and flops

@@ -169,8 +169,8 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
 // cores from one of two LDS buffers, so one barrier per chunk suffices.
 // CT picks the thread mapping of the C loads: false, consecutive threads read
 // consecutive cols (contiguous when C is stored [k][col]); true, consecutive
-// k (contiguous when C is stored [col][k]).  Ends with a barrier; the
-// caller's LDS buffers are free afterwards.
+// k (contiguous when C is stored [col][k]).  Ends with a barrier (except for
+// K <= 0, which returns at once); the caller's LDS buffers are free afterwards.
 template <typename T, int KC, bool CT = false, typename LR, typename LC>
 __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
                                     typename MfmaAcc<T>::type (&aim)[2][2], int K, LR ldR, LC ldC,
@@ -691,9 +691,12 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 aim[bi][bj] = V4{0, 0, 0, 0};
             }
         // sum over the later pivot columns m >= c1: X(rows, m) L(m, blk); L(m, c0 + a)
-        // is contiguous in m, so its loads use the transposed mapping
+        // is contiguous in m, so its loads use the transposed mapping.  Rows of
+        // L_F^{-1} are zero right of the diagonal, so a block of such rows stops
+        // at its own last row.
+        const int kend = r0 + 64 <= s ? r0 + 64 : s;
         cgemm64_pipe<T, KC, true>(
-            are, aim, s - c1,
+            are, aim, kend - c1,
             [&](int m, int a) { return r0 + a < n ? G[(int64_t)(c1 + m) * n + r0 + a] : cx<T>(0, 0); },
             [&](int m, int a) { return a < bw ? L[(int64_t)(c0 + a) * n + c1 + m] : cx<T>(0, 0); },
             Rre, Rim, Cre, Cim);

@@ -856,7 +856,7 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                 });
         }
         if (left || hybrid)
-            timed(ctx, "trailing", ds.schur.count, es * ds.schur.bytes_per_esz, 8 * ds.schur.cmac, [&] {
+            timed(ctx, "schur", ds.schur.count, es * ds.schur.bytes_per_esz, 8 * ds.schur.cmac, [&] {
                 launch_update<T>(ctx->d_fwork + ds.schur.off, ds.schur.count, ctx->d_inst, L, ws[d & 1],
                                  0, 2, bf16, st);
             });
@@ -1835,8 +1835,8 @@ extern "C" hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_
                                         int64_t* launches, double* seconds, double* bytes,
                                         double* flops) {
     if (!ctx || !kernel) return HSW_E_INVAL;
-    static const char* known[] = {"fwd", "bwd", "diag", "panel", "trailing", "assemble", "inverse",
-                                  "matvec"};
+    static const char* known[] = {"fwd", "bwd", "diag", "panel", "trailing", "schur", "assemble",
+                                  "inverse", "matvec"};
     bool ok = false;
     for (const char* k : known) ok = ok || std::strcmp(k, kernel) == 0;
     if (!ok) return fail(ctx, HSW_E_INVAL, std::string("unknown kernel class ") + kernel);
