@@ -39,9 +39,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def workload(name):
+    """The workload's problems and right-hand-side blocks (lists; the uneven
+    batch has one entry per problem)."""
     from paper_1204_0111_amd import workloads as wl
-    P = wl.make_problem(name)
-    return P, wl.sources(P)
+    nsub = wl.WORKLOADS[name].get("nprob", 1)
+    Ps = [wl.make_problem(name, sub=k) for k in range(nsub)]
+    return Ps, [wl.sources(P) for P in Ps]
 
 
 MODEL_TEXT = {"constant": "constant velocity 1",
@@ -54,8 +57,20 @@ MODEL_TEXT = {"constant": "constant velocity 1",
               "waveguide": "Gaussian waveguide 1.25(1-0.4exp(-32r^2)) (Sec. 3)"}
 
 
-def describe(P):
+def describe(Ps):
     from paper_1204_0111_amd import workloads as wl
+    if len(Ps) > 1:
+        P = Ps[0]
+        sizes = [list(Q["n"]) for Q in Ps]
+        return dict(workload="uneven batch of %d problems, interior sizes drawn from 30..70 per "
+                             "axis, %s each, 10 points per wavelength, PML gamma=%d (amplitude %.1f), "
+                             "panel depth %d, ND leaf %d, %d surface shots per problem, one batched "
+                             "setup and solve, GMRES(20) to FP64 rel-res 1e-5"
+                             % (len(Ps), MODEL_TEXT[wl.WORKLOADS[P["name"]]["model"]], P["gamma"],
+                                P["C"], P["d"], P["leaf"], P["nrhs"]),
+                    name=P["name"], problems=len(Ps), n=sizes, gamma=P["gamma"], panel_depth=P["d"],
+                    leaf=P["leaf"], pml_amp=P["C"], alpha=P["alpha"], nrhs=P["nrhs"])
+    P = Ps[0]
     model = MODEL_TEXT[wl.WORKLOADS[P["name"]]["model"]]
     src = ("the four forcings f0-f3 of Sec. 3" if P["src"] == "paper"
            else "%d Gaussian point source(s)" % P["nrhs"])
@@ -103,18 +118,34 @@ def roofline(S, step, kclass, prec):
     return t
 
 
-def run_path(P, b, prec, steps, warmup, measure=False):
+def run_path(Ps, bs, prec, steps, warmup, measure=False, rhs_group=0):
+    """Time whole solves of every problem of Ps in one context.  rhs_group > 0
+    solves the right-hand sides in groups of that many columns (bounds the
+    GMRES workspace of very large problems)."""
     import torch
     from paper_1204_0111_amd.hsweep import Solver
-    S = Solver(P, precision=prec)
-    c_dev = torch.as_tensor(P["c"]).to("cuda")
-    b_dev = torch.as_tensor(b).to("cuda")
+    S = Solver(Ps, precision=prec)
+    c_dev = [torch.as_tensor(P["c"]).to("cuda") for P in Ps]
+    b_dev = [torch.as_tensor(b).to("cuda") for b in bs]
+    nr = max(b.shape[0] for b in bs)
+    groups = [(0, nr)] if rhs_group <= 0 else [(g, g + rhs_group) for g in range(0, nr, rhs_group)]
     info = None
 
     def step():
-        S.assemble([c_dev])
+        S.assemble(c_dev)
         S.setup()
-        return S.solve([b_dev], rtol=1e-5, restart=20)[1]
+        acc = None
+        for g0, g1 in groups:
+            r = S.solve([b[g0:g1].contiguous() for b in b_dev], rtol=1e-5, restart=20)[1]
+            if acc is None:
+                acc = dict(r)
+            else:
+                acc["iters"] = acc["iters"] + r["iters"]
+                acc["relres"] = acc["relres"] + r["relres"]
+                acc["t_solve"] += r["t_solve"]
+                if r["status"] != "HSW_OK":
+                    acc["status"] = r["status"]
+        return acc
 
     for _ in range(warmup):
         info = step()
@@ -126,12 +157,15 @@ def run_path(P, b, prec, steps, warmup, measure=False):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = infos[-1]
-    nint = P["n"][0] * P["n"][1] * P["n"][2]
-    out = dict(precision=prec, value=nint * P["nrhs"] * steps / wall, ms_per_step=1e3 * wall / steps,
+    work = sum(P["n"][0] * P["n"][1] * P["n"][2] * b.shape[0] for P, b in zip(Ps, bs))
+    nprob = len(Ps)
+    out = dict(precision=prec, value=work * steps / wall, ms_per_step=1e3 * wall / steps,
                iters=info["iters"], relres=info["relres"], status=info["status"],
                t_setup_ms=1e3 * info["t_setup"], t_solve_ms=1e3 * info["t_solve"],
-               factor_bytes=S.query(0, "factor_bytes"), setup_flops=S.query(0, "setup_flops"),
-               apply_flops=S.query(0, "apply_flops"), panels=S.query(0, "m"))
+               factor_bytes=sum(S.query(k, "factor_bytes") for k in range(nprob)),
+               setup_flops=sum(S.query(k, "setup_flops") for k in range(nprob)),
+               apply_flops=sum(S.query(k, "apply_flops") for k in range(nprob)),
+               panels=sum(S.query(k, "m") for k in range(nprob)))
     if measure:
         # after the timed steps: one instrumented step per kernel class
         out["kernels"] = {k: roofline(S, step, k, prec) for k in KERNEL_CLASSES}
@@ -215,6 +249,8 @@ def main():
     ap.add_argument("--pml-amp", type=float, default=None,
                     help="override the PML amplitude C (exploration only)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--rhs-group", type=int, default=0,
+                    help="solve the right-hand sides in groups of this many columns")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -226,9 +262,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    P, b = workload(args.workload)
+    Ps, bs = workload(args.workload)
     if args.pml_amp is not None:
-        P["C"] = args.pml_amp
+        for P in Ps:
+            P["C"] = args.pml_amp
+    P = Ps[0]
     if args.calibrate_copy_mb:
         src = torch.empty(args.calibrate_copy_mb * (1 << 20) // 4, dtype=torch.float32,
                           device="cuda").fill_(1.0)
@@ -236,14 +274,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_run = run_path(P, b, "c64", args.steps, args.warmup, measure=not args.no_roofline)
+    main_run = run_path(Ps, bs, "c64", args.steps, args.warmup, measure=not args.no_roofline,
+                        rhs_group=args.rhs_group)
     kernels = main_run.pop("kernels", None)
     print("# c64: %s" % json.dumps(main_run), file=sys.stderr, flush=True)
     if kernels:
         print("# kernels: %s" % json.dumps(kernels), file=sys.stderr, flush=True)
     comp = None
     if not args.no_comparator:
-        comp = run_path(P, b, "c128", args.steps, args.warmup)
+        comp = run_path(Ps, bs, "c128", args.steps, args.warmup, rhs_group=args.rhs_group)
         print("# c128: %s" % json.dumps(comp), file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -251,7 +290,7 @@ def main():
     line = dict(metric=METRIC, value=main_run["value"], unit="unknowns/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=main_run["ms_per_step"],
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="c64",
-                data="synthetic", config=describe(P),
+                data="synthetic", config=describe(Ps),
                 precision="complex64 fronts and sweep, FP64 GMRES and residual",
                 iters=main_run["iters"], relres=main_run["relres"],
                 t_setup_ms=main_run["t_setup_ms"], t_solve_ms=main_run["t_solve_ms"],

@@ -184,7 +184,9 @@ hsw_status hsw_get_front_info(const hsw_ctx* ctx, int32_t prob, int32_t panel, i
  * Host copies (upcast to complex128) of the factored front (Sec. 2.2):
  * D (s), L_TL (s x s, column-major, unit lower; the upper part is zeroed)
  * and the final coupling F_BL = F_BL^ L_F^{-T} D_F^{-1} (u x s, column-major).
- * Any output may be NULL.  Requires hsw_setup.
+ * Any output may be NULL.  Requires hsw_setup with the factors kept (option
+ * keep_factors, on by default when memory allows; otherwise the factor
+ * block holds the selective inverse and this returns HSW_E_STATE).
  */
 hsw_status hsw_get_front(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
                          hsw_c128* D, hsw_c128* L_TL, hsw_c128* F_BL, int32_t* s, int32_t* u);
@@ -240,6 +242,20 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              part in.  A group whose residual block is rank deficient
  *              (dependent right-hand sides) is solved by GMRES(k) per column.
  *              0 (default): GMRES(k) per right-hand side.
+ *   "keep_factors" 1: hsw_setup keeps the factors L_F, D, F_BL (readable
+ *              by hsw_get_front) and writes the selective inverse G to a
+ *              block of its own (allocated when the option is set;
+ *              HSW_E_NOMEM if it does not fit); 0: G overwrites the factor
+ *              block in place (the rows of L_F^{-1} pass through a scratch and
+ *              are copied over L_F), which nearly halves the factor memory,
+ *              and hsw_get_front returns HSW_E_STATE.  hsw_create picks 1
+ *              when the separate block fits in device memory, else 0.
+ *   "inverse_by_depth" (in place only) 1: the inversion runs one tree depth
+ *              at a time through a scratch of the largest depth's L_F^{-1}
+ *              blocks; 0: all fronts in one launch through a scratch for
+ *              every L_F^{-1} (faster: the long rows of the top fronts overlap
+ *              the rest).  hsw_create picks 0 when that scratch fits, else 1.
+ * Changing "keep_factors" or "inverse_by_depth" requires a new hsw_setup.
  * Returns HSW_E_INVAL for an unknown key or value.
  */
 hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);

@@ -84,6 +84,7 @@ struct FrontInst {
     int64_t loff;                // offset of the (s+u) x s factor block (complex elements)
     int64_t woff;                // offset of the u x u update matrix in its depth-parity workspace
     int64_t doff;                // offset of the s reciprocal pivots
+    int64_t toff;                // offset of the s x s block of L_F^{-1} in the scratch of its depth
 };
 
 // One workgroup of a forward or backward pass of a panel solve.  Offsets are

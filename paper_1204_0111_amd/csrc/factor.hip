@@ -656,8 +656,8 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
 // diagonal-block inverse the factorisation stored above the diagonal.
 template <typename T>
 __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
-                                                 const FrontInst* __restrict__ inst,
-                                                 const Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Gb) {
+                                                 const FrontInst* __restrict__ inst, const Cx<T>* Lb,
+                                                 Cx<T>* Gb, Cx<T>* Tb) {
     constexpr int KC = 16;
     typedef typename MfmaAcc<T>::type V4;
     const int2 w = work[blockIdx.x];
@@ -665,6 +665,15 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
     const int n = f.s + f.u, s = f.s;
     const Cx<T>* L = Lb + f.loff;
     Cx<T>* G = Gb + f.loff;
+    // X(row, col): rows of L_F^{-1} in the depth's scratch (s x s, column-major)
+    // when Tb is given, every other row (and all rows without Tb) in G.  With
+    // Tb, G may be L itself: this workgroup's rows of F_BL are only read by
+    // it, before they are overwritten, and the rows of L_F that every row
+    // block reads are left in place.
+    Cx<T>* TF = Tb ? Tb + f.toff : nullptr;
+    auto xat = [&](int row, int col) -> Cx<T>* {
+        return (TF && row < s) ? TF + (int64_t)col * s + row : G + (int64_t)col * n + row;
+    };
     const int r0 = w.y * 64;
     const int tid = threadIdx.x;
     const int l = tid & 63, wv = tid >> 6;
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
         if (r0 + 63 < c0) {  // rows of the identity above the block: zero in L_F^{-1}
             for (int idx = tid; idx < 64 * 64; idx += 256) {
                 const int rr = idx & 63, cc = idx / 64;
-                if (cc < bw && r0 + rr < n) G[(int64_t)(c0 + cc) * n + r0 + rr] = cx<T>(0, 0);
+                if (cc < bw && r0 + rr < n) *xat(r0 + rr, c0 + cc) = cx<T>(0, 0);
             }
             continue;
         }
@@ -697,7 +706,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
         const int kend = r0 + 64 <= s ? r0 + 64 : s;
         cgemm64_pipe<T, KC, true>(
             are, aim, kend - c1,
-            [&](int m, int a) { return r0 + a < n ? G[(int64_t)(c1 + m) * n + r0 + a] : cx<T>(0, 0); },
+            [&](int m, int a) { return r0 + a < n ? *xat(r0 + a, c1 + m) : cx<T>(0, 0); },
             [&](int m, int a) { return a < bw ? L[(int64_t)(c0 + a) * n + c1 + m] : cx<T>(0, 0); },
             Rre, Rim, Cre, Cim);
         // acc = B_blk - sum, into LDS as [col][row]
@@ -739,9 +748,26 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 for (int r = 0; r < 4; ++r) {
                     const int row = r0 + (wv & 1) * 32 + 16 * bi + li;
                     const int cc = (wv >> 1) * 32 + 16 * bj + mfma_out_row<T>(lk, r);
-                    if (cc < bw && row < n)
-                        G[(int64_t)(c0 + cc) * n + row] = cx<T>(are[bi][bj][r], aim[bi][bj][r]);
+                    if (cc < bw && row < n) *xat(row, c0 + cc) = cx<T>(are[bi][bj][r], aim[bi][bj][r]);
                 }
+    }
+}
+
+// L_F^{-1} from the depth's scratch over the L_F rows of the factor block
+// (rows 64 w.y .. of every pivot column), after the depth's inversion.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lf_copy(const int2* __restrict__ work,
+                                                 const FrontInst* __restrict__ inst, Cx<T>* __restrict__ Lb,
+                                                 const Cx<T>* __restrict__ Tb) {
+    const int2 w = work[blockIdx.x];
+    const FrontInst f = inst[w.x];
+    const int n = f.s + f.u, s = f.s;
+    const int r0 = w.y * 64;
+    Cx<T>* L = Lb + f.loff;
+    const Cx<T>* TF = Tb + f.toff;
+    for (int idx = threadIdx.x; idx < 64 * s; idx += 256) {
+        const int col = idx >> 6, row = r0 + (idx & 63);
+        if (row < s) L[(int64_t)col * n + row] = TF[(int64_t)col * s + row];
     }
 }
 
@@ -775,9 +801,15 @@ void launch_update(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb
 }
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
+                    Cx<T>* Tb, hipStream_t st) {
+    if (nwork <= 0) return;
+    HSW_LAUNCH(k_inverse<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Gb, Tb);
+}
+template <typename T>
+void launch_lf_copy(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, const Cx<T>* Tb,
                     hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH(k_inverse<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Gb);
+    HSW_LAUNCH(k_lf_copy<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Tb);
 }
 
 #define HSW_INST(T)                                                                              \
@@ -792,6 +824,8 @@ void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx
     template void launch_update<T>(const int2*, int, const FrontInst*, Cx<T>*, Cx<T>*, int, int,  \
                                    int, hipStream_t);                                           \
     template void launch_inverse<T>(const int2*, int, const FrontInst*, const Cx<T>*, Cx<T>*,    \
+                                    Cx<T>*, hipStream_t);                                       \
+    template void launch_lf_copy<T>(const int2*, int, const FrontInst*, Cx<T>*, const Cx<T>*,    \
                                     hipStream_t);
 HSW_INST(float)
 HSW_INST(double)

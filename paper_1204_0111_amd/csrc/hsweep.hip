@@ -110,7 +110,17 @@ struct hsw_ctx {
     std::vector<ProbDev> prob_h;
     std::vector<FrontInst> inst_h;
     std::vector<DepthSchedule> fsched;  // index = depth
-    Launch inv_launch{0, 0, 0};
+    // selective inversion and the copy of L_F^{-1} over L_F: one launch each
+    // over all fronts when the scratch for every L_F^{-1} fits (inv_launch,
+    // lfcopy_all), else one pair per tree depth with the scratch of the
+    // largest depth
+    Launch inv_launch{0, 0, 0}, lfcopy_all{0, 0, 0};
+    std::vector<Launch> inv_depth, lfcopy_depth;
+    std::vector<int64_t> toff_all;  // scratch offsets of the one-launch layout
+    int64_t inv_scratch = 0, inv_scratch_all = 0;
+    bool inv_by_depth = false;
+    bool keep_factors = false; // keep L next to G (a separate G block) instead of inverting in place
+    void* d_T = nullptr;       // L_F^{-1} scratch of one depth
     std::vector<std::vector<SolveLevel>> slevels;  // per class, per depth
     int maxdepth = 0;
     int64_t ws_size[2] = {0, 0};
@@ -223,8 +233,8 @@ static void free_all(hsw_ctx* ctx) {
     if (ctx->gst) (void)hipStreamDestroy(ctx->gst);
     void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist,
                     ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
-                    ctx->d_L, ctx->d_G, ctx->d_dinv, ctx->d_ws[0], ctx->d_ws[1], ctx->d_err,
-                    ctx->d_xmid, ctx->d_xu, ctx->d_c2};
+                    ctx->d_L, ctx->d_G != ctx->d_L ? ctx->d_G : nullptr, ctx->d_dinv, ctx->d_ws[0],
+                    ctx->d_ws[1], ctx->d_err, ctx->d_xmid, ctx->d_xu, ctx->d_c2, ctx->d_T};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -526,19 +536,58 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
         xcd_group(fwork, ds.schur.off, fwork.size());
         ds.nfronts = (int)at[d].size();
     }
+    // selective inversion, one launch per depth (the fronts of a depth over all
+    // panels and problems), each followed by the copy of L_F^{-1} from the
+    // depth's scratch over L_F when the inverse overwrites the factor
+    ctx->inv_depth.assign(D + 1, Launch{0, 0, 0});
+    ctx->lfcopy_depth.assign(D + 1, Launch{0, 0, 0});
+    ctx->inv_launch = Launch{0, 0, 0};
+    ctx->inv_scratch = 0;
+    for (int d = D; d >= 0; --d) {
+        Launch& il = ctx->inv_depth[d];
+        il.off = (int64_t)fwork.size();
+        int64_t toff = 0;
+        for (int i : at[d]) {
+            FrontInst& f = ctx->inst_h[i];
+            f.toff = toff;
+            toff += (int64_t)f.s * f.s;
+            const int nrb = (f.s + f.u + 63) / 64;
+            for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
+            const double sd = f.s, ud = f.u;
+            il.bytes_per_esz += (sd + ud) * sd + sd * (sd + 1) / 2 + ud * sd;
+            il.cmac += sd * sd * sd / 6 + ud * sd * sd / 2;
+        }
+        il.count = (int)(fwork.size() - il.off);
+        xcd_group(fwork, il.off, fwork.size());
+        ctx->inv_scratch = std::max(ctx->inv_scratch, toff);
+        Launch& cl = ctx->lfcopy_depth[d];
+        cl.off = (int64_t)fwork.size();
+        for (int i : at[d]) {
+            const FrontInst& f = ctx->inst_h[i];
+            for (int rb = 0; rb < (f.s + 63) / 64; ++rb) fwork.push_back(make_int2(i, rb));
+            cl.bytes_per_esz += 2.0 * f.s * f.s;
+        }
+        cl.count = (int)(fwork.size() - cl.off);
+        ctx->inv_launch.bytes_per_esz += il.bytes_per_esz;
+        ctx->inv_launch.cmac += il.cmac;
+        ctx->lfcopy_all.bytes_per_esz += cl.bytes_per_esz;
+    }
+    // the one-launch layout: every front, long rows first in the XCD order
+    ctx->toff_all.assign(ctx->inst_h.size(), 0);
+    ctx->inv_scratch_all = 0;
     ctx->inv_launch.off = (int64_t)fwork.size();
     for (size_t i = 0; i < ctx->inst_h.size(); ++i) {
         const FrontInst& f = ctx->inst_h[i];
-        int nrb = (f.s + f.u + 63) / 64;
-        for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2((int)i, rb));
+        ctx->toff_all[i] = ctx->inv_scratch_all;
+        ctx->inv_scratch_all += (int64_t)f.s * f.s;
+        for (int rb = 0; rb < (f.s + f.u + 63) / 64; ++rb) fwork.push_back(make_int2((int)i, rb));
     }
     ctx->inv_launch.count = (int)(fwork.size() - ctx->inv_launch.off);
     xcd_group(fwork, ctx->inv_launch.off, fwork.size());
-    for (const FrontInst& f : ctx->inst_h) {
-        const double sd = f.s, ud = f.u;
-        ctx->inv_launch.bytes_per_esz += (sd + ud) * sd + sd * (sd + 1) / 2 + ud * sd;
-        ctx->inv_launch.cmac += sd * sd * sd / 6 + ud * sd * sd / 2;
-    }
+    ctx->lfcopy_all.off = (int64_t)fwork.size();
+    for (size_t i = 0; i < ctx->inst_h.size(); ++i)
+        for (int rb = 0; rb < (ctx->inst_h[i].s + 63) / 64; ++rb) fwork.push_back(make_int2((int)i, rb));
+    ctx->lfcopy_all.count = (int)(fwork.size() - ctx->lfcopy_all.off);
     // solve work lists per class and depth
     ctx->slevels.assign(ctx->classes.size(), {});
     for (size_t ci = 0; ci < ctx->classes.size(); ++ci) {
@@ -668,17 +717,30 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     size_t ints = 0;
     for (auto& c : ctx->classes)
         ints += (size_t)c.naux + c.ulist.size() + c.cmap.size() + c.pmap.size();
-    const size_t need = (size_t)ctx->esz * (2 * ctx->L_size + ctx->D_size + ctx->ws_size[0] +
-                                             ctx->ws_size[1]) +
-                        sizeof(FrontInst) * ctx->inst_h.size() + sizeof(PanelDev) * ctx->pan_h.size() +
-                        sizeof(ProbDev) * ctx->prob_h.size() + 4 * ints + 8 * fwork.size() +
-                        sizeof(SolveItem) * sitems.size() + 16 * (size_t)eo + 8 * (size_t)nint_total;
+    // the factor block holds L during the factorisation and G after the
+    // in-place selective inversion; the scratch holds L_F^{-1} of every front
+    // (one inversion launch) or, when that does not fit, of one depth
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
         g_create_error = "hipMemGetInfo failed (no device?)";
         delete ctx;
         return HSW_E_DEVICE;
     }
+    // the fastest layout that fits: a separate G block (no scratch, no copy),
+    // else in place with every L_F^{-1} in the scratch, else in place one
+    // depth at a time
+    const size_t base = (size_t)ctx->esz * (ctx->L_size + ctx->D_size + ctx->ws_size[0] + ctx->ws_size[1]);
+    const size_t room = freeb / 100 * 90;
+    ctx->keep_factors = base + (size_t)ctx->esz * ctx->L_size <= room;
+    ctx->inv_by_depth = !ctx->keep_factors && base + (size_t)ctx->esz * ctx->inv_scratch_all > room;
+    if (!ctx->inv_by_depth) {
+        for (size_t i = 0; i < ctx->inst_h.size(); ++i) ctx->inst_h[i].toff = ctx->toff_all[i];
+        ctx->inv_scratch = ctx->inv_scratch_all;
+    }
+    const size_t need = base + (size_t)ctx->esz * (ctx->keep_factors ? ctx->L_size : ctx->inv_scratch) +
+                        sizeof(FrontInst) * ctx->inst_h.size() + sizeof(PanelDev) * ctx->pan_h.size() +
+                        sizeof(ProbDev) * ctx->prob_h.size() + 4 * ints + 8 * fwork.size() +
+                        sizeof(SolveItem) * sitems.size() + 16 * (size_t)eo + 8 * (size_t)nint_total;
     if (need > freeb / 100 * 95) {
         char buf[256];
         snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory, %.3f GB free",
@@ -717,7 +779,12 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ACHK(dalloc(&ctx->d_sitems, sizeof(SolveItem) * std::max<size_t>(sitems.size(), 1)));
     ACHK(dalloc(&ctx->d_et, 16 * (size_t)eo));
     ACHK(dalloc(&ctx->d_L, (size_t)ctx->esz * ctx->L_size));
-    ACHK(dalloc(&ctx->d_G, (size_t)ctx->esz * ctx->L_size));
+    if (ctx->keep_factors) {
+        ACHK(dalloc(&ctx->d_G, (size_t)ctx->esz * ctx->L_size));
+    } else {
+        ctx->d_G = ctx->d_L;
+        ACHK(dalloc(&ctx->d_T, (size_t)ctx->esz * std::max<int64_t>(ctx->inv_scratch, 1)));
+    }
     ACHK(dalloc(&ctx->d_dinv, (size_t)ctx->esz * ctx->D_size));
     ACHK(dalloc(&ctx->d_ws[0], (size_t)ctx->esz * std::max<int64_t>(ctx->ws_size[0], 1)));
     ACHK(dalloc(&ctx->d_ws[1], (size_t)ctx->esz * std::max<int64_t>(ctx->ws_size[1], 1)));
@@ -763,6 +830,67 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->autotune = value != 0;
     } else if (k == "block_gmres") {
         ctx->block_gmres = value != 0;
+    } else if (k == "inverse_by_depth") {
+        const bool by = value != 0;
+        if (by != ctx->inv_by_depth) {
+            int64_t need = 0;
+            std::vector<FrontInst> inst = ctx->inst_h;
+            if (by) {
+                std::vector<int64_t> off(ctx->maxdepth + 1, 0);
+                for (auto& f : inst) {
+                    f.toff = off[f.depth];
+                    off[f.depth] += (int64_t)f.s * f.s;
+                }
+                for (int64_t o : off) need = std::max(need, o);
+            } else {
+                for (size_t i = 0; i < inst.size(); ++i) inst[i].toff = ctx->toff_all[i];
+                need = ctx->inv_scratch_all;
+            }
+            if (need > ctx->inv_scratch) {
+                void* t = nullptr;
+                if (hipMalloc(&t, (size_t)ctx->esz * need) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(ctx, HSW_E_NOMEM, "inverse_by_depth: no room for the scratch");
+                }
+                HIPCHK(hipStreamSynchronize(ctx->st));
+                (void)hipFree(ctx->d_T);
+                ctx->d_T = t;
+                ctx->inv_scratch = need;
+            }
+            HIPCHK(hipMemcpyAsync(ctx->d_inst, inst.data(), sizeof(FrontInst) * inst.size(),
+                                  hipMemcpyHostToDevice, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            ctx->inst_h = inst;
+            ctx->inv_by_depth = by;
+            ctx->factored = false;
+        }
+    } else if (k == "keep_factors") {
+        const bool keep = value != 0;
+        if (keep != ctx->keep_factors) {
+            if (keep) {
+                void* g = nullptr;
+                if (hipMalloc(&g, (size_t)ctx->esz * std::max<int64_t>(ctx->L_size, 1)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(ctx, HSW_E_NOMEM, "keep_factors: no room for a separate G block");
+                }
+                ctx->d_G = g;
+            } else {
+                if (!ctx->d_T) {
+                    void* t = nullptr;
+                    if (hipMalloc(&t, (size_t)ctx->esz * std::max<int64_t>(ctx->inv_scratch, 1)) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return fail(ctx, HSW_E_NOMEM, "keep_factors 0: no room for the scratch");
+                    }
+                    ctx->d_T = t;
+                }
+                HIPCHK(hipStreamSynchronize(ctx->st));
+                (void)hipFree(ctx->d_G);
+                ctx->d_G = ctx->d_L;
+            }
+            ctx->keep_factors = keep;
+            ctx->factored = false;  // G is rebuilt by the next setup
+            drop_graphs(ctx);
+        }
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
         ctx->update_order = (int)value;
@@ -861,10 +989,23 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                                  0, 2, bf16, st);
             });
     }
-    timed(ctx, "inverse", ctx->inv_launch.count, sizeof(Cx<T>) * ctx->inv_launch.bytes_per_esz, 8 * ctx->inv_launch.cmac, [&] {
-        launch_inverse<T>(ctx->d_fwork + ctx->inv_launch.off, ctx->inv_launch.count, ctx->d_inst, L,
-                          G, st);
-    });
+    // selective inversion depth by depth: in place, the rows of F_BL L_F^{-1}
+    // overwrite F_BL and the rows of L_F^{-1} go to the scratch (the other row
+    // blocks of the front still read L_F) and are copied over L_F afterwards
+    Cx<T>* T_ = ctx->keep_factors ? nullptr : (Cx<T>*)ctx->d_T;
+    const int ngroups = ctx->inv_by_depth ? ctx->maxdepth + 1 : 1;
+    for (int g = 0; g < ngroups; ++g) {
+        const int d = ctx->maxdepth - g;
+        const Launch& il = ctx->inv_by_depth ? ctx->inv_depth[d] : ctx->inv_launch;
+        const Launch& cl = ctx->inv_by_depth ? ctx->lfcopy_depth[d] : ctx->lfcopy_all;
+        timed(ctx, "inverse", il.count, sizeof(Cx<T>) * il.bytes_per_esz, 8 * il.cmac, [&] {
+            launch_inverse<T>(ctx->d_fwork + il.off, il.count, ctx->d_inst, L, G, T_, st);
+        });
+        if (T_)
+            timed(ctx, "inverse", cl.count, sizeof(Cx<T>) * cl.bytes_per_esz, 0.0, [&] {
+                launch_lf_copy<T>(ctx->d_fwork + cl.off, cl.count, ctx->d_inst, L, T_, st);
+            });
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, st));
     int err[2];
@@ -1796,6 +1937,10 @@ extern "C" hsw_status hsw_get_front(const hsw_ctx* cctx, int32_t prob, int32_t p
                                     int32_t* pu) {
     hsw_ctx* ctx = const_cast<hsw_ctx*>(cctx);
     if (!ctx) return HSW_E_INVAL;
+    if (!ctx->keep_factors)
+        return fail(ctx, HSW_E_STATE,
+                    "the factors were overwritten by their selective inverse: set the option "
+                    "keep_factors before hsw_setup");
     std::vector<Cx<double>> blk;
     int s = 0, u = 0;
     hsw_status st = front_block(ctx, prob, panel, front, ctx->d_L, blk, s, u);

@@ -48,6 +48,9 @@ void launch_update(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb
                    int mode, int bf16, hipStream_t st);
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,
+                    Cx<T>* Tb, hipStream_t st);
+template <typename T>
+void launch_lf_copy(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, const Cx<T>* Tb,
                     hipStream_t st);
 
 // solve.hip

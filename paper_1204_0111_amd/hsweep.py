@@ -262,7 +262,8 @@ class Solver:
         return D, L, F[:u]
 
     def set_option(self, key, value):
-        """Execution option of the context: "graph" or "autotune" (0 or 1)."""
+        """Option of the context: "graph", "autotune", "update_order", "block_gmres" or
+        "keep_factors" (see hsw_set_option)."""
         self._check(self.lib.hsw_set_option(self.ctx, key.encode(), int(value)))
 
     def kernel_timing(self, kernel, enable):

@@ -34,10 +34,14 @@ WORKLOADS = {
                        nrhs=16, src="surface", C=30.0),
     # one of 48 problems with per-axis sizes drawn from 30..70, 4 shots each
     "batch48": dict(seed=4, n=None, gamma=8, d=4, leaf=4, model="grf", nrhs=4, src="surface",
-                    C=30.0),
+                    C=30.0, nprob=48),
     # 250^3 wedge with a salt body, 32 surface shots
     "wedge250": dict(seed=5, n=(250, 250, 250), gamma=12, d=4, leaf=4, model="wedge_salt",
                      nrhs=32, src="surface", C=30.0),
+    # one GPU's share of it: the same lateral shape, PML and panel depth over
+    # 40 planes (10 of its 63 panels), the same 32 shots
+    "wedge250slab": dict(seed=5, n=(250, 250, 40), gamma=12, d=4, leaf=4, model="wedge_salt",
+                         nrhs=32, src="surface", C=30.0),
     # the analytic models of Sec. 3 at 50^3 (5 PML points, 4 planes per panel
     # as in Table 3.1), each with the four forcings f0..f3 as one block; C is
     # the amplitude the search over {2,3,4,7.5,10,15,20,30,45,60} picked

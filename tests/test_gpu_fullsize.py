@@ -33,9 +33,11 @@ def grf50():
     return P, wl.sources(P)
 
 
-def _solver(P, prec):
+def _solver(P, prec, keep=None):
     from paper_1204_0111_amd.hsweep import Solver
     S = Solver(P, precision=prec)
+    if keep is not None:
+        S.set_option("keep_factors", 1 if keep else 0)
     S.assemble(P["c"])
     S.setup()
     return S
@@ -44,7 +46,7 @@ def _solver(P, prec):
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_factors_bitwise_reproducible(grf50, prec):
     P, _ = grf50
-    S = _solver(P, prec)
+    S = _solver(P, prec, keep=True)
     fronts = [(3, 0), (3, 1), (3, 2), (5, 100), (0, 0), (12, 0), (12, 255)]
     a = [S.front_inverse(0, i, f) for i, f in fronts]
     d = [S.front(0, i, f)[0] for i, f in fronts]
@@ -133,3 +135,38 @@ def test_layered100_sixteen_shots_as_one_block():
             assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5, (prec, r)
         its[prec] = max(info["iters"])
     assert its["c64"] <= 1.2 * its["c128"] + 1, its
+
+
+def test_batch48_uneven_batch_full_size():
+    """The uneven batch: 48 problems of 30..70 nodes per axis, each with its own
+    velocity and 4 surface shots, in one context with one batched setup and
+    solve in complex64 (the factors are inverted in place: two copies do not
+    fit).  Every shot reaches rel-res 1e-5; for three sampled problems the FP64
+    true residual is checked with the oracle's operator, and complex64 needs at
+    most 1.2x the complex128 iterations of those problems plus one."""
+    from paper_1204_0111_amd.hsweep import Solver
+    Ps = [wl.make_problem("batch48", sub=k) for k in range(48)]
+    bs = [wl.sources(P) for P in Ps]
+    S = Solver(Ps, precision="c64")
+    S.assemble([P["c"] for P in Ps])
+    S.setup()
+    xs, info = S.solve([torch.as_tensor(b).to("cuda") for b in bs], rtol=1e-5, restart=20)
+    assert info["status"] == "HSW_OK" and len(info["iters"]) == 192
+    assert max(info["relres"]) < 1e-5
+    samples = [0, 21, 47]
+    x = {k: xs[k].cpu().numpy() for k in samples}
+    S.close()
+    del xs
+    Q = [Ps[k] for k in samples]
+    S2 = Solver(Q, precision="c128")
+    S2.assemble([P["c"] for P in Q])
+    S2.setup()
+    _, info2 = S2.solve([torch.as_tensor(bs[k]).to("cuda") for k in samples], rtol=1e-5, restart=20)
+    S2.close()
+    for j, k in enumerate(samples):
+        P = Ps[k]
+        A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+        for r in range(4):
+            b = bs[k][r]
+            assert np.linalg.norm(b - A @ x[k][r]) / np.linalg.norm(b) < 1e-5, (k, r)
+            assert info["iters"][4 * k + r] <= 1.2 * info2["iters"][4 * j + r] + 1, (k, r)
