@@ -367,19 +367,21 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
 // share the front's data in that L2: fronts go to the least loaded of eight
 // bins, and slot p takes the next item of bin p mod 8 (or, once that bin is
 // empty, of the fullest bin).
-static void xcd_group(std::vector<int2>& w, size_t b, size_t e) {
+template <typename W, typename K>
+static void xcd_group_by(std::vector<W>& w, size_t b, size_t e, K key) {
     constexpr int X = 8;
     if (e - b <= 1) return;
-    std::map<int, std::vector<int2>> by;
-    std::vector<int> order;
+    std::map<int64_t, std::vector<W>> by;
+    std::vector<int64_t> order;
     for (size_t i = b; i < e; ++i) {
-        if (!by.count(w[i].x)) order.push_back(w[i].x);
-        by[w[i].x].push_back(w[i]);
+        const int64_t k = key(w[i]);
+        if (!by.count(k)) order.push_back(k);
+        by[k].push_back(w[i]);
     }
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return by[a].size() > by[c].size(); });
-    std::vector<std::vector<int2>> bins(X);
-    for (int f : order) {
+                     [&](int64_t a, int64_t c) { return by[a].size() > by[c].size(); });
+    std::vector<std::vector<W>> bins(X);
+    for (int64_t f : order) {
         int x = 0;
         for (int y = 1; y < X; ++y)
             if (bins[y].size() < bins[x].size()) x = y;
@@ -395,6 +397,10 @@ static void xcd_group(std::vector<int2>& w, size_t b, size_t e) {
         }
         w[p] = bins[x][pos[x]++];
     }
+}
+
+static void xcd_group(std::vector<int2>& w, size_t b, size_t e) {
+    xcd_group_by(w, b, e, [](const int2& v) { return (int64_t)v.x; });
 }
 
 static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<SolveItem>& sitems) {
@@ -620,6 +626,9 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 for (int f : c.at_depth[d])
                     for (int blk = 0; blk < c.s[f] + c.u[f]; blk += rb) sitems.push_back(item(f, blk));
                 sl.fcount[k] = (int)(sitems.size() - sl.foff[k]);
+                // the row blocks of one front on one XCD: their shared cache
+                // lines and the staged front vector hit that XCD's L2
+                xcd_group_by(sitems, sl.foff[k], sitems.size(), [](const SolveItem& q) { return q.loff; });
             }
             for (int k = 0; k < N_BWD_SHAPES; ++k) {
                 const int cb = BWD_SHAPES[k].block;
@@ -627,6 +636,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 for (int f : c.at_depth[d])
                     for (int blk = 0; blk < c.s[f]; blk += cb) sitems.push_back(item(f, blk));
                 sl.bcount[k] = (int)(sitems.size() - sl.boff[k]);
+                xcd_group_by(sitems, sl.boff[k], sitems.size(), [](const SolveItem& q) { return q.loff; });
             }
             for (int f : c.at_depth[d]) {
                 sl.smax = std::max(sl.smax, c.s[f]);
