@@ -385,3 +385,48 @@ def test_solve_options_agree(medium):
     assert rel(out[0][1], out[1][1]) < 1e-4
     with pytest.raises(Exception):
         S.set_option("no-such-option", 1)
+
+
+@pytest.mark.parametrize("args", [dict(n=(1, 1, 1), gamma=1, d=1, leaf=2),
+                                  dict(n=(2, 2, 2), gamma=1, d=1, leaf=2),
+                                  dict(n=(3, 1, 5), gamma=2, d=2, leaf=2),
+                                  dict(n=(5, 4, 3), gamma=2, d=7, leaf=2),
+                                  dict(n=(6, 5, 9), gamma=1, d=1, leaf=2)],
+                         ids=["one_node", "two_cubed_pml1", "flat_axis", "one_panel_deep", "pml1_d1"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_degenerate_shapes_match_oracle(args, prec):
+    """Single interior node, an axis of one node, PML of one point, panel
+    deeper than the grid (one panel), one plane per panel: the sweep still
+    matches the oracle and GMRES reaches the FP64 true residual."""
+    P = case(**args)
+    S = _solver(P, prec)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((2, O.N_pad), 23)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    assert rel(z, O.apply(r.T).T) <= TOL[prec]
+    A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+    xs, info = S.solve([_cuda(r)], rtol=1e-5)
+    x = xs[0].cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(r[k] - A @ x[k]) / np.linalg.norm(r[k]) < 1e-5
+
+
+def test_empty_and_bad_right_hand_side_blocks():
+    """No right-hand side, a too short leading dimension and aliased input and
+    output are reported, not run."""
+    from paper_1204_0111_amd.hsweep import HswError
+    P = case(n=(6, 5, 4), gamma=2, d=2, leaf=2)
+    S = _solver(P, "c64")
+    N = S.N_pad()
+    r = _cuda(wl.random_complex((2, N), 3))
+    lib = S.lib
+    import ctypes
+    z = torch.empty_like(r)
+    assert lib.hsw_apply(S.ctx, 0, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 0, N) == 1
+    assert lib.hsw_apply(S.ctx, 0, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 2, N - 1) == 1
+    assert lib.hsw_apply(S.ctx, 0, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(r.data_ptr()), 2, N) == 1
+    assert lib.hsw_apply(S.ctx, 5, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 2, N) == 1
+    with pytest.raises(ValueError):
+        S.apply(0, r[:, : N - 1])
+    with pytest.raises(HswError):
+        S.apply(3, r)
