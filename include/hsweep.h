@@ -232,6 +232,16 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              pivots before it is factored, F_BR once at the end); 2 or -1
  *              (default) hybrid: right-looking over the pivot columns, F_BR
  *              once at the end.  The factors agree to rounding.
+ *   "solve_lanes" 1..16 (default 4): hsw_solve spreads the problems of a
+ *              context over this many lanes -- streams with their own
+ *              workspaces, one host thread each -- so that the launch-latency
+ *              bound sweeps of small problems overlap (the device runs 4
+ *              hardware queues per process).  The solve kernels' block shapes
+ *              are tuned on the context's stream first; the lanes' work is
+ *              ordered after earlier work on the context's stream and later
+ *              work after it.  With fixed block shapes (autotune 0) the
+ *              results do not depend on the lane count.  One lane while a
+ *              kernel class is being timed.
  *   "block_gmres" 1: hsw_solve runs block GMRES(k) (Sec. 2.4 names block
  *              variants of GMRES as a way to lower the iteration count): the
  *              right-hand sides of a problem, in groups of at most 16, share

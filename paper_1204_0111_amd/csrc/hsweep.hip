@@ -16,7 +16,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -97,8 +99,19 @@ struct ProbHost {
 
 }  // namespace
 
+// A solve lane: a stream and the workspaces of the panel solves and of GMRES
+// that run on it.  Lane 0 runs on the context's stream; hsw_solve spreads the
+// problems of a context over several lanes, one host thread each.
+struct Lane {
+    hipStream_t st = nullptr;
+    void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;  // panel-solve workspace
+    int nrhs_cap = 0;
+    std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
+};
+
 struct hsw_ctx {
     hipStream_t st = nullptr;
+    int device = 0;
     hsw_precision prec = HSW_C128;
     int esz = 16;  // bytes per complex entry of the factors
     std::vector<hsw_problem> probs;
@@ -142,8 +155,11 @@ struct hsw_ctx {
     double* d_c = nullptr;
     void *d_L = nullptr, *d_G = nullptr, *d_dinv = nullptr, *d_ws[2] = {nullptr, nullptr};
     int* d_err = nullptr;
-    // solve workspace (grown on demand)
-    int nrhs_cap = 0;
+    // solve lanes (lane 0 on st; workspaces grown on demand)
+    std::vector<Lane> lanes;
+    int nlanes = 4;
+    bool in_lanes = false;  // set while hsw_solve runs problems on several lanes
+    std::mutex err_mu;
     bool autotune = true;
     bool tuned[N_RHS_KEYS] = {};
     // captured sweeps, their stream and the events joining it to st
@@ -153,9 +169,6 @@ struct hsw_ctx {
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
-    // GMRES workspace, kept between solves: (pointer, bytes) per buffer
-    std::vector<std::pair<void*, size_t>> gws;
-    void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;
 
     KernelTimer timer;
     bool assembled = false, factored = false;
@@ -164,19 +177,18 @@ struct hsw_ctx {
     std::string err;
 };
 
-#define HIPCHK(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) {                                                          \
-            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
-            return HSW_E_DEVICE;                                                         \
-        }                                                                                \
-    } while (0)
-
 static hsw_status fail(hsw_ctx* ctx, hsw_status s, const std::string& msg) {
+    std::lock_guard<std::mutex> g(ctx->err_mu);
     ctx->err = msg;
     return s;
 }
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, HSW_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
 
 hsw::LaunchTiming& hsw::launch_timing() {
     static thread_local LaunchTiming lt;
@@ -223,18 +235,29 @@ static void drop_graphs(hsw_ctx* ctx) {
     ctx->graphs.clear();
 }
 
+static void free_lane(Lane& L, bool own_stream) {
+    for (auto& w : L.gws)
+        if (w.first) (void)hipFree(w.first);
+    L.gws.clear();
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    L.nrhs_cap = 0;
+    if (own_stream && L.st) (void)hipStreamDestroy(L.st);
+}
+
 static void free_all(hsw_ctx* ctx) {
     drop_graphs(ctx);
-    for (auto& w : ctx->gws)
-        if (w.first) (void)hipFree(w.first);
-    ctx->gws.clear();
+    for (size_t l = 0; l < ctx->lanes.size(); ++l) free_lane(ctx->lanes[l], l > 0);
+    ctx->lanes.clear();
     for (hipEvent_t& e : ctx->gev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->gst) (void)hipStreamDestroy(ctx->gst);
     void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist,
                     ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
                     ctx->d_L, ctx->d_G != ctx->d_L ? ctx->d_G : nullptr, ctx->d_dinv, ctx->d_ws[0],
-                    ctx->d_ws[1], ctx->d_err, ctx->d_xmid, ctx->d_xu, ctx->d_c2, ctx->d_T};
+                    ctx->d_ws[1], ctx->d_err, ctx->d_T};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -676,6 +699,9 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     }
     hsw_ctx* ctx = new hsw_ctx();
     ctx->st = (hipStream_t)stream;
+    ctx->lanes.resize(1);
+    ctx->lanes[0].st = ctx->st;
+    if (hipGetDevice(&ctx->device) != hipSuccess) ctx->device = 0;
     if (const char* at = std::getenv("HSW_AUTOTUNE")) ctx->autotune = std::string(at) != "0";
     ctx->prec = prec;
     ctx->esz = prec == HSW_C128 ? 16 : 8;
@@ -838,6 +864,9 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->use_graph = value != 0;
     } else if (k == "autotune") {
         ctx->autotune = value != 0;
+    } else if (k == "solve_lanes") {
+        if (value < 1 || value > 16) return fail(ctx, HSW_E_INVAL, "solve_lanes is 1..16");
+        ctx->nlanes = (int)value;
     } else if (k == "block_gmres") {
         ctx->block_gmres = value != 0;
     } else if (k == "inverse_by_depth") {
@@ -1049,19 +1078,19 @@ extern "C" hsw_status hsw_setup(hsw_ctx* ctx) {
 
 // ---------------------------------------------------------------------------
 template <typename T>
-static hsw_status ensure_solve_ws(hsw_ctx* ctx, int nrhs) {
-    if (nrhs <= ctx->nrhs_cap) return HSW_OK;
-    HIPCHK(hipStreamSynchronize(ctx->st));
-    drop_graphs(ctx);  // they hold the old workspace addresses
-    for (void** p : {&ctx->d_xmid, &ctx->d_xu, &ctx->d_c2}) {
+static hsw_status ensure_solve_ws(hsw_ctx* ctx, Lane& L, int nrhs) {
+    if (nrhs <= L.nrhs_cap) return HSW_OK;
+    HIPCHK(hipStreamSynchronize(L.st));
+    if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     const size_t e = sizeof(Cx<T>) * (size_t)nrhs;
-    HIPCHK(hipMalloc(&ctx->d_xmid, e * (size_t)ctx->max_naux));
-    HIPCHK(hipMalloc(&ctx->d_xu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
-    HIPCHK(hipMalloc(&ctx->d_c2, e * (size_t)std::max<int64_t>(ctx->max_c2, 1)));
-    ctx->nrhs_cap = nrhs;
+    HIPCHK(hipMalloc(&L.d_xmid, e * (size_t)ctx->max_naux));
+    HIPCHK(hipMalloc(&L.d_xu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
+    HIPCHK(hipMalloc(&L.d_c2, e * (size_t)std::max<int64_t>(ctx->max_c2, 1)));
+    L.nrhs_cap = nrhs;
     return HSW_OK;
 }
 
@@ -1074,10 +1103,10 @@ static hsw_status ensure_solve_ws(hsw_ctx* ctx, int nrhs) {
 // (two events per launch, forward launches first) times each launch: both
 // serve the autotuner.
 template <typename T>
-static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* src, int64_t ld,
-                         int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
+static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx<double>* src,
+                         int64_t ld, int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
                          int force_f = -1, int force_b = -1, hipEvent_t* ev = nullptr) {
-    hipStream_t st = ctx->st;
+    hipStream_t st = ln.st;
     const PanelDev& P = ctx->pan_h[gpanel];
     const ProbDev& Q = ctx->prob_h[P.prob];
     const PanelClass& c = ctx->classes[P.cls];
@@ -1091,9 +1120,9 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
     A.src = src;
     A.dst = dst;
     A.ld = ld;
-    A.xmid = (Cx<T>*)ctx->d_xmid;
-    A.c2 = (Cx<T>*)ctx->d_c2;
-    A.xu = (Cx<T>*)ctx->d_xu;
+    A.xmid = (Cx<T>*)ln.d_xmid;
+    A.c2 = (Cx<T>*)ln.d_c2;
+    A.xu = (Cx<T>*)ln.d_xu;
     A.naux = c.naux;
     A.c2ld = (int)std::max<int64_t>(c.c2size, 1);
     A.xuld = (int)std::max<int64_t>(c.wsize, 1);
@@ -1169,7 +1198,8 @@ static void panel_tsolve(hsw_ctx* ctx, int gpanel, int gmode, const Cx<double>* 
 template <typename T>
 static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     const int key = rhs_key(nrhs);
-    if (!ctx->autotune || ctx->tuned[key] || nrhs >= MM_MIN_RHS) return HSW_OK;
+    // inside a multi-lane solve the shapes are fixed (tuning runs on lane 0 before it)
+    if (!ctx->autotune || ctx->tuned[key] || nrhs >= MM_MIN_RHS || ctx->in_lanes) return HSW_OK;
     constexpr int REPS = 3;
     const int NS = std::max(N_FWD_SHAPES, N_BWD_SHAPES);
     int64_t plen = 1;
@@ -1209,7 +1239,7 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
                 const int gp = panels[run % panels.size()];
                 const int kf = k % N_FWD_SHAPES, kb = k % N_BWD_SHAPES;
                 const PanelDev& P = ctx->pan_h[gp];
-                panel_tsolve<T>(ctx, gp, 0, v, plen, P.lo, 0, 0, v, nrhs, kf, kb, ev.data());
+                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, nrhs, kf, kb, ev.data());
                 TCHK(hipGetLastError());
                 TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
                 for (int l = 0; l < 2 * (D + 1); ++l) {
@@ -1238,18 +1268,19 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
 
 // z := M^{-1} r (Alg. 1.5), r may equal z.
 template <typename T>
-static hsw_status sweep_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
-                             int64_t ld) {
-    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+static hsw_status sweep_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* r, Cx<double>* z,
+                             int nrhs, int64_t ld) {
+    hsw_status s = ensure_solve_ws<T>(ctx, ln, nrhs);
     if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
     if (s != HSW_OK) return s;
     const ProbHost& h = ctx->ph[prob];
     if (r != z)
         HIPCHK(hipMemcpy2DAsync(z, 16 * ld, r, 16 * ld, 16 * h.Npad, nrhs, hipMemcpyDeviceToDevice,
-                                ctx->st));
+                                ln.st));
     for (int i = 0; i < h.m; ++i)
-        panel_tsolve<T>(ctx, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs);
-    for (int i = h.m - 2; i >= 0; --i) panel_tsolve<T>(ctx, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs);
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs);
+    for (int i = h.m - 2; i >= 0; --i)
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs);
     HIPCHK(hipGetLastError());
     return HSW_OK;
 }
@@ -1259,10 +1290,11 @@ static hsw_status sweep_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<dou
 // Alg. 1.5 on it, and the result is copied to z.  The graph runs on a
 // context-owned stream joined to st by events before and after.
 template <typename T>
-static hsw_status sweep_any(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
-                            int64_t ld) {
-    if (!ctx->use_graph || ctx->timer.on) return sweep_impl<T>(ctx, prob, r, z, nrhs, ld);
-    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* r, Cx<double>* z,
+                            int nrhs, int64_t ld) {
+    if (&ln != &ctx->lanes[0] || !ctx->use_graph || ctx->timer.on || ctx->in_lanes)
+        return sweep_impl<T>(ctx, ln, prob, r, z, nrhs, ld);
+    hsw_status s = ensure_solve_ws<T>(ctx, ln, nrhs);
     if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
     if (s != HSW_OK) return s;
     const ProbHost& h = ctx->ph[prob];
@@ -1280,20 +1312,23 @@ static hsw_status sweep_any(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<doub
         ng.nrhs = nrhs;
         HIPCHK(hipMalloc(&ng.z, 16 * (size_t)N * nrhs));
         Cx<double>* zz = (Cx<double>*)ng.z;
-        const hipStream_t saved = ctx->st;
-        ctx->st = ctx->gst;
+        Lane gl;  // lane 0's workspaces on the capture stream
+        gl.st = ctx->gst;
+        gl.d_xmid = ln.d_xmid;
+        gl.d_xu = ln.d_xu;
+        gl.d_c2 = ln.d_c2;
+        gl.nrhs_cap = ln.nrhs_cap;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             for (int i = 0; i < h.m; ++i)
-                panel_tsolve<T>(ctx, h.panel_base + i, 0, zz, N, 0, 0, i < h.m - 1, zz, nrhs);
+                panel_tsolve<T>(ctx, gl, h.panel_base + i, 0, zz, N, 0, 0, i < h.m - 1, zz, nrhs);
             for (int i = h.m - 2; i >= 0; --i)
-                panel_tsolve<T>(ctx, h.panel_base + i, 1, zz, N, 0, 1, 0, zz, nrhs);
+                panel_tsolve<T>(ctx, gl, h.panel_base + i, 1, zz, N, 0, 1, 0, zz, nrhs);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(ctx->gst, &graph);
             if (e == hipSuccess) e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
             if (graph) (void)hipGraphDestroy(graph);
         }
-        ctx->st = saved;
         if (e != hipSuccess) {
             (void)hipFree(ng.z);
             return fail(ctx, HSW_E_DEVICE, std::string("sweep capture: ") + hipGetErrorString(e));
@@ -1328,8 +1363,8 @@ extern "C" hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, h
     if (s != HSW_OK) return s;
     if ((const void*)r == (const void*)z) return fail(ctx, HSW_E_INVAL, "r and z alias");
     return ctx->prec == HSW_C128
-               ? sweep_any<double>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld)
-               : sweep_any<float>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
+               ? sweep_any<double>(ctx, ctx->lanes[0], prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld)
+               : sweep_any<float>(ctx, ctx->lanes[0], prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
 }
 
 extern "C" hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel, const hsw_c128* v,
@@ -1344,14 +1379,14 @@ extern "C" hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel,
     if (s != HSW_OK) return s;
     if ((const void*)v == (const void*)y) return fail(ctx, HSW_E_INVAL, "v and y alias");
     if (ctx->prec == HSW_C128) {
-        s = ensure_solve_ws<double>(ctx, nrhs);
+        s = ensure_solve_ws<double>(ctx, ctx->lanes[0], nrhs);
         if (s != HSW_OK) return s;
-        panel_tsolve<double>(ctx, h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
+        panel_tsolve<double>(ctx, ctx->lanes[0], h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
                              (Cx<double>*)y, nrhs);
     } else {
-        s = ensure_solve_ws<float>(ctx, nrhs);
+        s = ensure_solve_ws<float>(ctx, ctx->lanes[0], nrhs);
         if (s != HSW_OK) return s;
-        panel_tsolve<float>(ctx, h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
+        panel_tsolve<float>(ctx, ctx->lanes[0], h.panel_base + panel, 0, (const Cx<double>*)v, ld, P.lo, 0, 0,
                             (Cx<double>*)y, nrhs);
     }
     HIPCHK(hipGetLastError());
@@ -1379,9 +1414,9 @@ extern "C" hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, 
 // Flexible right-preconditioned GMRES(k) of one problem, all right-hand
 // sides advanced together; classical Gram-Schmidt applied twice.
 template <typename T>
-static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x, int nrhs,
-                             const hsw_solve_opts& o, int* iters_out, double* relres_out) {
-    hipStream_t st = ctx->st;
+static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* b, Cx<double>* x,
+                             int nrhs, const hsw_solve_opts& o, int* iters_out, double* relres_out) {
+    hipStream_t st = ln.st;
     const ProbHost& hp = ctx->ph[prob];
     const ProbDev& Q = ctx->prob_h[prob];
     const int64_t N = hp.Npad, ld = N;
@@ -1398,9 +1433,8 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
         if (e_ != hipSuccess) {                                                        \
-            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
             cleanup();                                                                 \
-            return HSW_E_DEVICE;                                                       \
+            return fail(ctx, HSW_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
         }                                                                              \
     } while (0)
     {
@@ -1413,9 +1447,9 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
                                 8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs,
                                 8 * (size_t)nrhs * nch, 4 * (size_t)nrhs, 4 * (size_t)nrhs};
         const size_t nslot = sizeof(bytes) / sizeof(bytes[0]);
-        if (ctx->gws.size() < nslot) ctx->gws.resize(nslot, {nullptr, 0});
+        if (ln.gws.size() < nslot) ln.gws.resize(nslot, {nullptr, 0});
         for (size_t i = 0; i < nslot; ++i) {
-            auto& w = ctx->gws[i];
+            auto& w = ln.gws[i];
             if (w.second < bytes[i]) {
                 if (w.first) GCHK(hipFree(w.first));
                 w = {nullptr, 0};
@@ -1425,7 +1459,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             *slots[i] = w.first;
         }
     }
-    hsw_status s = ensure_solve_ws<T>(ctx, nrhs);
+    hsw_status s = ensure_solve_ws<T>(ctx, ln, nrhs);
     if (s != HSW_OK) { cleanup(); return s; }
     std::vector<double> bn_h(nrhs), beta_h(nrhs), est_h(nrhs), rel(nrhs, 1.0);
     std::vector<int> act_h(nrhs), it_h(nrhs, 0), jc_h(nrhs), done(nrhs, 0);
@@ -1461,7 +1495,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<dou
             Cx<double>* Vj = V + (int64_t)j * vs;
             Cx<double>* Vn = V + (int64_t)(j + 1) * vs;
             Cx<double>* Zj = Z + (int64_t)j * vs;
-            s = sweep_any<T>(ctx, prob, Vj, Zj, nrhs, ld);
+            s = sweep_any<T>(ctx, ln, prob, Vj, Zj, nrhs, ld);
             if (s != HSW_OK) { cleanup(); return s; }
             timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st); });
@@ -1590,10 +1624,10 @@ inline void apply_rot(const Rot& R, zc* x) {
 }  // namespace
 
 template <typename T>
-static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x,
-                                    int64_t ld, int p, const hsw_solve_opts& o, int* iters_out,
-                                    double* relres_out) {
-    hipStream_t st = ctx->st;
+static hsw_status block_gmres_group(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* b,
+                                    Cx<double>* x, int64_t ld, int p, const hsw_solve_opts& o,
+                                    int* iters_out, double* relres_out) {
+    hipStream_t st = ln.st;
     const ProbHost& hp = ctx->ph[prob];
     const ProbDev& Q = ctx->prob_h[prob];
     const int64_t N = hp.Npad;
@@ -1610,9 +1644,9 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b,
                                 16 * (size_t)nchb * LDH * p, 16 * (size_t)k * p * p, 8 * (size_t)p,
                                 8 * (size_t)p * nchn, 4 * (size_t)p};
         const size_t nslot = sizeof(bytes) / sizeof(bytes[0]), base = 16;
-        if (ctx->gws.size() < base + nslot) ctx->gws.resize(base + nslot, {nullptr, 0});
+        if (ln.gws.size() < base + nslot) ln.gws.resize(base + nslot, {nullptr, 0});
         for (size_t i = 0; i < nslot; ++i) {
-            auto& w = ctx->gws[base + i];
+            auto& w = ln.gws[base + i];
             if (w.second < bytes[i]) {
                 if (w.first) HIPCHK(hipFree(w.first));
                 w = {nullptr, 0};
@@ -1622,7 +1656,7 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b,
             *slots[i] = w.first;
         }
     }
-    hsw_status s = ensure_solve_ws<T>(ctx, p);
+    hsw_status s = ensure_solve_ws<T>(ctx, ln, p);
     if (s != HSW_OK) return s;
     std::vector<double> bn_h(p), nrm_h(p), rel(p, 1.0);
     std::vector<int> its(p, 0);
@@ -1688,7 +1722,7 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b,
             Cx<double>* Vj = V + (int64_t)j * q * N;
             Cx<double>* W = V + (int64_t)(j + 1) * q * N;
             Cx<double>* Zj = Z + (int64_t)j * q * N;
-            s = sweep_any<T>(ctx, prob, Vj, Zj, q, N);
+            s = sweep_any<T>(ctx, ln, prob, Vj, Zj, q, N);
             if (s != HSW_OK) return s;
             timed(ctx, "matvec", 1, (double)N * (32.0 * q + 8.0), 56.0 * (double)N * q,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, W, nullptr, N, q, 0, st); });
@@ -1776,16 +1810,89 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, int prob, const Cx<double>* b,
 }
 
 template <typename T>
-static hsw_status block_gmres_impl(hsw_ctx* ctx, int prob, const Cx<double>* b, Cx<double>* x, int nrhs,
-                                   const hsw_solve_opts& o, int* iters_out, double* relres_out) {
+static hsw_status block_gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* b,
+                                   Cx<double>* x, int nrhs, const hsw_solve_opts& o, int* iters_out,
+                                   double* relres_out) {
     const int64_t ld = ctx->ph[prob].Npad;
     hsw_status worst = HSW_OK;
     for (int g0 = 0; g0 < nrhs; g0 += BLOCK_KRYLOV_MAX) {
         const int ng = std::min(BLOCK_KRYLOV_MAX, nrhs - g0);
-        hsw_status s = block_gmres_group<T>(ctx, prob, b + g0 * ld, x + g0 * ld, ld, ng, o,
+        hsw_status s = block_gmres_group<T>(ctx, ln, prob, b + g0 * ld, x + g0 * ld, ld, ng, o,
                                             iters_out + g0, relres_out + g0);
         if (s == HSW_E_BREAKDOWN)  // dependent right-hand sides: one Krylov space per column
-            s = gmres_impl<T>(ctx, prob, b + g0 * ld, x + g0 * ld, ng, o, iters_out + g0, relres_out + g0);
+            s = gmres_impl<T>(ctx, ln, prob, b + g0 * ld, x + g0 * ld, ng, o, iters_out + g0,
+                              relres_out + g0);
+        if (s != HSW_OK && s != HSW_E_NOCONV) return s;
+        if (s == HSW_E_NOCONV) worst = s;
+    }
+    return worst;
+}
+
+template <typename T>
+static hsw_status solve_problem(hsw_ctx* ctx, Lane& ln, int k, const Cx<double>* bk, Cx<double>* xk,
+                                int nr, const hsw_solve_opts& o, int* it, double* rr) {
+    return ctx->block_gmres ? block_gmres_impl<T>(ctx, ln, k, bk, xk, nr, o, it, rr)
+                            : gmres_impl<T>(ctx, ln, k, bk, xk, nr, o, it, rr);
+}
+
+// Solve every problem of the context.  With several problems, they are spread
+// over up to nlanes lanes (streams with their own workspaces), one host thread
+// each, so that the latency-bound launches of small problems overlap; the
+// solve-kernel shapes are tuned on lane 0 first.  Work on the lanes is ordered
+// after earlier work on the context's stream, and later work after it.
+template <typename T>
+static hsw_status solve_all(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128* const* x,
+                            const int32_t* nrhs, const hsw_solve_opts& o, std::vector<int>& its,
+                            std::vector<double>& rrs, std::vector<int>& offs) {
+    const int np = (int)ctx->ph.size();
+    const int nl = (ctx->timer.on || np < 2 || ctx->nlanes < 2) ? 1 : std::min(ctx->nlanes, np);
+    std::vector<hsw_status> st(np, HSW_OK);
+    auto run = [&](int l) {
+        for (int k = l; k < np; k += nl)
+            st[k] = solve_problem<T>(ctx, ctx->lanes[l], k, (const Cx<double>*)b[k], (Cx<double>*)x[k],
+                                     nrhs[k], o, its.data() + offs[k], rrs.data() + offs[k]);
+    };
+    if (nl == 1) {
+        run(0);
+    } else {
+        // tune the shapes the lanes will use, on lane 0
+        // (GMRES sweeps all of a problem's right-hand sides at once; block
+        // GMRES sweeps its active columns, any count up to the group size)
+        for (int k = 0; k < np; ++k) {
+            const int top = ctx->block_gmres ? std::min(nrhs[k], BLOCK_KRYLOV_MAX) : nrhs[k];
+            for (int q = ctx->block_gmres ? 1 : top; q <= top; ++q) {
+                hsw_status s = ensure_solve_ws<T>(ctx, ctx->lanes[0], q);
+                if (s == HSW_OK) s = tune_solve<T>(ctx, q);
+                if (s != HSW_OK) return s;
+            }
+        }
+        if ((int)ctx->lanes.size() < nl) ctx->lanes.resize(nl);
+        hipEvent_t ev = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, ctx->st));
+        for (int l = 1; l < nl; ++l) {
+            if (!ctx->lanes[l].st) HIPCHK(hipStreamCreateWithFlags(&ctx->lanes[l].st, hipStreamNonBlocking));
+            HIPCHK(hipStreamWaitEvent(ctx->lanes[l].st, ev, 0));
+        }
+        ctx->in_lanes = true;
+        std::vector<std::thread> th;
+        for (int l = 1; l < nl; ++l)
+            th.emplace_back([&, l] {
+                (void)hipSetDevice(ctx->device);
+                run(l);
+            });
+        run(0);
+        for (auto& t : th) t.join();
+        ctx->in_lanes = false;
+        for (int l = 1; l < nl; ++l) {
+            HIPCHK(hipEventRecord(ev, ctx->lanes[l].st));
+            HIPCHK(hipStreamWaitEvent(ctx->st, ev, 0));
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        (void)hipEventDestroy(ev);
+    }
+    hsw_status worst = HSW_OK;
+    for (hsw_status s : st) {
         if (s != HSW_OK && s != HSW_E_NOCONV) return s;
         if (s == HSW_E_NOCONV) worst = s;
     }
@@ -1801,33 +1908,24 @@ extern "C" hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128
     if (opts) o = *opts;
     if (o.restart_k < 1 || o.maxit < 1 || !(o.rtol > 0))
         return fail(ctx, HSW_E_INVAL, "restart_k >= 1, maxit >= 1, rtol > 0 required");
+    const int np = (int)ctx->ph.size();
+    std::vector<int> offs(np + 1, 0);
+    for (int k = 0; k < np; ++k) {
+        if (!b[k] || !x[k] || nrhs[k] < 1) return fail(ctx, HSW_E_INVAL, "bad right-hand side block");
+        offs[k + 1] = offs[k] + nrhs[k];
+    }
+    std::vector<int> its(offs[np], 0);
+    std::vector<double> rrs(offs[np], 0.0);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, ctx->st));
-    hsw_status worst = HSW_OK;
-    int off = 0, itmax = 0;
-    for (size_t k = 0; k < ctx->ph.size(); ++k) {
-        if (!b[k] || !x[k] || nrhs[k] < 1) return fail(ctx, HSW_E_INVAL, "bad right-hand side block");
-        std::vector<int> it(nrhs[k]);
-        std::vector<double> rr(nrhs[k]);
-        const Cx<double>* bk = (const Cx<double>*)b[k];
-        Cx<double>* xk = (Cx<double>*)x[k];
-        hsw_status s;
-        if (ctx->block_gmres)
-            s = ctx->prec == HSW_C128 ? block_gmres_impl<double>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data())
-                                      : block_gmres_impl<float>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data());
-        else
-            s = ctx->prec == HSW_C128 ? gmres_impl<double>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data())
-                                      : gmres_impl<float>(ctx, (int)k, bk, xk, nrhs[k], o, it.data(), rr.data());
-        if (s != HSW_OK && s != HSW_E_NOCONV) return s;
-        if (s == HSW_E_NOCONV) worst = s;
-        for (int r = 0; r < nrhs[k]; ++r) {
-            if (info && info->iters) info->iters[off + r] = it[r];
-            if (info && info->relres) info->relres[off + r] = rr[r];
-            itmax = std::max(itmax, it[r]);
-        }
-        off += nrhs[k];
+    const hsw_status worst = ctx->prec == HSW_C128 ? solve_all<double>(ctx, b, x, nrhs, o, its, rrs, offs)
+                                                   : solve_all<float>(ctx, b, x, nrhs, o, its, rrs, offs);
+    if (worst != HSW_OK && worst != HSW_E_NOCONV) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return worst;
     }
     HIPCHK(hipEventRecord(e1, ctx->st));
     HIPCHK(hipEventSynchronize(e1));
@@ -1835,13 +1933,19 @@ extern "C" hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    int itmax = 0;
+    for (int r = 0; r < offs[np]; ++r) {
+        if (info && info->iters) info->iters[r] = its[r];
+        if (info && info->relres) info->relres[r] = rrs[r];
+        itmax = std::max(itmax, its[r]);
+    }
     if (info) {
         info->iters_max = itmax;
         info->t_setup = ctx->t_setup;
         info->t_solve = ms * 1e-3;
         info->bad_problem = info->bad_panel = info->bad_front = info->bad_pivot = -1;
     }
-    if (worst == HSW_E_NOCONV) ctx->err = "GMRES did not reach rtol within maxit";
+    if (worst == HSW_E_NOCONV) fail(ctx, HSW_E_NOCONV, "GMRES did not reach rtol within maxit");
     return worst;
 }
 

@@ -430,3 +430,35 @@ def test_empty_and_bad_right_hand_side_blocks():
         S.apply(0, r[:, : N - 1])
     with pytest.raises(HswError):
         S.apply(3, r)
+
+
+@pytest.mark.parametrize("block", [0, 1])
+def test_solve_lanes_give_the_same_solutions(block):
+    """Six problems of different sizes in one context, solved on one lane and
+    on four (streams and host threads of their own): with fixed block shapes
+    the solutions agree bit for bit, and each reaches the FP64 true residual."""
+    from paper_1204_0111_amd.hsweep import Solver
+    Ps = [case(n=(9 + k, 8 + (k % 3), 7 + 2 * k), gamma=2, d=2, leaf=3, seed=40 + k,
+               model="layered" if k % 2 else "grf") for k in range(6)]
+    bs = [wl.random_complex((1 + k % 3, int(np.prod(hz.padded_shape(P["n"], P["gamma"])))), 50 + k)
+          for k, P in enumerate(Ps)]
+    out = []
+    for lanes in (1, 4):
+        S = Solver(Ps, precision="c64")
+        S.set_option("autotune", 0)
+        S.set_option("solve_lanes", lanes)
+        S.set_option("block_gmres", block)
+        S.assemble([P["c"] for P in Ps])
+        S.setup()
+        xs, info = S.solve([_cuda(b) for b in bs], rtol=1e-5, restart=10)
+        assert info["status"] == "HSW_OK"
+        out.append(([x.cpu().numpy() for x in xs], info["iters"]))
+        S.close()
+    (x1, i1), (x4, i4) = out
+    assert i1 == i4
+    for a, c in zip(x1, x4):
+        assert np.array_equal(a, c)
+    for P, b, x in zip(Ps, bs, x4):
+        A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
+        for r in range(b.shape[0]):
+            assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5
