@@ -10,7 +10,9 @@ right-hand side are resident on the device before timing starts.
 
 Prints one JSON line.  value = N_int * nrhs * K / (wall seconds of K steps).
 The complex128 path (the plain FP64 sweep) is timed the same way as the
-comparator; the CPU oracle is timed on a bounded sample (rank 0 only).
+comparator, and so is the variant whose Schur-update GEMMs take complex BF16
+inputs (FP32 accumulation, "bf16_gemm_variant"); the CPU oracle is timed on a
+bounded sample (rank 0 only).
 """
 
 import argparse
@@ -245,6 +247,8 @@ def main():
     ap.add_argument("--workload", default="grf50",
                     help="a workload name of paper_1204_0111_amd.workloads.WORKLOADS")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the variant with BF16 Schur-update GEMM inputs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pml-amp", type=float, default=None,
                     help="override the PML amplitude C (exploration only)")
@@ -280,6 +284,11 @@ def main():
     print("# c64: %s" % json.dumps(main_run), file=sys.stderr, flush=True)
     if kernels:
         print("# kernels: %s" % json.dumps(kernels), file=sys.stderr, flush=True)
+    bf16 = None
+    if not args.no_bf16:
+        # the variant with complex BF16 inputs to the Schur-update GEMMs (FP32 accumulation)
+        bf16 = run_path(Ps, bs, "c64_bf16", args.steps, args.warmup, rhs_group=args.rhs_group)
+        print("# c64_bf16: %s" % json.dumps(bf16), file=sys.stderr, flush=True)
     comp = None
     if not args.no_comparator:
         comp = run_path(Ps, bs, "c128", args.steps, args.warmup, rhs_group=args.rhs_group)
@@ -295,6 +304,7 @@ def main():
                 iters=main_run["iters"], relres=main_run["relres"],
                 t_setup_ms=main_run["t_setup_ms"], t_solve_ms=main_run["t_solve_ms"],
                 comparator=comp,
+                bf16_gemm_variant=bf16,
                 speedup_vs_fp64=(main_run["value"] / comp["value"]) if comp else None,
                 roofline=roofline_entry(kernels, "c64", args.workload) if kernels else None,
                 kernel_times_ms={k: 1e3 * v["seconds"] for k, v in kernels.items()} if kernels
