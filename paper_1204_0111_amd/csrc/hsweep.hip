@@ -1667,7 +1667,11 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, Lane& ln, int prob, const Cx<d
     for (int c = 0; c < p; ++c)
         if (!(bn_h[c] > 0)) rel[c] = 0.0;
     int total = 0;
-    std::vector<zc> H, Gr, Cs, Gm, S1, S2, Sh;
+    std::vector<zc> H, Gr, Cs, Gm;
+    // host sources of asynchronous uploads: each is rewritten only after a
+    // later synchronisation of the stream, so the upload has completed
+    std::vector<zc> Sbuf, Ybuf;
+    std::vector<int> actbuf;
     // Cholesky QR of the q vectors at W (in place); false on breakdown.
     auto cholqr = [&](Cx<double>* W, int q, std::vector<zc>& S) -> int {
         std::vector<zc> Sp[2];
@@ -1678,8 +1682,8 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, Lane& ln, int prob, const Cx<d
                 hipStreamSynchronize(st) != hipSuccess)
                 return -1;
             if (!chol_upper(Gm, q, Sp[pass])) return 0;
-            const std::vector<zc> Si = inv_upper(Sp[pass], q);
-            if (hipMemcpyAsync(Sd, Si.data(), 16 * (size_t)q * q, hipMemcpyHostToDevice, st) != hipSuccess)
+            Sbuf = inv_upper(Sp[pass], q);
+            if (hipMemcpyAsync(Sd, Sbuf.data(), 16 * (size_t)q * q, hipMemcpyHostToDevice, st) != hipSuccess)
                 return -1;
             launch_bcombine(W, N, q, Sd, q, W, N, nullptr, N, 1.0, 0.0, st);
         }
@@ -1704,7 +1708,8 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, Lane& ln, int prob, const Cx<d
             if (act[u] != u)
                 HIPCHK(hipMemcpyAsync(V + (int64_t)u * N, V + (int64_t)act[u] * N, 16 * (size_t)N,
                                       hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(actd, act.data(), 4 * q, hipMemcpyHostToDevice, st));
+        actbuf = act;
+        HIPCHK(hipMemcpyAsync(actd, actbuf.data(), 4 * q, hipMemcpyHostToDevice, st));
         std::vector<zc> S0;
         const int ok0 = cholqr(V, q, S0);
         if (ok0 < 0) return fail(ctx, HSW_E_DEVICE, "block GMRES transfer failed");
@@ -1789,7 +1794,8 @@ static hsw_status block_gmres_group(hsw_ctx* ctx, Lane& ln, int prob, const Cx<d
         }
         // Y = R^{-1} Gr over the first jdone * q rows; x[act] += Z Y
         const int m = jdone * q;
-        std::vector<zc> Y((size_t)m * q, zc(0, 0));  // row-major (i, c)
+        std::vector<zc>& Y = Ybuf;
+        Y.assign((size_t)m * q, zc(0, 0));  // row-major (i, c)
         for (int c = 0; c < q; ++c)
             for (int i = m - 1; i >= 0; --i) {
                 zc t = Gr[(size_t)c * ldh + i];
