@@ -49,8 +49,12 @@ __device__ inline Cx<T> keep(bool on, Cx<T> v) {
 
 // Loads in flight per thread: the G entries a thread consumes are issued in
 // rounds of QL before the previous round is used.
-template <typename T> struct PassLoads { static constexpr int QL = 16; };
+template <typename T> struct PassLoads { static constexpr int QL = 8; };
 template <> struct PassLoads<double> { static constexpr int QL = 8; };
+static_assert((PassLoads<float>::QL & (PassLoads<float>::QL - 1)) == 0 &&
+                  (PassLoads<double>::QL & (PassLoads<double>::QL - 1)) == 0,
+              "loads per round must be a power of two (the backward passes split a wave's "
+              "power-of-two column count into rounds)");
 
 // Forward pass over the fronts of one depth.  Workgroup = (front, RB rows),
 // NT threads as RB rows x NT/RB column phases.  Rows of G_TL = L_F^{-1}
@@ -203,6 +207,7 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
     constexpr int QW = CW < QL / RC ? CW : (QL / RC > 0 ? QL / RC : 1);  // columns per pass
     constexpr int RU = QL / QW > 0 ? QL / QW : 1;                  // unrolled row steps
     static_assert(CW >= 1 && CW <= 64, "column block");
+    static_assert(CW % QW == 0, "the passes must cover every column of the wave");
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
     const SolveItem it = A.items[blockIdx.x];
