@@ -659,34 +659,35 @@ static void bwd_cfg(const PassArgs<T>& A, int nwork, int nmax, hipStream_t st) {
 }
 
 // Block shapes: the tables in plan.hpp, in the same order.
+template <typename T, int I>
+static void fwd_pick(const PassArgs<T>& A, int nwork, int cfg, int smax, int nmax, hipStream_t st) {
+    if constexpr (I + 1 < N_FWD_SHAPES) {
+        if (cfg != I) {
+            fwd_pick<T, I + 1>(A, nwork, cfg, smax, nmax, st);
+            return;
+        }
+    }
+    fwd_cfg<T, FWD_SHAPES[I].block, FWD_SHAPES[I].threads>(A, nwork, smax, nmax, st);
+}
+template <typename T, int I>
+static void bwd_pick(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t st) {
+    if constexpr (I + 1 < N_BWD_SHAPES) {
+        if (cfg != I) {
+            bwd_pick<T, I + 1>(A, nwork, cfg, nmax, st);
+            return;
+        }
+    }
+    bwd_cfg<T, BWD_SHAPES[I].block, BWD_SHAPES[I].threads>(A, nwork, nmax, st);
+}
 template <typename T>
 void launch_fwd(const PassArgs<T>& A, int nwork, int cfg, int smax, int nmax, hipStream_t st) {
     if (nwork <= 0) return;
-    switch (cfg) {
-        case 0: fwd_cfg<T, FWD_SHAPES[0].block, FWD_SHAPES[0].threads>(A, nwork, smax, nmax, st); break;
-        case 1: fwd_cfg<T, FWD_SHAPES[1].block, FWD_SHAPES[1].threads>(A, nwork, smax, nmax, st); break;
-        case 2: fwd_cfg<T, FWD_SHAPES[2].block, FWD_SHAPES[2].threads>(A, nwork, smax, nmax, st); break;
-        case 3: fwd_cfg<T, FWD_SHAPES[3].block, FWD_SHAPES[3].threads>(A, nwork, smax, nmax, st); break;
-        case 4: fwd_cfg<T, FWD_SHAPES[4].block, FWD_SHAPES[4].threads>(A, nwork, smax, nmax, st); break;
-        case 5: fwd_cfg<T, FWD_SHAPES[5].block, FWD_SHAPES[5].threads>(A, nwork, smax, nmax, st); break;
-        case 6: fwd_cfg<T, FWD_SHAPES[6].block, FWD_SHAPES[6].threads>(A, nwork, smax, nmax, st); break;
-        default: fwd_cfg<T, FWD_SHAPES[7].block, FWD_SHAPES[7].threads>(A, nwork, smax, nmax, st); break;
-    }
+    fwd_pick<T, 0>(A, nwork, cfg, smax, nmax, st);
 }
 template <typename T>
 void launch_bwd(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t st) {
     if (nwork <= 0) return;
-    switch (cfg) {
-        case 0: bwd_cfg<T, BWD_SHAPES[0].block, BWD_SHAPES[0].threads>(A, nwork, nmax, st); break;
-        case 1: bwd_cfg<T, BWD_SHAPES[1].block, BWD_SHAPES[1].threads>(A, nwork, nmax, st); break;
-        case 2: bwd_cfg<T, BWD_SHAPES[2].block, BWD_SHAPES[2].threads>(A, nwork, nmax, st); break;
-        case 3: bwd_cfg<T, BWD_SHAPES[3].block, BWD_SHAPES[3].threads>(A, nwork, nmax, st); break;
-        case 4: bwd_cfg<T, BWD_SHAPES[4].block, BWD_SHAPES[4].threads>(A, nwork, nmax, st); break;
-        case 5: bwd_cfg<T, BWD_SHAPES[5].block, BWD_SHAPES[5].threads>(A, nwork, nmax, st); break;
-        case 6: bwd_cfg<T, BWD_SHAPES[6].block, BWD_SHAPES[6].threads>(A, nwork, nmax, st); break;
-        case 7: bwd_cfg<T, BWD_SHAPES[7].block, BWD_SHAPES[7].threads>(A, nwork, nmax, st); break;
-        default: bwd_cfg<T, BWD_SHAPES[8].block, BWD_SHAPES[8].threads>(A, nwork, nmax, st); break;
-    }
+    bwd_pick<T, 0>(A, nwork, cfg, nmax, st);
 }
 
 template <typename T>
