@@ -249,6 +249,22 @@ __device__ inline Cx<T> shfl_cx(Cx<T> v, int src) {
     return cx<T>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 
+// The value of lane L (a compile-time constant) in every lane, read through a
+// scalar register (no LDS round trip, unlike a shuffle).
+__device__ inline float lane_bcast(float v, int L) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+__device__ inline double lane_bcast(double v, int L) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), L);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), L);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ inline Cx<T> lane_bcast_cx(Cx<T> v, int L) {
+    return cx<T>(lane_bcast(v.re, L), lane_bcast(v.im, L));
+}
+
 // Reciprocal of a pivot: a power-of-two prescale keeps |b|^2 in range; in
 // FP32 the hardware reciprocal (about one ulp) replaces the division.
 __device__ inline Cx<float> pivot_recip(Cx<float> b) {
@@ -265,7 +281,7 @@ template <int m, typename T>
 __device__ inline void diag16_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, int l, int c0, int w,
                                    Cx<T>* dv, Cx<T>* __restrict__ dinv, int& first_bad) {
     constexpr int src = 16 * (m & 3);  // lanes holding column m: l / 16 == m % 4, register m / 4
-    const Cx<T> d = shfl_cx(a[m >> 2], m + src);
+    const Cx<T> d = lane_bcast_cx(a[m >> 2], m + src);  // the pivot, from one fixed lane
     const Cx<T> idm = pivot_recip(d);
     const Cx<T> aim = shfl_cx(a[m >> 2], i + src);
     const Cx<T> li = aim * idm;
