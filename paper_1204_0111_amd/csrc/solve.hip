@@ -64,6 +64,9 @@ template <typename T, int RC, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     constexpr int P = NT / RB;
     constexpr int QL = PassLoads<T>::QL;
+    static_assert(RB >= 1 && RB <= 64 && 64 % RB == 0 && NT % 64 == 0,
+                  "a row block lies inside one wave: the phases of a row are reduced by "
+                  "shuffles within the wave, then one partial per wave");
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* sm = reinterpret_cast<Cx<T>*>(smem_raw);
     const SolveItem it = A.items[blockIdx.x];
