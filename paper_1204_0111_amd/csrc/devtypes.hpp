@@ -103,7 +103,7 @@ struct SolveItem {
     // the front's cells, a rectangle: (x0 | y0 << 16) and (cells per row |
     // cells << 16); pivot e is cell e mod cells (row-major) on aux plane e / cells
     int32_t cell0, cellw;
-    int32_t pad;
+    int32_t leaf;            // 1 if the front has no children
 };
 static_assert(sizeof(SolveItem) == 64, "SolveItem is one 64-byte scalar load");
 

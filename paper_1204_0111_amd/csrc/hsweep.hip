@@ -64,10 +64,15 @@ struct SolveLevel {
     int fcount[N_FWD_SHAPES] = {}, bcount[N_BWD_SHAPES] = {};
     int fsel[N_RHS_KEYS] = {}, bsel[N_RHS_KEYS] = {};  // shape in use, per right-hand-side group
     int smax = 0, nmax = 0;
-    // algorithmic traffic in complex entries: factor part, and per right-hand side
-    // algorithmic traffic: G entries, and bytes per right-hand side of the
-    // vectors each pass reads and writes
-    double g_entries = 0, fwd_vec_bytes = 0, bwd_vec_bytes = 0, cmac = 0;
+    // algorithmic traffic: bytes per right-hand side of the vectors each pass
+    // reads and writes, and the G entries a pass needs (also its complex
+    // multiply-adds per right-hand side): those of the fronts with children,
+    // plus, for the leaves, only the columns from the first pivot on plane p
+    // (p = 0..nz): the passes skip the columns of a leaf that multiply exact zeros
+    double fwd_vec_bytes = 0, bwd_vec_bytes = 0;
+    double g_inner = 0;
+    std::vector<double> g_leaf;
+    double g_need(int p) const { return g_inner + g_leaf[p]; }
 };
 
 struct KernelTimer {
@@ -641,6 +646,7 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 it.cxu1 = c.child1[f] >= 0 ? c.woff[c.child1[f]] : -1;
                 it.cell0 = c.cell0[f];
                 it.cellw = c.cellw[f];
+                it.leaf = c.child0[f] < 0 && c.child1[f] < 0;
                 return it;
             };
             for (int k = 0; k < N_FWD_SHAPES; ++k) {
@@ -661,7 +667,17 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 sl.bcount[k] = (int)(sitems.size() - sl.boff[k]);
                 xcd_group_by(sitems, sl.boff[k], sitems.size(), [](const SolveItem& q) { return q.loff; });
             }
+            sl.g_leaf.assign(c.nz + 1, 0.0);
             for (int f : c.at_depth[d]) {
+                if (c.child0[f] < 0 && c.child1[f] < 0) {
+                    const int cells = c.cellw[f] >> 16;
+                    for (int p = 0; p <= c.nz; ++p) {
+                        const double r = std::max(0, c.s[f] - p * cells);
+                        sl.g_leaf[p] += r * (r + 1) / 2 + (double)c.u[f] * r;
+                    }
+                } else {
+                    sl.g_inner += (double)c.s[f] * (c.s[f] + 1) / 2 + (double)c.u[f] * c.s[f];
+                }
                 sl.smax = std::max(sl.smax, c.s[f]);
                 sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
                 const double sd = c.s[f], ud = c.u[f];
@@ -669,14 +685,12 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 for (int ch : {c.child0[f], c.child1[f]})
                     if (ch >= 0) uc += c.u[ch];
                 const double es = ctx->esz;
-                sl.g_entries += sd * (sd + 1) / 2 + ud * sd;  // lower G_TL and G_BL
                 // forward: right-hand side (complex128, deepest use), children's
                 // contributions, 1/D, x_mid and the update part written
                 sl.fwd_vec_bytes += 16 * sd + es * (uc + 3 * sd + ud);
                 // backward: x_mid and x_U read, x_S to the grid (complex128) and
                 // to the children's update-set values
                 sl.bwd_vec_bytes += es * (sd + ud + uc) + 16 * sd;
-                sl.cmac += sd * (sd + 1) / 2 + ud * sd;          // per right-hand side
             }
             const int dflt = sl.nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
             for (int key = 0; key < N_RHS_KEYS; ++key) sl.fsel[key] = sl.bsel[key] = dflt;
@@ -1142,6 +1156,9 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     const auto& lv = ctx->slevels[P.cls];
     const double es = sizeof(Cx<T>);
     const int key = rhs_key(nrhs);
+    // G entries the passes need: leaves from their first live pivot's plane
+    // (forward) or from their first plane of the panel's own (backward)
+    const int pf = gmode == 0 ? P.ga : P.nz - 1, pb = P.ga;
     int li = 0;
     auto run = [&](const char* cls, int count, double bytes, double flops, auto&& launch) {
         if (ev) {
@@ -1160,14 +1177,14 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         for (int d = c.maxdepth; d >= 0; --d) {
             const int fs = mm_fwd_shape<T>();
             A.items = ctx->d_sitems + lv[d].foff[fs];
-            run("fwd", lv[d].fcount[fs], es * lv[d].g_entries * ((nrhs + 15) / 16) + nrhs * lv[d].fwd_vec_bytes,
-                8.0 * nrhs * lv[d].cmac, [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], st); });
+            run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * ((nrhs + 15) / 16) + nrhs * lv[d].fwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pf), [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], st); });
         }
         A.mode = emode;
         for (int d = 0; d <= c.maxdepth; ++d) {
             A.items = ctx->d_sitems + lv[d].boff[MM_BWD_SHAPE];
-            run("bwd", lv[d].bcount[MM_BWD_SHAPE], es * lv[d].g_entries * ((nrhs + 15) / 16) + nrhs * lv[d].bwd_vec_bytes,
-                8.0 * nrhs * lv[d].cmac, [&] { launch_bwd_mm<T>(A, lv[d].bcount[MM_BWD_SHAPE], st); });
+            run("bwd", lv[d].bcount[MM_BWD_SHAPE], es * lv[d].g_need(pb) * ((nrhs + 15) / 16) + nrhs * lv[d].bwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[MM_BWD_SHAPE], st); });
         }
         return;
     }
@@ -1175,16 +1192,16 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     for (int d = c.maxdepth; d >= 0; --d) {
         const int k = force_f >= 0 ? force_f : lv[d].fsel[key];
         A.items = ctx->d_sitems + lv[d].foff[k];
-        run("fwd", lv[d].fcount[k], es * lv[d].g_entries + nrhs * lv[d].fwd_vec_bytes,
-            8.0 * nrhs * lv[d].cmac,
+        run("fwd", lv[d].fcount[k], es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec_bytes,
+            8.0 * nrhs * lv[d].g_need(pf),
             [&] { launch_fwd<T>(A, lv[d].fcount[k], k, lv[d].smax, lv[d].nmax, st); });
     }
     A.mode = emode;
     for (int d = 0; d <= c.maxdepth; ++d) {
         const int k = force_b >= 0 ? force_b : lv[d].bsel[key];
         A.items = ctx->d_sitems + lv[d].boff[k];
-        run("bwd", lv[d].bcount[k], es * lv[d].g_entries + nrhs * lv[d].bwd_vec_bytes,
-            8.0 * nrhs * lv[d].cmac,
+        run("bwd", lv[d].bcount[k], es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec_bytes,
+            8.0 * nrhs * lv[d].g_need(pb),
             [&] { launch_bwd<T>(A, lv[d].bcount[k], k, lv[d].nmax, st); });
     }
 }

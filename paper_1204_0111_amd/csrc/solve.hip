@@ -47,6 +47,25 @@ __device__ inline Cx<T> keep(bool on, Cx<T> v) {
     return cx<T>(on ? v.re : (T)0, on ? v.im : (T)0);
 }
 
+// Pivots of a front are ordered plane by plane (pivot e on auxiliary plane
+// e / cells).  A leaf front has no children, so its forward-pass vector is
+// the right-hand side alone: zero on the ga auxiliary PML planes in mode 0
+// (the zero extension of the panel) and zero below the last plane in mode 1
+// (the coupling J_{i+1,i}^T reaches the last plane only).  Returns the first
+// pivot that can hold a non-zero entry; the product skips the columns before
+// it, which multiply exact zeros.
+template <typename T>
+__device__ inline int leaf_first_live(const PassArgs<T>& A, const SolveItem& it) {
+    if (!it.leaf) return 0;
+    return (A.mode == 0 ? A.ga : A.nz - 1) * (it.cellw >> 16);
+}
+// The backward pass of a leaf writes only the pivots on the panel's own
+// planes (the auxiliary ones are neither extracted nor needed by children):
+// true when columns [c0, c0 + cb) all lie on auxiliary planes.
+__device__ inline bool leaf_aux_block(const SolveItem& it, int ga, int c0, int cb) {
+    return it.leaf && c0 + cb <= ga * (it.cellw >> 16);
+}
+
 // Loads in flight per thread: the G entries a thread consumes are issued in
 // rounds of QL before the previous round is used.
 template <typename T> struct PassLoads { static constexpr int QL = 8; };
@@ -79,10 +98,15 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     const int lr = tid % RB, ph = tid / RB;
     const int row = it.blk + lr;
     const int kend = (it.blk + RB <= s) ? it.blk + RB : s;
+    const int k0 = leaf_first_live(A, it);
     const Cx<T>* g = A.G + it.loff + min(row, n - 1);
     Cx<T> cur[QL];
 #pragma unroll
-    for (int q = 0; q < QL; ++q) cur[q] = g[(int64_t)min(ph + P * q, kend - 1) * n];
+    for (int q = 0; q < QL; ++q) cur[q] = cx<T>(0, 0);
+    if (k0 < kend) {
+#pragma unroll
+        for (int q = 0; q < QL; ++q) cur[q] = g[(int64_t)min(k0 + ph + P * q, kend - 1) * n];
+    }
     const int* map0 = A.cmap + it.moff;
     const int* map1 = map0 + n;
     // the output row's operands (threads of phase 0)
@@ -108,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     }
     // front vector: right-hand side on the panel plus the children's slots;
     // slots a child does not cover hold stale values and are masked out
-    for (int k = tid; k < s; k += NT) {
+    for (int k = k0 + tid; k < s; k += NT) {
         const int b = pivot_box(it, A.Nx, A.NxNy, k);
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
         const bool h0 = map0[k] >= 0, h1 = map1[k] >= 0;
@@ -143,7 +167,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     Cx<T> acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = cx<T>(0, 0);
-    for (int k = ph; k < kend; k += QL * P) {
+    for (int k = k0 + ph; k < kend; k += QL * P) {
         const int kn = k + QL * P;
         Cx<T> nxt[QL];
         if (kn < kend) {
@@ -214,6 +238,7 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
     const SolveItem it = A.items[blockIdx.x];
+    if (leaf_aux_block(it, A.ga, it.blk, CB)) return;
     const int n = it.n, s = it.s;
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, A.nrhs - rhs0);
@@ -428,9 +453,11 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
         are[t] = V4{0, 0, 0, 0};
         aim[t] = V4{0, 0, 0, 0};
     }
-    const int nch = (kend + KC - 1) / KC;
+    // chunks from the one holding the first live pivot (entries before it are zeros)
+    const int kb = (leaf_first_live(A, it) / KC) * KC;
+    const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
     int ch = wave;
-    if (ch < nch) load(ch * KC, ga, vv);
+    if (ch < nch) load(kb + ch * KC, ga, vv);
     for (; ch < nch; ch += 4) {
         const bool more = ch + 4 < nch;
 #pragma unroll
@@ -440,7 +467,7 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
             Vim[wave][e >> 4][e & 15] = vv[j].im;
         }
         wave_lds_sync();
-        if (more) load((ch + 4) * KC, gn, vn);
+        if (more) load(kb + (ch + 4) * KC, gn, vn);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T br = Vre[wave][4 * q + lk][li], bi = Vim[wave][4 * q + lk][li];
@@ -507,6 +534,7 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
     const SolveItem it = A.items[blockIdx.x];  // items of 16 columns
+    if (leaf_aux_block(it, A.ga, it.blk, 16)) return;
     const int n = it.n, s = it.s;
     const int rhs0 = blockIdx.y * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
