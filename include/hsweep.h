@@ -194,6 +194,8 @@ hsw_status hsw_get_front(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_
 /*
  * Host copy of the selectively inverted front used by the solves (Sec. 2.2):
  * G = [L_F^{-1}; F_BL L_F^{-1}], (s+u) x s column-major, upcast to complex128.
+ * Columns the inversion did not form (before g0, see the option
+ * "full_inverse") are returned as zeros.
  */
 hsw_status hsw_get_front_inverse(const hsw_ctx* ctx, int32_t prob, int32_t panel, int32_t front,
                                  hsw_c128* G);
@@ -265,7 +267,17 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              blocks; 0: all fronts in one launch through a scratch for
  *              every L_F^{-1} (faster: the long rows of the top fronts overlap
  *              the rest).  hsw_create picks 0 when that scratch fits, else 1.
- * Changing "keep_factors" or "inverse_by_depth" requires a new hsw_setup.
+ *   "full_inverse" 1: every column of every G is formed; 0 (default): a
+ *              leaf front (one without children) of a panel with ga > 0
+ *              auxiliary planes skips the columns of those planes, which no
+ *              solve reads: its pivots are ordered plane by plane, the solves'
+ *              vectors are zero there and the backward pass extracts only the
+ *              panel's own planes.  Its first formed column is
+ *              g0 = 64 floor(min(ga cells, s) / 64), cells being the front's
+ *              pivots per plane (s / panel_nz); the formed columns hold the
+ *              same values either way.
+ * Changing "keep_factors", "inverse_by_depth" or "full_inverse" requires a
+ * new hsw_setup.
  * Returns HSW_E_INVAL for an unknown key or value.
  */
 hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);

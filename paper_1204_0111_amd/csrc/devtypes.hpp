@@ -85,6 +85,8 @@ struct FrontInst {
     int64_t woff;                // offset of the u x u update matrix in its depth-parity workspace
     int64_t doff;                // offset of the s reciprocal pivots
     int64_t toff;                // offset of the s x s block of L_F^{-1} in the scratch of its depth
+    int32_t g0;                  // first column of G that is formed (a multiple of 64; see the inversion)
+    int32_t pad;
 };
 
 // One workgroup of a forward or backward pass of a panel solve.  Offsets are

@@ -669,7 +669,9 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
 // workgroup per 64 rows, sweeping the 64-column pivot blocks from last to
 // first:  acc = B_blk - X(:, later columns) L(later, blk)  and then
 // X_blk = acc L_blk^{-1}, both on the matrix cores; L_blk^{-1} is the
-// diagonal-block inverse the factorisation stored above the diagonal.
+// diagonal-block inverse the factorisation stored above the diagonal.  A
+// block's columns depend only on later columns, so stopping the sweep at
+// the front's first formed column g0 leaves the formed columns unchanged.
 template <typename T>
 __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                                                  const FrontInst* __restrict__ inst, const Cx<T>* Lb,
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
     __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
     __shared__ T Are[64][LDP], Aim[64][LDP];  // the block accumulator [col][row]
     const int ncb = (s + 63) / 64;
-    for (int cbk = ncb - 1; cbk >= 0; --cbk) {
+    for (int cbk = ncb - 1; cbk >= f.g0 / 64; --cbk) {
         const int c0 = cbk * 64, c1 = min(c0 + 64, s), bw = c1 - c0;
         __syncthreads();  // the previous block's columns of G, stored by every thread, are read below
         if (r0 + 63 < c0) {  // rows of the identity above the block: zero in L_F^{-1}
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
 }
 
 // L_F^{-1} from the depth's scratch over the L_F rows of the factor block
-// (rows 64 w.y .. of every pivot column), after the depth's inversion.
+// (rows 64 w.y .. of every formed pivot column), after the depth's inversion.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lf_copy(const int2* __restrict__ work,
                                                  const FrontInst* __restrict__ inst, Cx<T>* __restrict__ Lb,
@@ -781,8 +783,8 @@ __global__ __launch_bounds__(256) void k_lf_copy(const int2* __restrict__ work,
     const int r0 = w.y * 64;
     Cx<T>* L = Lb + f.loff;
     const Cx<T>* TF = Tb + f.toff;
-    for (int idx = threadIdx.x; idx < 64 * s; idx += 256) {
-        const int col = idx >> 6, row = r0 + (idx & 63);
+    for (int idx = threadIdx.x; idx < 64 * (s - f.g0); idx += 256) {
+        const int col = f.g0 + (idx >> 6), row = r0 + (idx & 63);
         if (row < s) L[(int64_t)col * n + row] = TF[(int64_t)col * s + row];
     }
 }

@@ -137,6 +137,7 @@ struct hsw_ctx {
     std::vector<int64_t> toff_all;  // scratch offsets of the one-launch layout
     int64_t inv_scratch = 0, inv_scratch_all = 0;
     bool inv_by_depth = false;
+    bool full_inverse = false;  // form every column of G (else leaves skip their auxiliary-plane columns)
     bool keep_factors = false; // keep L next to G (a separate G block) instead of inverting in place
     void* d_T = nullptr;       // L_F^{-1} scratch of one depth
     std::vector<std::vector<SolveLevel>> slevels;  // per class, per depth
@@ -268,6 +269,49 @@ static void free_all(hsw_ctx* ctx) {
 }
 
 // ---------------------------------------------------------------------------
+// First column of G the solves read, rounded down to the inversion's 64-column
+// blocks.  A leaf front's pivots are ordered plane by plane; on a panel with
+// ga auxiliary planes the forward products of its solves start at the first
+// pivot of the panel's own planes (the vector is zero before it) and the
+// backward pass writes only those pivots (a leaf has no children to feed), so
+// the columns of the auxiliary planes are never read and the inversion skips
+// their blocks.  Every other front, and every front with full_inverse, is
+// formed whole.
+static void set_inverse_columns(hsw_ctx* ctx) {
+    for (size_t i = 0; i < ctx->inst_h.size(); ++i) {
+        FrontInst& f = ctx->inst_h[i];
+        f.g0 = 0;
+        if (ctx->full_inverse || f.child0 >= 0 || f.child1 >= 0) continue;
+        const PanelDev& P = ctx->pan_h[f.panel];
+        const int cells = ctx->classes[P.cls].cellw[(int)i - P.inst_base] >> 16;
+        f.g0 = std::min(P.ga * cells, f.s) / 64 * 64;
+    }
+}
+
+// Algorithmic bytes and multiply-adds of the inversion launches and of the
+// copies of L_F^{-1}, from the formed columns of every front (s' = s - g0):
+// G written for its n rows, the trailing s' x s' part of L_F and the formed
+// columns of F_BL read; s'^3/6 + u s'^2/2 complex multiply-adds.
+static void inverse_accounting(hsw_ctx* ctx) {
+    for (Launch& l : ctx->inv_depth) l.bytes_per_esz = l.cmac = 0;
+    for (Launch& l : ctx->lfcopy_depth) l.bytes_per_esz = 0;
+    ctx->inv_launch.bytes_per_esz = ctx->inv_launch.cmac = 0;
+    ctx->lfcopy_all.bytes_per_esz = 0;
+    for (ProbHost& h : ctx->ph) h.inverse_cmac = 0;
+    for (const FrontInst& f : ctx->inst_h) {
+        const double sd = f.s - f.g0, ud = f.u, nd = f.s + f.u;
+        const double bytes = nd * sd + sd * (sd + 1) / 2 + ud * sd;
+        const double cmac = sd * sd * sd / 6 + ud * sd * sd / 2;
+        ctx->inv_depth[f.depth].bytes_per_esz += bytes;
+        ctx->inv_depth[f.depth].cmac += cmac;
+        ctx->lfcopy_depth[f.depth].bytes_per_esz += 2.0 * f.s * sd;
+        ctx->inv_launch.bytes_per_esz += bytes;
+        ctx->inv_launch.cmac += cmac;
+        ctx->lfcopy_all.bytes_per_esz += 2.0 * f.s * sd;
+        ctx->ph[ctx->pan_h[f.panel].prob].inverse_cmac += cmac;
+    }
+}
+
 static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
     std::map<std::tuple<int, int, int>, int> tree_idx;
     std::map<std::tuple<int, int, int, int>, int> cls_idx;
@@ -345,7 +389,6 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
         P.nfront = c.nfront;
         ProbHost& h = ctx->ph[P.prob];
         h.setup_cmac += c.factor_cmac;
-        h.inverse_cmac += c.inverse_cmac;
         h.apply_cmac += c.solve_cmac * (P.prob >= 0 ? 1 : 0);
         h.factor_entries += c.lsize;
         h.levels = std::max(h.levels, c.maxdepth + 1);
@@ -370,6 +413,7 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
             ctx->inst_h.push_back(fi);
         }
     }
+    set_inverse_columns(ctx);
     ctx->L_size = loff;
     ctx->D_size = doff;
     for (auto& h : ctx->ph) {
@@ -587,9 +631,6 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
             toff += (int64_t)f.s * f.s;
             const int nrb = (f.s + f.u + 63) / 64;
             for (int rb = 0; rb < nrb; ++rb) fwork.push_back(make_int2(i, rb));
-            const double sd = f.s, ud = f.u;
-            il.bytes_per_esz += (sd + ud) * sd + sd * (sd + 1) / 2 + ud * sd;
-            il.cmac += sd * sd * sd / 6 + ud * sd * sd / 2;
         }
         il.count = (int)(fwork.size() - il.off);
         xcd_group(fwork, il.off, fwork.size());
@@ -599,12 +640,8 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
         for (int i : at[d]) {
             const FrontInst& f = ctx->inst_h[i];
             for (int rb = 0; rb < (f.s + 63) / 64; ++rb) fwork.push_back(make_int2(i, rb));
-            cl.bytes_per_esz += 2.0 * f.s * f.s;
         }
         cl.count = (int)(fwork.size() - cl.off);
-        ctx->inv_launch.bytes_per_esz += il.bytes_per_esz;
-        ctx->inv_launch.cmac += il.cmac;
-        ctx->lfcopy_all.bytes_per_esz += cl.bytes_per_esz;
     }
     // the one-launch layout: every front, long rows first in the XCD order
     ctx->toff_all.assign(ctx->inst_h.size(), 0);
@@ -729,6 +766,7 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     std::vector<int2> fwork;
     std::vector<SolveItem> sitems;
     schedule_all(ctx, fwork, sitems);
+    inverse_accounting(ctx);
     // stretch tables: per problem 3 axes, per panel one x3 table
     int64_t eo = 0;
     for (size_t k = 0; k < ctx->ph.size(); ++k) {
@@ -915,6 +953,17 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             HIPCHK(hipStreamSynchronize(ctx->st));
             ctx->inst_h = inst;
             ctx->inv_by_depth = by;
+            ctx->factored = false;
+        }
+    } else if (k == "full_inverse") {
+        const bool full = value != 0;
+        if (full != ctx->full_inverse) {
+            ctx->full_inverse = full;
+            set_inverse_columns(ctx);
+            inverse_accounting(ctx);
+            HIPCHK(hipMemcpyAsync(ctx->d_inst, ctx->inst_h.data(), sizeof(FrontInst) * ctx->inst_h.size(),
+                                  hipMemcpyHostToDevice, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
             ctx->factored = false;
         }
     } else if (k == "keep_factors") {
@@ -2109,7 +2158,10 @@ extern "C" hsw_status hsw_get_front_inverse(const hsw_ctx* cctx, int32_t prob, i
     int s = 0, u = 0;
     hsw_status st = front_block(ctx, prob, panel, front, ctx->d_G, blk, s, u);
     if (st != HSW_OK) return st;
-    for (size_t i = 0; i < blk.size(); ++i) G[i] = {blk[i].re, blk[i].im};
+    const int g0 = ctx->inst_h[get_panel(ctx, prob, panel)->inst_base + front].g0;
+    const int64_t n = (int64_t)s + u;
+    for (size_t i = 0; i < blk.size(); ++i)
+        G[i] = (int64_t)i < g0 * n ? hsw_c128{0, 0} : hsw_c128{blk[i].re, blk[i].im};
     return HSW_OK;
 }
 

@@ -262,8 +262,9 @@ class Solver:
         return D, L, F[:u]
 
     def set_option(self, key, value):
-        """Option of the context: "graph", "autotune", "update_order", "block_gmres" or
-        "keep_factors" (see hsw_set_option)."""
+        """Option of the context: "graph", "autotune", "update_order", "block_gmres",
+        "solve_lanes", "keep_factors", "inverse_by_depth" or "full_inverse" (see
+        hsw_set_option)."""
         self._check(self.lib.hsw_set_option(self.ctx, key.encode(), int(value)))
 
     def kernel_timing(self, kernel, enable):

@@ -126,6 +126,7 @@ def test_update_orders_match_dense_ldlt(wide, wide_oracle_factors, prec, order):
     S = Solver(wide, precision=prec)
     S.set_option("update_order", order)
     S.set_option("keep_factors", 1)
+    S.set_option("full_inverse", 1)  # whole inverses (the leaves here skip 64 columns otherwise)
     S.assemble(wide["c"])
     S.setup()
     multi = 0
@@ -189,6 +190,87 @@ def test_inverted_fronts_match_oracle(small, small_oracle_factors, prec):
             G = S.front_inverse(0, i, f)
             ref = np.vstack([GT, GB])
             assert rel(G, ref) <= TOL[prec], (i, f)
+
+
+@pytest.fixture(scope="module")
+def deep_pml():
+    # a 10 x 9 lateral grid: 4 x 4- and 4 x 2-cell leaves.  Under the 4
+    # auxiliary planes of panel 1 the 16-cell leaves form G from column 64
+    # on; the 8-cell leaves (32 auxiliary pivots) and panel 0 form all of it
+    return case(n=(2, 1, 4), gamma=4, d=2, leaf=4)
+
+
+@pytest.fixture(scope="module")
+def deep_pml_oracle_factors(deep_pml):
+    return _oracle_factors(deep_pml)
+
+
+def _first_formed_columns(P):
+    """Per panel and front, the documented first formed column of G: for a
+    leaf (no children) of a panel with ga auxiliary planes, 64 floor(min(ga
+    cells, s) / 64), cells being its lateral cells; 0 for every other front.
+    Computed from the oracle's nested dissection and panel layout."""
+    N = hz.padded_shape(P["n"], P["gamma"])
+    nodes = nd.nested_dissection(N[0], N[1], P["leaf"])
+    out = {}
+    for i in range(len(pn.panel_bounds(P["n"][2], P["gamma"], P["d"]))):
+        _, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
+                                        P["d"], i)
+        nz = ga + hi - lo
+        out[i] = [64 * (min(ga * len(x.cells), nz * len(x.cells)) // 64) if not x.children else 0
+                  for x in nodes]
+    return out
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("keep", [True, False])
+def test_leaf_inverse_skips_auxiliary_plane_columns(deep_pml, deep_pml_oracle_factors, prec, keep):
+    """Leaves of a panel with auxiliary planes form G from column g0 on (the
+    rest reads as zeros); the formed columns match the oracle's selective
+    inverse and equal, bit for bit, the same columns of the whole inverse
+    (option full_inverse), for G in a block of its own and in place."""
+    P = deep_pml
+    S = _solver(P, prec, keep=keep)
+    g0s = _first_formed_columns(P)
+    assert any(g > 0 for g0 in g0s.values() for g in g0)
+    part = {}
+    for i, (perm, U, blocks, starts) in deep_pml_oracle_factors.items():
+        for f, (dF, LF, FBL) in enumerate(blocks):
+            GT, GB = ld.selective_inverse(LF, FBL)
+            ref = np.vstack([GT, GB])
+            G = S.front_inverse(0, i, f)
+            g0 = g0s[i][f]
+            assert not G[:, :g0].any(), (i, f)
+            assert rel(G[:, g0:], ref[:, g0:]) <= TOL[prec], (i, f)
+            part[i, f] = (G, ref)
+    S.set_option("full_inverse", 1)
+    S.setup()
+    for (i, f), (Gp, ref) in part.items():
+        G = S.front_inverse(0, i, f)
+        assert rel(G, ref) <= TOL[prec], (i, f)
+        g0 = g0s[i][f]
+        assert np.array_equal(G[:, g0:], Gp[:, g0:]), (i, f)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 17])
+def test_sweep_with_skipped_leaf_columns_matches_oracle(deep_pml, prec, nrhs):
+    """The sweep reads no column the inversion skipped: it matches the oracle,
+    and with fixed block shapes it equals the sweep over whole inverses bit
+    for bit (17 right-hand sides: one matrix-core group of 16 plus one)."""
+    P = deep_pml
+    S = _solver(P, prec)
+    S.set_option("autotune", 0)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((nrhs, O.N_pad), 5)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    ref = O.apply(r.T).T
+    for k in range(nrhs):
+        assert rel(z[k], ref[k]) <= TOL[prec], k
+    S.set_option("full_inverse", 1)
+    S.setup()
+    z2 = S.apply(0, _cuda(r)).cpu().numpy()
+    assert np.array_equal(z, z2)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
