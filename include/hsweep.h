@@ -68,7 +68,8 @@ typedef struct {
     int32_t gamma;       /* PML nodes per face, physical and artificial (Sec. 1.1) */
     double pml_amp;      /* PML amplitude C in sigma(t) = (C/eta)(t/eta)^2, eta = (gamma+1) h */
     int32_t panel_depth; /* interior x3 planes per panel, d (Sec. 1.1, before Alg. 1.4) */
-    int32_t leaf;        /* nested-dissection leaf lateral extent (>= 2) (Sec. 2.1) */
+    int32_t leaf;        /* nested-dissection leaf lateral extent (>= 2), or 0 for the
+                            default 4, the fastest leaf measured (Sec. 2.1) */
 } hsw_problem;
 
 typedef struct {

@@ -757,7 +757,9 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ctx->prec = prec;
     ctx->esz = prec == HSW_C128 ? 16 : 8;
     ctx->probs.assign(p, p + nprob);
-    hsw_status s = plan_all(ctx, p, nprob);
+    for (hsw_problem& q : ctx->probs)
+        if (q.leaf == 0) q.leaf = DEFAULT_LEAF;
+    hsw_status s = plan_all(ctx, ctx->probs.data(), nprob);
     if (s != HSW_OK) {
         g_create_error = ctx->err;
         delete ctx;

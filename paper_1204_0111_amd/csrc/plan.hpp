@@ -20,6 +20,9 @@
 namespace hsw {
 
 constexpr int TILE = 64;        // square tile of the front kernels
+// Nested-dissection leaf extent given to a problem that asks for 0: the
+// fastest of the leaves 2..8 timed on the 50^3 and 100^3 workloads.
+constexpr int DEFAULT_LEAF = 4;
 constexpr int NB = 64;          // pivot block of the blocked partial LDL^T
 // Block shapes of the solve passes: rows (forward) or columns (backward) per
 // workgroup and threads per workgroup.  Each tree depth of each panel class

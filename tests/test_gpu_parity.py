@@ -105,6 +105,16 @@ def test_matvec_matches_oracle(medium):
         assert rel(y[r], A @ x[r]) <= 1e-13
 
 
+def test_leaf_zero_takes_the_default_leaf(medium):
+    """leaf = 0 asks for the default nested-dissection leaf, 4: the same plan."""
+    from paper_1204_0111_amd.hsweep import Solver
+    A = Solver(dict(medium, leaf=0), precision="c64")
+    B = Solver(dict(medium, leaf=4), precision="c64")
+    assert A.query(0, "fronts") == B.query(0, "fronts")
+    for i in range(A.query(0, "m")):
+        assert np.array_equal(A.perm(0, i), B.perm(0, i))
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_front_factors_match_dense_ldlt(small, small_oracle_factors, prec):
     S = _solver(small, prec, keep=True)
