@@ -275,10 +275,109 @@ __device__ inline Cx<float> pivot_recip(Cx<float> b) {
 }
 __device__ inline Cx<double> pivot_recip(Cx<double> b) { return crecip(b); }
 
-// Step m of the 16 x 16 sub-block factorisation (see diag16); m is a
-// template parameter so that every register index is static.
+// Lane m of each 16-lane row, in every lane of that row (DPP row broadcast:
+// a register move, no LDS round trip).
+template <int m>
+__device__ inline float row_bcast(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + m, 0xf, 0xf, false));
+}
 template <int m, typename T>
-__device__ inline void diag16_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, int l, int c0, int w,
+__device__ inline Cx<T> row_bcast_cx(Cx<T> v) {
+    return cx<T>(row_bcast<m>(v.re), row_bcast<m>(v.im));
+}
+
+// Step m of the complex64 16 x 16 sub-block factorisation (see diag16); m is
+// a template parameter so that every register index is static.  The whole
+// trailing square is updated, so it stays symmetric: the operands A(j, m)
+// and X(m, j) of lane (i, j) are then both held by lane (m, j) of its own row
+// of 16 lanes, and reach it by a row broadcast.
+template <int m, typename T>
+__device__ inline void diag16_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, int l, Cx<T>& dl,
+                                   Cx<T>& idl) {
+    constexpr int src = 16 * (m & 3);  // lanes holding column m: l / 16 == m % 4, register m / 4
+    const Cx<T> d = lane_bcast_cx(a[m >> 2], m + src);  // the pivot, from one fixed lane
+    const Cx<T> idm = pivot_recip(d);
+    const Cx<T> aim = shfl_cx(a[m >> 2], i + src);
+    const Cx<T> li = aim * idm;
+    const bool below = i > m;
+    // every operand is read before any register of this step changes: the
+    // lanes holding column m overwrite it with l_im below
+    Cx<T> amj[4], xm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        amj[q] = row_bcast_cx<m>(a[q]);  // A(m, j) = A(j, m)
+        xm[q] = row_bcast_cx<m>(x[q]);   // X(m, j), final at step m
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        Cx<T> na = a[q], nx = x[q];
+        cfms(na, li, amj[q]);
+        cfms(nx, li, xm[q]);
+        a[q] = (below && j > m) ? na : a[q];
+        x[q] = (below && j <= m) ? nx : x[q];
+        a[q] = (below && j == m) ? li : a[q];
+    }
+    // lane m keeps the pivot and its reciprocal
+    dl = l == m ? d : dl;
+    idl = l == m ? idm : idl;
+}
+
+template <typename T, int... M>
+__device__ inline void diag16_steps(std::integer_sequence<int, M...>, Cx<T> (&a)[4], Cx<T> (&x)[4], int i,
+                                    int jg, int l, Cx<T>& dl, Cx<T>& idl) {
+    (diag16_step<M, T>(a, x, i, jg, l, dl, idl), ...);
+}
+
+// One wave factors the 16 x 16 diagonal sub-block at c0 (w <= 16 valid
+// columns; the rest is padded with the identity) and inverts its unit lower
+// factor.  Lane l holds rows i = l % 16 at columns j = l / 16 + 4q of the
+// block and of X; the 16 steps are unrolled and free of branches.  The block
+// is read whole (the upper part from its symmetric lower entries).
+template <typename T>
+__device__ inline void diag16(T (*Mre)[LDP], T (*Mim)[LDP], Cx<T>* dv, Cx<T>* __restrict__ dinv,
+                              int c0, int w, int* bad) {
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, jg = l >> 4;
+    Cx<T> a[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        const T one = i == j ? (T)1 : (T)0;
+        const int r = i >= j ? i : j, c = i >= j ? j : i;
+        a[q] = (i < w && j < w) ? cx<T>(Mre[c0 + c][c0 + r], Mim[c0 + c][c0 + r]) : cx<T>(one, 0);
+        x[q] = cx<T>(one, 0);
+    }
+    Cx<T> dl = cx<T>(1, 0), idl = cx<T>(1, 0);
+    diag16_steps<T>(std::make_integer_sequence<int, 16>{}, a, x, i, jg, l, dl, idl);
+    // pivots and reciprocals of the block's columns; the first bad one is reported
+    const bool mine = l < w;
+    if (mine) {
+        dv[c0 + l] = dl;
+        dinv[c0 + l] = idl;
+    }
+    const bool finite = isfinite(dl.re) && isfinite(dl.im) && isfinite(idl.re) && isfinite(idl.im);
+    const unsigned long long bm = __ballot(mine && (!finite || (dl.re == 0 && dl.im == 0)));
+    if (l == 0 && bm != 0 && *bad < 0) *bad = c0 + __ffsll((long long)bm) - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = jg + 4 * q;
+        if (i < w && j < w && i >= j) {
+            Mre[c0 + j][c0 + i] = a[q].re;
+            Mim[c0 + j][c0 + i] = a[q].im;
+        }
+        if (i < w && j < w && i > j) {  // X(i, j) in the upper triangle: row j, column i
+            Mre[c0 + i][c0 + j] = x[q].re;
+            Mim[c0 + i][c0 + j] = x[q].im;
+        }
+    }
+}
+
+// The complex128 form of the sub-block factorisation: the operands of a step
+// arrive by cross-lane shuffles.  (With row broadcasts its register pressure
+// spills inside the pivot loop: 8.4 against 17.4 ms at 50^3.)  Step m:
+template <int m, typename T>
+__device__ inline void diag16s_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, int l, int c0, int w,
                                    Cx<T>* dv, Cx<T>* __restrict__ dinv, int& first_bad) {
     constexpr int src = 16 * (m & 3);  // lanes holding column m: l / 16 == m % 4, register m / 4
     const Cx<T> d = lane_bcast_cx(a[m >> 2], m + src);  // the pivot, from one fixed lane
@@ -314,10 +413,10 @@ __device__ inline void diag16_step(Cx<T> (&a)[4], Cx<T> (&x)[4], int i, int jg, 
 }
 
 template <typename T, int... M>
-__device__ inline void diag16_steps(std::integer_sequence<int, M...>, Cx<T> (&a)[4], Cx<T> (&x)[4], int i,
+__device__ inline void diag16s_steps(std::integer_sequence<int, M...>, Cx<T> (&a)[4], Cx<T> (&x)[4], int i,
                                     int jg, int l, int c0, int w, Cx<T>* dv, Cx<T>* __restrict__ dinv,
                                     int& first_bad) {
-    (diag16_step<M, T>(a, x, i, jg, l, c0, w, dv, dinv, first_bad), ...);
+    (diag16s_step<M, T>(a, x, i, jg, l, c0, w, dv, dinv, first_bad), ...);
 }
 
 // One wave factors the 16 x 16 diagonal sub-block at c0 (w <= 16 valid
@@ -325,7 +424,7 @@ __device__ inline void diag16_steps(std::integer_sequence<int, M...>, Cx<T> (&a)
 // factor.  Lane l holds rows i = l % 16 at columns j = l / 16 + 4q of the
 // block and of X; the 16 steps are unrolled and free of branches.
 template <typename T>
-__device__ inline void diag16(T (*Mre)[LDP], T (*Mim)[LDP], Cx<T>* dv, Cx<T>* __restrict__ dinv,
+__device__ inline void diag16s(T (*Mre)[LDP], T (*Mim)[LDP], Cx<T>* dv, Cx<T>* __restrict__ dinv,
                               int c0, int w, int* bad) {
     const int l = threadIdx.x & 63;
     const int i = l & 15, jg = l >> 4;
@@ -338,7 +437,7 @@ __device__ inline void diag16(T (*Mre)[LDP], T (*Mim)[LDP], Cx<T>* dv, Cx<T>* __
         x[q] = cx<T>(one, 0);
     }
     int first_bad = -1;
-    diag16_steps<T>(std::make_integer_sequence<int, 16>{}, a, x, i, jg, l, c0, w, dv, dinv, first_bad);
+    diag16s_steps<T>(std::make_integer_sequence<int, 16>{}, a, x, i, jg, l, c0, w, dv, dinv, first_bad);
     if (l == 0 && first_bad >= 0 && *bad < 0) *bad = first_bad;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -395,7 +494,10 @@ __global__ __launch_bounds__(256) void k_ldlt_diag(const int2* __restrict__ work
     const int nJ = (b + 15) / 16;
     for (int J = 0; J < nJ; ++J) {
         const int c0 = 16 * J, wj = min(16, b - c0);
-        if (wave == 0) diag16<T>(Mre, Mim, dv, dinv + f.doff + k, c0, wj, &bad);
+        if (wave == 0) {
+            if constexpr (sizeof(T) == 4) diag16<T>(Mre, Mim, dv, dinv + f.doff + k, c0, wj, &bad);
+            else diag16s<T>(Mre, Mim, dv, dinv + f.doff + k, c0, wj, &bad);
+        }
         __syncthreads();
         const int r0 = c0 + wj, nr = b - r0;
         if (nr <= 0) continue;
