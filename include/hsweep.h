@@ -158,9 +158,11 @@ hsw_status hsw_solve(hsw_ctx* ctx, const hsw_c128* const* b, hsw_c128* const* x,
 /*
  * Integer facts about problem `prob`.  Keys: "N_pad", "N_int", "m" (panels),
  * "N1", "N2", "N3", "fronts" (per panel), "levels", "factor_bytes",
- * "setup_flops", "apply_flops" (per right-hand side), "panel_lo",
- * "panel_hi", "panel_nz", "panel_artificial" (for these four *val holds the
- * panel index on entry).
+ * "setup_flops" (the partial factorisations and the formed columns of the
+ * inversion), "factor_flops", "apply_flops" (per right-hand side: one
+ * multiply-add per entry of G each pass reads, see "full_inverse"),
+ * "panel_lo", "panel_hi", "panel_nz", "panel_artificial" (for these four
+ * *val holds the panel index on entry).
  */
 hsw_status hsw_query(const hsw_ctx* ctx, int32_t prob, const char* key, int64_t* val);
 

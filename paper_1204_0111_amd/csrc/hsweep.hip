@@ -389,7 +389,6 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
         P.nfront = c.nfront;
         ProbHost& h = ctx->ph[P.prob];
         h.setup_cmac += c.factor_cmac;
-        h.apply_cmac += c.solve_cmac * (P.prob >= 0 ? 1 : 0);
         h.factor_entries += c.lsize;
         h.levels = std::max(h.levels, c.maxdepth + 1);
         for (int f = 0; f < c.nfront; ++f) {
@@ -416,20 +415,6 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
     set_inverse_columns(ctx);
     ctx->L_size = loff;
     ctx->D_size = doff;
-    for (auto& h : ctx->ph) {
-        // one sweep application: 2m - 1 panel solves; the first m are forward
-        (void)h;
-    }
-    for (size_t k = 0; k < ctx->ph.size(); ++k) {
-        ProbHost& h = ctx->ph[k];
-        double fwd = 0, last = 0;
-        for (int i = 0; i < h.m; ++i) {
-            const PanelClass& c = ctx->classes[ctx->pan_h[h.panel_base + i].cls];
-            fwd += c.solve_cmac;
-            if (i == h.m - 1) last = c.solve_cmac;
-        }
-        h.apply_cmac = 2 * fwd - last;
-    }
     return HSW_OK;
 }
 
@@ -473,6 +458,26 @@ static void xcd_group_by(std::vector<W>& w, size_t b, size_t e, K key) {
 
 static void xcd_group(std::vector<int2>& w, size_t b, size_t e) {
     xcd_group_by(w, b, e, [](const int2& v) { return (int64_t)v.x; });
+}
+
+static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<SolveItem>& sitems);
+
+// Complex multiply-adds of one sweep application per right-hand side (Alg.
+// 1.5: 2m - 1 panel solves), from the G entries the passes need: panel i's
+// solve of the forward sweep reads leaves from the panel's own planes in both
+// passes; its coupling solve of the backward sweep (i < m - 1) reads them from
+// the last plane in the forward pass.
+static void apply_accounting(hsw_ctx* ctx) {
+    for (ProbHost& h : ctx->ph) {
+        h.apply_cmac = 0;
+        for (int i = 0; i < h.m; ++i) {
+            const PanelDev& P = ctx->pan_h[h.panel_base + i];
+            for (const SolveLevel& l : ctx->slevels[P.cls]) {
+                h.apply_cmac += 2 * l.g_need(P.ga);
+                if (i < h.m - 1) h.apply_cmac += l.g_need(P.nz - 1) + l.g_need(P.ga);
+            }
+        }
+    }
 }
 
 static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<SolveItem>& sitems) {
@@ -769,6 +774,7 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     std::vector<SolveItem> sitems;
     schedule_all(ctx, fwork, sitems);
     inverse_accounting(ctx);
+    apply_accounting(ctx);
     // stretch tables: per problem 3 axes, per panel one x3 table
     int64_t eo = 0;
     for (size_t k = 0; k < ctx->ph.size(); ++k) {

@@ -209,8 +209,6 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
         pc.wsize += pc.u[k];
         pc.at_depth[pc.depth[k]].push_back(k);
         pc.factor_cmac += s * s * s / 6 + s * s * u / 2 + s * u * u / 2;
-        pc.inverse_cmac += s * s * s / 6 + u * s * s / 2;
-        pc.solve_cmac += s * s + 2 * s * u;
     }
     return "";
 }

@@ -93,7 +93,7 @@ struct PanelClass {
     int64_t lsize = 0;             // sum (s+u) s
     int64_t wsize = 0;             // sum u
     std::vector<std::vector<int>> at_depth;
-    double factor_cmac = 0, inverse_cmac = 0, solve_cmac = 0;  // per panel, per rhs for solves
+    double factor_cmac = 0;  // complex multiply-adds of the panel's partial factorisations
 };
 
 // Returns an empty string on success, else an error message.
