@@ -1,8 +1,11 @@
-"""Summarise rocprofv3 CSV output into the short text files kept in this folder.
+"""Summarise rocprofv3 CSV output into the short text files kept in profiles/.
 
-    python profiles/summarize.py stats <kernel_stats.csv> <out.txt> "<command>"
-    python profiles/summarize.py pmc <fetch_counter_collection.csv> <write_counter_collection.csv> \
-        <kernel symbol> <workload> <out.txt> "<fetch command>" "<write command>"
+    python -m paper_1204_0111_amd.profile_summary stats <kernel_stats.csv> <out.txt> "<command>"
+    python -m paper_1204_0111_amd.profile_summary pmc <fetch_counter_collection.csv> \
+        <write_counter_collection.csv> <kernel symbol> <workload> <out.txt> "<fetch command>" \
+        "<write command>"
+    python -m paper_1204_0111_amd.profile_summary sq <counter_collection.csv> <workload> <out.txt> \
+        "<command>"
 
 The PMC summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
 factor the same counter reads for the plain 512 MiB device copy the benchmark
@@ -95,8 +98,49 @@ def pmc(fetch_csv, write_csv, sym, workload, out, cmd_f, cmd_w):
         f.write("result:%s\n" % json.dumps(res))
 
 
+SQ_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS",
+               "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VMEM", "GRBM_GUI_ACTIVE")
+SIMDS = 1024  # 256 compute units x 4 SIMDs
+
+
+def sq(csv_path, workload, out, cmd):
+    """Matrix-core busy fraction and stall shares per kernel over the last step.
+
+    Each dispatch's value is summed over the counter's instances: the SQ
+    counters over all SIMDs, GRBM_GUI_ACTIVE over the eight XCDs (so one
+    XCD's active cycles are 1/8 of it).  MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES
+    / (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs); the waits and LDS activity are
+    fractions of the waves' resident cycles (SQ_WAVE_CYCLES)."""
+    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Dispatch_Id"]))
+    last = max(i for i, r in enumerate(rows) if "k_check_velocity" in r["Kernel_Name"])
+    agg, disp = {}, {}
+    for r in rows[last:]:
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").split("<")[0]
+        agg.setdefault(k, {c: 0.0 for c in SQ_COUNTERS})
+        if r["Counter_Name"] in SQ_COUNTERS:
+            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    with open(out, "w") as f:
+        f.write("# rocprofv3 --pmc %s, per kernel over the last step (%s)\n" % (" ".join(SQ_COUNTERS), workload))
+        f.write("# command: %s\n" % cmd)
+        f.write("# mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x %d SIMDs); "
+                "wait_any, wait_lds, lds_active = per SQ_WAVE_CYCLES\n" % SIMDS)
+        f.write("%-22s %6s %10s %9s %9s %11s %14s\n" % ("kernel", "calls", "mfma_busy", "wait_any", "wait_lds",
+                                                       "lds_active", "lds_bank_confl"))
+        for k, c in sorted(agg.items(), key=lambda kv: -kv[1]["GRBM_GUI_ACTIVE"]):
+            if not k.startswith("hsw::") or c["GRBM_GUI_ACTIVE"] == 0:
+                continue
+            wc = max(c["SQ_WAVE_CYCLES"], 1.0)
+            mf = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] / 8.0 * SIMDS)
+            f.write("%-22s %6d %9.1f%% %9.3f %9.3f %11.3f %14.3f\n" % (
+                k.replace("hsw::", ""), len(disp[k]), 100 * mf, c["SQ_WAIT_INST_ANY"] / wc,
+                c["SQ_WAIT_INST_LDS"] / wc, c["SQ_ACTIVE_INST_LDS"] / wc,
+                c["SQ_LDS_BANK_CONFLICT"] / max(c["SQ_ACTIVE_INST_LDS"], 1.0)))
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if sys.argv[1] == "sq":
+        sq(*sys.argv[2:6])
+    elif sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     else:
         pmc(*sys.argv[2:9])
