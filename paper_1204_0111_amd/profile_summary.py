@@ -43,6 +43,19 @@ def stats(csv_path, out, cmd):
             f.write("%-34s %7s %11.3f %10.3f %6.2f\n" % (name, r["Calls"],
                     float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
                     float(r["Percentage"])))
+        # one line per kernel over all its template instances (block shapes);
+        # these include the autotuner's trial launches of the warm-up step
+        f.write("# per kernel, all block shapes together\n")
+        fam = {}
+        for r in rows:
+            k = r["Name"].split("(")[0].replace("void ", "").split("<")[0]
+            c, t = fam.get(k, (0, 0.0))
+            fam[k] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
+        for k in ("hsw::k_fwd", "hsw::k_bwd", "hsw::k_update", "hsw::k_inverse", "hsw::k_ldlt_diag",
+                  "hsw::k_panel_trsm", "hsw::k_assemble"):
+            if k in fam:
+                c, t = fam[k]
+                f.write("%-34s %7d %11.3f %10.3f\n" % (k, c, t / 1e6, t / c / 1e3))
 
 
 def per_kernel(path):
