@@ -279,6 +279,14 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              g0 = 64 floor(min(ga cells, s) / 64), cells being the front's
  *              pivots per plane (s / panel_nz); the formed columns hold the
  *              same values either way.
+ *   "triangular_solves" the solve passes of a tree depth may instead run
+ *              as triangular solves with the kept factors, the path selective
+ *              inversion replaces (Sec. 2.2): by 64-pivot blocks, one
+ *              workgroup per front, with the stored inverses of the diagonal
+ *              blocks.  2 (default): the autotuner times them against the
+ *              inverse passes at every depth and keeps the faster; 1: at
+ *              every depth; 0: never.  They need the factors (keep_factors
+ *              1); without them every depth runs the inverse passes.
  * Changing "keep_factors", "inverse_by_depth" or "full_inverse" requires a
  * new hsw_setup.
  * Returns HSW_E_INVAL for an unknown key or value.

@@ -58,11 +58,19 @@ struct DepthSchedule {
 constexpr int N_RHS_KEYS = 4;
 inline int rhs_key(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
 
+// Selection of the triangular passes with the kept factors in a level's
+// fsel / bsel, past the block shapes of the inverse passes.
+constexpr int TRI_F = N_FWD_SHAPES, TRI_B = N_BWD_SHAPES;
+
 struct SolveLevel {
     // work items of every block shape (plan.hpp) of the two passes
     int64_t foff[N_FWD_SHAPES] = {}, boff[N_BWD_SHAPES] = {};
     int fcount[N_FWD_SHAPES] = {}, bcount[N_BWD_SHAPES] = {};
     int fsel[N_RHS_KEYS] = {}, bsel[N_RHS_KEYS] = {};  // shape in use, per right-hand-side group
+    // one work item per front for the triangular passes (selected as shape
+    // TRI_F / TRI_B)
+    int64_t toff = 0;
+    int tcount = 0;
     int smax = 0, nmax = 0;
     // algorithmic traffic: bytes per right-hand side of the vectors each pass
     // reads and writes, and the G entries a pass needs (also its complex
@@ -168,6 +176,9 @@ struct hsw_ctx {
     std::mutex err_mu;
     bool autotune = true;
     bool tuned[N_RHS_KEYS] = {};
+    // triangular passes with the kept factors: 0 never, 1 at every depth,
+    // 2 where the autotuner finds them faster than the inverse passes
+    int tri_mode = 2;
     // captured sweeps, their stream and the events joining it to st
     bool use_graph = false;  // measured slower than stream launches for the sweep
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
@@ -701,6 +712,10 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 // lines and the staged front vector hit that XCD's L2
                 xcd_group_by(sitems, sl.foff[k], sitems.size(), [](const SolveItem& q) { return q.loff; });
             }
+            sl.toff = (int64_t)sitems.size();
+            for (int f : c.at_depth[d]) sitems.push_back(item(f, 0));
+            sl.tcount = (int)(sitems.size() - sl.toff);
+            xcd_group_by(sitems, sl.toff, sitems.size(), [](const SolveItem& q) { return q.loff; });
             for (int k = 0; k < N_BWD_SHAPES; ++k) {
                 const int cb = BWD_SHAPES[k].block;
                 sl.boff[k] = (int64_t)sitems.size();
@@ -963,6 +978,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             ctx->inv_by_depth = by;
             ctx->factored = false;
         }
+    } else if (k == "triangular_solves") {
+        if (value < 0 || value > 2) return fail(ctx, HSW_E_INVAL, "triangular_solves is 0, 1 or 2");
+        ctx->tri_mode = (int)value;
+        for (bool& t : ctx->tuned) t = false;
     } else if (k == "full_inverse") {
         const bool full = value != 0;
         if (full != ctx->full_inverse) {
@@ -999,6 +1018,7 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             }
             ctx->keep_factors = keep;
             ctx->factored = false;  // G is rebuilt by the next setup
+            for (bool& t : ctx->tuned) t = false;  // the triangular passes come and go with the factors
             drop_graphs(ctx);
         }
     } else if (k == "update_order") {
@@ -1173,6 +1193,12 @@ static hsw_status ensure_solve_ws(hsw_ctx* ctx, Lane& L, int nrhs) {
 // force_f / force_b >= 0 run every depth with that block shape, and `ev`
 // (two events per launch, forward launches first) times each launch: both
 // serve the autotuner.
+// The triangular passes read the factors, which exist next to G only when
+// they are kept (a separate G block).
+static bool tri_available(const hsw_ctx* ctx) {
+    return ctx->tri_mode != 0 && ctx->keep_factors && ctx->d_G != ctx->d_L;
+}
+
 template <typename T>
 static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx<double>* src,
                          int64_t ld, int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
@@ -1229,7 +1255,12 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         }
         ++li;
     };
-    if (nrhs >= MM_MIN_RHS && force_f < 0) {  // matrix-core passes, 16 right-hand sides per group
+    const bool tri_ok = tri_available(ctx);
+    const bool tri_all = tri_ok && ctx->tri_mode == 1;
+    // the same arguments with the kept factor block in place of G
+    PassArgs<T> AT = A;
+    AT.G = (const Cx<T>*)ctx->d_L + f0.loff;
+    if (nrhs >= MM_MIN_RHS && force_f < 0 && !tri_all) {  // matrix-core passes, 16 right-hand sides per group
         A.mode = gmode;
         for (int d = c.maxdepth; d >= 0; --d) {
             const int fs = mm_fwd_shape<T>();
@@ -1245,17 +1276,31 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         }
         return;
     }
-    A.mode = gmode;
+    A.mode = AT.mode = gmode;
     for (int d = c.maxdepth; d >= 0; --d) {
-        const int k = force_f >= 0 ? force_f : lv[d].fsel[key];
+        int k = force_f >= 0 ? force_f : (tri_all ? TRI_F : lv[d].fsel[key]);
+        if (k == TRI_F && !tri_ok) k = lv[d].nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
+        if (k == TRI_F) {
+            AT.items = ctx->d_sitems + lv[d].toff;
+            run("fwd", lv[d].tcount, es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pf), [&] { launch_tri<T>(AT, lv[d].tcount, lv[d].nmax, true, st); });
+            continue;
+        }
         A.items = ctx->d_sitems + lv[d].foff[k];
         run("fwd", lv[d].fcount[k], es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec_bytes,
             8.0 * nrhs * lv[d].g_need(pf),
             [&] { launch_fwd<T>(A, lv[d].fcount[k], k, lv[d].smax, lv[d].nmax, st); });
     }
-    A.mode = emode;
+    A.mode = AT.mode = emode;
     for (int d = 0; d <= c.maxdepth; ++d) {
-        const int k = force_b >= 0 ? force_b : lv[d].bsel[key];
+        int k = force_b >= 0 ? force_b : (tri_all ? TRI_B : lv[d].bsel[key]);
+        if (k == TRI_B && !tri_ok) k = lv[d].nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
+        if (k == TRI_B) {
+            AT.items = ctx->d_sitems + lv[d].toff;
+            run("bwd", lv[d].tcount, es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_tri<T>(AT, lv[d].tcount, lv[d].nmax, false, st); });
+            continue;
+        }
         A.items = ctx->d_sitems + lv[d].boff[k];
         run("bwd", lv[d].bcount[k], es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec_bytes,
             8.0 * nrhs * lv[d].g_need(pb),
@@ -1275,7 +1320,9 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     // inside a multi-lane solve the shapes are fixed (tuning runs on lane 0 before it)
     if (!ctx->autotune || ctx->tuned[key] || nrhs >= MM_MIN_RHS || ctx->in_lanes) return HSW_OK;
     constexpr int REPS = 3;
-    const int NS = std::max(N_FWD_SHAPES, N_BWD_SHAPES);
+    // candidates: every block shape, plus the triangular passes when the factors are kept
+    const bool tri = tri_available(ctx);
+    const int NS = std::max(N_FWD_SHAPES, N_BWD_SHAPES) + (tri ? 1 : 0);
     int64_t plen = 1;
     for (const PanelDev& P : ctx->pan_h) plen = std::max<int64_t>(plen, (int64_t)(P.hi - P.lo) * P.Nx * P.Ny);
     Cx<double>* v = nullptr;
@@ -1305,13 +1352,14 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        std::vector<std::vector<float>> tf(D + 1, std::vector<float>(N_FWD_SHAPES, 1e30f));
-        std::vector<std::vector<float>> tb(D + 1, std::vector<float>(N_BWD_SHAPES, 1e30f));
+        std::vector<std::vector<float>> tf(D + 1, std::vector<float>(N_FWD_SHAPES + 1, 1e30f));
+        std::vector<std::vector<float>> tb(D + 1, std::vector<float>(N_BWD_SHAPES + 1, 1e30f));
         int run = 0;
         for (int rep = 0; rep < REPS; ++rep)
             for (int k = 0; k < NS; ++k, ++run) {
                 const int gp = panels[run % panels.size()];
-                const int kf = k % N_FWD_SHAPES, kb = k % N_BWD_SHAPES;
+                const bool kt = tri && k == NS - 1;
+                const int kf = kt ? TRI_F : k % N_FWD_SHAPES, kb = kt ? TRI_B : k % N_BWD_SHAPES;
                 const PanelDev& P = ctx->pan_h[gp];
                 panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, nrhs, kf, kb, ev.data());
                 TCHK(hipGetLastError());

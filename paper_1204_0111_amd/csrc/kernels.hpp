@@ -64,6 +64,10 @@ template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
 template <typename T>
 int solve_rhs_chunk(int nrhs, int nmax);
+// triangular passes with the kept factors (fwd: forward pass, else backward),
+// one work item per front
+template <typename T>
+void launch_tri(const PassArgs<T>& A, int nwork, int nmax, bool fwd, hipStream_t st);
 
 // assemble.hip
 void launch_axis_table(Cx<double>* out, int nj, int gj, double h, double C, double omega,

@@ -646,6 +646,265 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Triangular passes with the factors themselves, the path selective
+// inversion replaces (Sec. 2.2): the forward step x_S := L_F^{-1} x_S,
+// x_U := x_U - F_BL x_S and the backward step x_S := L_F^{-T}(x_S - F_BL^T
+// x_U), by 64-pivot blocks in order.  L = [L_F; F_BL] is the kept factor
+// block (n x s, column-major, the layout of G); each 64 x 64 diagonal block of
+// L_F holds above its diagonal the inverse X of its unit lower part, X(r, c)
+// (r > c) at row c, column r of the block, as the factorisation left it.
+// One workgroup of TRI_NT threads per (front, right-hand-side chunk); inputs,
+// outputs and the exchanges between fronts are those of k_fwd / k_bwd.
+constexpr int TRI_NT = 256;
+
+template <typename T, int RC>
+__global__ __launch_bounds__(TRI_NT) void k_fwd_tri(PassArgs<T> A) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* v = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]: the front vector, then x
+    __shared__ Cx<T> xb[RC][64];
+    const SolveItem it = A.items[blockIdx.x];
+    const int n = it.n, s = it.s;
+    const int rhs0 = blockIdx.y * RC;
+    const int nr = min(RC, A.nrhs - rhs0);
+    const int tid = threadIdx.x;
+    const Cx<T>* L = A.G + it.loff;
+    const int* map0 = A.cmap + it.moff;
+    const int* map1 = map0 + n;
+    // children's contributions on every row of the front, plus the
+    // right-hand side on its pivots (slots a child does not cover are masked)
+    for (int k = tid; k < n; k += TRI_NT) {
+        const bool h0 = map0[k] >= 0, h1 = map1[k] >= 0;
+        bool live = false;
+        int64_t gi = 0;
+        Cx<double> cf = cx<double>(1, 0);
+        if (k < s) {
+            const int b = pivot_box(it, A.Nx, A.NxNy, k);
+            const int q = b / A.NxNy, lat = b - q * A.NxNy;
+            if (A.mode == 0) {
+                live = q >= A.ga;
+                gi = (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
+            } else {
+                live = q == A.nz - 1;
+                gi = (int64_t)(A.hi - A.plane0) * A.NxNy + lat;
+                if (live) cf = plane_coupling(A, lat);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            Cx<T> val = cx<T>(0, 0);
+            if (r < nr) {
+                const int64_t rr = rhs0 + r;
+                const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
+                val = keep(h0, cc[k]) + keep(h1, cc[n + k]);
+                if (live) {
+                    const Cx<double> x = A.src[rr * A.ld + gi];
+                    val = val + ccast<T>(A.mode == 0 ? x : cf * x);
+                }
+            }
+            v[r * n + k] = val;
+        }
+    }
+    __syncthreads();
+    // a leaf's vector is zero before its first live pivot: those blocks stay zero
+    for (int b0 = leaf_first_live(A, it) / 64 * 64; b0 < s; b0 += 64) {
+        const int bw = min(64, s - b0);
+        {   // x_b = X v_b: row r of X is column b0 + r of the block, above the diagonal;
+            // four lanes per row, each over every fourth column
+            const int r = tid >> 2, ph = tid & 3;
+            const Cx<T>* xr = L + (int64_t)(b0 + r) * n + b0;
+            Cx<T> acc[RC];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) acc[q] = cx<T>(0, 0);
+            if (r < bw)
+                for (int c = ph; c < r; c += 4) {
+                    const Cx<T> xv = xr[c];
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) cfma(acc[q], xv, v[q * n + b0 + c]);
+                }
+#pragma unroll
+            for (int q = 0; q < RC; ++q)
+#pragma unroll
+                for (int off = 1; off < 4; off <<= 1) {
+                    acc[q].re += __shfl_xor(acc[q].re, off, 64);
+                    acc[q].im += __shfl_xor(acc[q].im, off, 64);
+                }
+            if (ph == 0 && r < bw) {
+#pragma unroll
+                for (int q = 0; q < RC; ++q) xb[q][r] = v[q * n + b0 + r] + acc[q];
+            }
+        }
+        __syncthreads();
+        if (tid < bw) {
+#pragma unroll
+            for (int q = 0; q < RC; ++q) v[q * n + b0 + tid] = xb[q][tid];
+        }
+        // later rows (pivots and update rows): v_i -= L(i, block) x_b
+        for (int i = b0 + bw + tid; i < n; i += TRI_NT) {
+            Cx<T> acc[RC];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) acc[q] = v[q * n + i];
+            for (int c = 0; c < bw; ++c) {
+                const Cx<T> lv = L[(int64_t)(b0 + c) * n + i];
+#pragma unroll
+                for (int q = 0; q < RC; ++q) cfms(acc[q], lv, xb[q][c]);
+            }
+#pragma unroll
+            for (int q = 0; q < RC; ++q) v[q * n + i] = acc[q];
+        }
+        __syncthreads();
+    }
+    // x_mid = D^{-1} x_S; the update rows go to the parent's slots
+    for (int i = tid; i < n; i += TRI_NT) {
+        const Cx<T> dv = i < s ? A.dinv[it.start + i] : cx<T>(0, 0);
+        const int pm = i < s ? 0 : A.pmap[it.pmap + i - s];
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            if (q >= nr) break;
+            const int64_t rr = rhs0 + q;
+            const Cx<T> y = v[q * n + i];
+            if (i < s) A.xmid[rr * A.naux + it.start + i] = y * dv;
+            else A.c2[rr * A.c2ld + it.push + pm] = y;
+        }
+    }
+}
+
+template <typename T, int RC>
+__global__ __launch_bounds__(TRI_NT) void k_bwd_tri(PassArgs<T> A) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* w = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]: x_mid and x_U, then x
+    __shared__ Cx<T> tb[RC][64];
+    const SolveItem it = A.items[blockIdx.x];
+    const int n = it.n, s = it.s;
+    const int rhs0 = blockIdx.y * RC;
+    const int nr = min(RC, A.nrhs - rhs0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const Cx<T>* L = A.G + it.loff;
+    // [x_mid; x_U] of this front; the update-set values go on to the children
+    for (int i = tid; i < n; i += TRI_NT) {
+        int p0 = -1, p1 = -1;
+        if (i >= s) {
+            if (it.cxu0 >= 0) p0 = A.cmap[it.moff + i];
+            if (it.cxu1 >= 0) p1 = A.cmap[it.moff + n + i];
+        }
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            Cx<T> val = cx<T>(0, 0);
+            if (q < nr) {
+                const int64_t rr = rhs0 + q;
+                if (i < s) {
+                    val = A.xmid[rr * A.naux + it.start + i];
+                } else {
+                    val = A.xu[rr * A.xuld + it.xu + i - s];
+                    if (p0 >= 0) A.xu[rr * A.xuld + it.cxu0 + p0] = val;
+                    if (p1 >= 0) A.xu[rr * A.xuld + it.cxu1 + p1] = val;
+                }
+            }
+            w[q * n + i] = val;
+        }
+    }
+    __syncthreads();
+    // a leaf writes only its pivots on the panel's own planes: the blocks of
+    // auxiliary-plane pivots before them are not needed
+    const int bstop = it.leaf ? min(A.ga * (it.cellw >> 16), s) / 64 * 64 : 0;
+    for (int b0 = (s - 1) / 64 * 64; b0 >= bstop; b0 -= 64) {
+        const int bw = min(64, s - b0);
+        // t_c = w_c - sum over the later rows i of L(i, b0 + c) x_i: one wave per
+        // column, its lanes down the rows
+        for (int c = wave; c < bw; c += TRI_NT / 64) {
+            const Cx<T>* lc = L + (int64_t)(b0 + c) * n;
+            Cx<T> acc[RC];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) acc[q] = cx<T>(0, 0);
+            for (int i = b0 + bw + lane; i < n; i += 64) {
+                const Cx<T> lv = lc[i];
+#pragma unroll
+                for (int q = 0; q < RC; ++q) cfma(acc[q], lv, w[q * n + i]);
+            }
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                acc[q].re = wave_sum(acc[q].re);
+                acc[q].im = wave_sum(acc[q].im);
+                if (lane == 0) tb[q][c] = w[q * n + b0 + c] - acc[q];
+            }
+        }
+        __syncthreads();
+        {   // x_b = X^T t: x_c = t_c + sum over r > c of X(r, c) t_r; four lanes per column
+            const int c = tid >> 2, ph = tid & 3;
+            Cx<T> acc[RC];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) acc[q] = cx<T>(0, 0);
+            if (c < bw)
+                for (int r = c + 1 + ph; r < bw; r += 4) {
+                    const Cx<T> xv = L[(int64_t)(b0 + r) * n + b0 + c];
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) cfma(acc[q], xv, tb[q][r]);
+                }
+#pragma unroll
+            for (int q = 0; q < RC; ++q)
+#pragma unroll
+                for (int off = 1; off < 4; off <<= 1) {
+                    acc[q].re += __shfl_xor(acc[q].re, off, 64);
+                    acc[q].im += __shfl_xor(acc[q].im, off, 64);
+                }
+            if (ph == 0 && c < bw) {
+#pragma unroll
+                for (int q = 0; q < RC; ++q) w[q * n + b0 + c] = tb[q][c] + acc[q];
+            }
+        }
+        __syncthreads();
+    }
+    // the front's pivots: to the children's update-set values and the grid
+    for (int j = bstop + tid; j < s; j += TRI_NT) {
+        int o0 = -1, o1 = -1;
+        if (it.cxu0 >= 0) o0 = A.cmap[it.moff + j];
+        if (it.cxu1 >= 0) o1 = A.cmap[it.moff + n + j];
+        const int b = pivot_box(it, A.Nx, A.NxNy, j);
+        const int q3 = b / A.NxNy, lat = b - q3 * A.NxNy;
+        const bool oplane = q3 >= A.ga;
+        const int64_t ogi = (int64_t)(A.lo + q3 - A.ga - A.plane0) * A.NxNy + lat;
+        const bool onext = A.couple && A.mode == 0 && q3 == A.nz - 1;
+        const Cx<double> ocf = onext ? plane_coupling(A, lat) : cx<double>(0, 0);
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            if (q >= nr) break;
+            const int64_t rr = rhs0 + q;
+            const Cx<T> x = w[q * n + j];
+            if (o0 >= 0) A.xu[rr * A.xuld + it.cxu0 + o0] = x;
+            if (o1 >= 0) A.xu[rr * A.xuld + it.cxu1 + o1] = x;
+            if (oplane) {
+                Cx<double>* up = A.dst + rr * A.ld + ogi;
+                const Cx<double> xd = ccast<double>(x);
+                if (A.mode == 0) {
+                    *up = xd;
+                    if (onext) up[A.NxNy] = up[A.NxNy] - ocf * xd;
+                } else {
+                    *up = *up - xd;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int RC>
+static void tri_rc(const PassArgs<T>& A, int nwork, int nmax, bool fwd, hipStream_t st) {
+    const size_t shm = sizeof(Cx<T>) * (size_t)RC * nmax;
+    const dim3 grid(nwork, (A.nrhs + RC - 1) / RC);
+    if (fwd) HSW_LAUNCH((k_fwd_tri<T, RC>), grid, dim3(TRI_NT), shm, st, A);
+    else HSW_LAUNCH((k_bwd_tri<T, RC>), grid, dim3(TRI_NT), shm, st, A);
+}
+
+template <typename T>
+void launch_tri(const PassArgs<T>& A, int nwork, int nmax, bool fwd, hipStream_t st) {
+    if (nwork <= 0) return;
+    switch (solve_rhs_chunk<T>(A.nrhs, nmax)) {
+        case 8: tri_rc<T, 8>(A, nwork, nmax, fwd, st); break;
+        case 4: tri_rc<T, 4>(A, nwork, nmax, fwd, st); break;
+        case 2: tri_rc<T, 2>(A, nwork, nmax, fwd, st); break;
+        default: tri_rc<T, 1>(A, nwork, nmax, fwd, st); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T, int RC, int RB, int NT>
 static void fwd_rc(const PassArgs<T>& A, int nwork, int smax, hipStream_t st) {
     size_t shm = sizeof(Cx<T>) * ((size_t)RC * smax + (size_t)(NT / 64) * RB * RC);
@@ -733,6 +992,7 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
 }
 
 #define HSW_INST(T)                                                                          \
+    template void launch_tri<T>(const PassArgs<T>&, int, int, bool, hipStream_t);           \
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
     template void launch_fwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \

@@ -284,6 +284,41 @@ def test_sweep_with_skipped_leaf_columns_matches_oracle(deep_pml, prec, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("which", ["medium", "deep_pml"])
+def test_triangular_passes_match_oracle(request, which, prec):
+    """The triangular passes with the kept factors (option triangular_solves 1,
+    every depth) reproduce the oracle's T_i and sweep, like the inverse passes;
+    17 right-hand sides run in chunks (no matrix-core group on this path)."""
+    P = request.getfixturevalue(which)
+    S = _solver(P, prec, keep=True)
+    S.set_option("triangular_solves", 1)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    for i in range(O.m):
+        lo, hi = O.bounds[i]
+        v = wl.random_complex((2, (hi - lo) * O.plane), 20 + i)
+        y = S.panel_solve(0, i, _cuda(v)).cpu().numpy()
+        assert rel(y, O.T(i, v.T).T) <= TOL[prec], i
+    for nrhs in (1, 5, 17):
+        r = wl.random_complex((nrhs, O.N_pad), 7)
+        z = S.apply(0, _cuda(r)).cpu().numpy()
+        ref = O.apply(r.T).T
+        for k in range(nrhs):
+            assert rel(z[k], ref[k]) <= TOL[prec], (nrhs, k)
+
+
+def test_triangular_passes_need_the_kept_factors(medium):
+    """Without the factors (G formed in place) the triangular passes are not
+    available: every depth keeps the inverse passes, bit for bit."""
+    S = _solver(medium, "c64", keep=False)
+    S.set_option("autotune", 0)
+    r = _cuda(wl.random_complex((2, S.N_pad()), 8))
+    z0 = S.apply(0, r).cpu().numpy()
+    S.set_option("triangular_solves", 1)
+    z1 = S.apply(0, r).cpu().numpy()
+    assert np.array_equal(z0, z1)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_panel_solve_matches_oracle(medium, prec):
     P = medium
     S = _solver(P, prec)
