@@ -398,10 +398,13 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// RT row tiles of 16 per workgroup: each wave updates all of them over its
-// quarter of the contraction (the front vector is staged once per RT tiles).
-template <typename T, int RT>
-__global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
+// RT row tiles of 16 per workgroup: each of the NW waves updates all of them
+// over every NW-th chunk of the contraction (the front vector is staged once
+// per RT tiles).  Launches with few workgroups (the upper depths, with long
+// contractions) take the wide form, NW = 8, to shorten each wave's chain of
+// chunks.
+template <typename T, int RT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
     const SolveItem it = A.items[blockIdx.x];  // items of 16 RT rows
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int kend = (it.blk + 16 * RT <= s) ? it.blk + 16 * RT : s;
-    __shared__ T Vre[4][KC][17], Vim[4][KC][17];  // per wave: front-vector chunk [entry][rhs]
+    __shared__ T Vre[NW][KC][17], Vim[NW][KC][17];  // per wave: front-vector chunk [entry][rhs]
     __shared__ T Yre[16 * RT][17], Yim[16 * RT][17];  // the block's sum [row][rhs]
     const int* map0 = A.cmap + it.moff;
     const int* map1 = map0 + n;
@@ -458,8 +461,8 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
     const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
     int ch = wave;
     if (ch < nch) load(kb + ch * KC, ga, vv);
-    for (; ch < nch; ch += 4) {
-        const bool more = ch + 4 < nch;
+    for (; ch < nch; ch += NW) {
+        const bool more = ch + NW < nch;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int e = lane + 64 * j;
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
             Vim[wave][e >> 4][e & 15] = vv[j].im;
         }
         wave_lds_sync();
-        if (more) load(kb + (ch + 4) * KC, gn, vn);
+        if (more) load(kb + (ch + NW) * KC, gn, vn);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T br = Vre[wave][4 * q + lk][li], bi = Vim[wave][4 * q + lk][li];
@@ -492,8 +495,8 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
             for (int j = 0; j < 4; ++j) vv[j] = vn[j];
         }
     }
-    // sum the four waves' partial blocks in LDS, one wave at a time
-    for (int w = 0; w < 4; ++w) {
+    // sum the waves' partial blocks in LDS, one wave at a time
+    for (int w = 0; w < NW; ++w) {
         if (wave == w) {
 #pragma unroll
             for (int t = 0; t < RT; ++t)
@@ -511,9 +514,9 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
         }
         __syncthreads();
     }
-    // thread tid: rows blk + tid / 16 + 16 t, right-hand side rhs0 + tid % 16
+    // thread tid < 256: rows blk + tid / 16 + 16 t, right-hand side rhs0 + tid % 16
     const int64_t orr = rhs0 + (tid & 15);
-    if (orr >= A.nrhs) return;
+    if (tid >= 256 || orr >= A.nrhs) return;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int lrow = (tid >> 4) + 16 * t, row = it.blk + lrow;
@@ -529,8 +532,10 @@ __global__ __launch_bounds__(256) void k_fwd_mm(PassArgs<T> A) {
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
+// NW waves split the rows of the contraction by chunks; the wide form serves
+// launches with few workgroups, as for k_fwd_mm.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
     const SolveItem it = A.items[blockIdx.x];  // items of 16 columns
@@ -540,12 +545,12 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int c0 = it.blk;
-    __shared__ T Gre[4][KC][17], Gim[4][KC][17];  // per wave: G chunk [row][column]
-    __shared__ T Rre[4][KC][17], Rim[4][KC][17];  // per wave: [x_S; -x_U] chunk [row][rhs]
-    __shared__ T Yre[4][16][17], Yim[4][16][17];  // per wave: partial block [column][rhs]
+    __shared__ T Gre[NW][KC][17], Gim[NW][KC][17];  // per wave: G chunk [row][column]
+    __shared__ T Rre[NW][KC][17], Rim[NW][KC][17];  // per wave: [x_S; -x_U] chunk [row][rhs]
+    __shared__ T Yre[16][17], Yim[16][17];          // the waves' partial blocks, summed [column][rhs]
     // the first column block hands the update-set values on to the children
     if (c0 == 0 && (it.cxu0 >= 0 || it.cxu1 >= 0)) {
-        for (int idx = tid; idx < (n - s) * 16; idx += 256) {
+        for (int idx = tid; idx < (n - s) * 16; idx += 64 * NW) {
             const int i = s + (idx >> 4);
             const int64_t rr = rhs0 + (idx & 15);
             if (rr >= A.nrhs) continue;
@@ -580,8 +585,8 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
     const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
     int ch = wave;
     if (ch < nch) load(c0 + ch * KC, gv, rv);
-    for (; ch < nch; ch += 4) {
-        const bool more = ch + 4 < nch;
+    for (; ch < nch; ch += NW) {
+        const bool more = ch + NW < nch;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int e = lane + 64 * j;
@@ -591,7 +596,7 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
             Rim[wave][e >> 4][e & 15] = rv[j].im;
         }
         wave_lds_sync();
-        if (more) load(c0 + (ch + 4) * KC, gn, rn);
+        if (more) load(c0 + (ch + NW) * KC, gn, rn);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int kk = 4 * q + lk;
@@ -611,19 +616,28 @@ __global__ __launch_bounds__(256) void k_bwd_mm(PassArgs<T> A) {
             }
         }
     }
+    // sum the waves' partial blocks in LDS, one wave at a time
+    for (int w = 0; w < NW; ++w) {
+        if (wave == w) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        Yre[wave][mfma_out_row<T>(lk, r)][li] = are[r];
-        Yim[wave][mfma_out_row<T>(lk, r)][li] = aim[r];
+            for (int r = 0; r < 4; ++r) {
+                const int col = mfma_out_row<T>(lk, r);
+                if (w == 0) {
+                    Yre[col][li] = are[r];
+                    Yim[col][li] = aim[r];
+                } else {
+                    Yre[col][li] += are[r];
+                    Yim[col][li] += aim[r];
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // thread tid: column c0 + tid / 16, right-hand side rhs0 + tid % 16
+    // thread tid < 256: column c0 + tid / 16, right-hand side rhs0 + tid % 16
     const int j = c0 + (tid >> 4);
     const int64_t orr = rhs0 + (tid & 15);
-    if (j >= s || orr >= A.nrhs) return;
-    Cx<T> x = cx<T>(0, 0);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) x = x + cx<T>(Yre[w][tid >> 4][tid & 15], Yim[w][tid >> 4][tid & 15]);
+    if (tid >= 256 || j >= s || orr >= A.nrhs) return;
+    const Cx<T> x = cx<T>(Yre[tid >> 4][tid & 15], Yim[tid >> 4][tid & 15]);
     if (it.cxu0 >= 0) {
         const int o0 = A.cmap[it.moff + j];
         if (o0 >= 0) A.xu[orr * A.xuld + it.cxu0 + o0] = x;
@@ -980,15 +994,33 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t 
     bwd_pick<T, 0>(A, nwork, cfg, nmax, st);
 }
 
+// Waves per workgroup of the matrix-core passes: 4, or the wide form when a
+// launch has fewer than MM_WIDE_BELOW workgroups (LDS per wave and registers
+// bound it: 8 forward, 16 / 4 backward in complex64 / complex128).
+constexpr int MM_WIDE_BELOW = 512;
+template <typename T> struct MmWide {
+    static constexpr int fwd = 8, bwd = sizeof(T) == 4 ? 16 : 4;
+};
+
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value>), dim3(nwork, (A.nrhs + 15) / 16), dim3(256), 0, st, A);
+    const dim3 grid(nwork, (A.nrhs + 15) / 16);
+    constexpr int W = MmWide<T>::fwd;
+    if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
+        HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value, W>), grid, dim3(64 * W), 0, st, A);
+    else
+        HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value, 4>), grid, dim3(256), 0, st, A);
 }
 template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH(k_bwd_mm<T>, dim3(nwork, (A.nrhs + 15) / 16), dim3(256), 0, st, A);
+    const dim3 grid(nwork, (A.nrhs + 15) / 16);
+    constexpr int W = MmWide<T>::bwd;
+    if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
+        HSW_LAUNCH((k_bwd_mm<T, W>), grid, dim3(64 * W), 0, st, A);
+    else
+        HSW_LAUNCH((k_bwd_mm<T, 4>), grid, dim3(256), 0, st, A);
 }
 
 #define HSW_INST(T)                                                                          \
