@@ -8,13 +8,13 @@ What the paper fixes
   the panel vector by zero over the artificial PML, solve with H_i, and
   extract the panel's entries, which is valid because the panel's unknowns
   come last in H_i (Sec. 1.1, Eqs. 1.3-1.4 and Alg. 1.3).
-* The sweep combines L^{-1} and D^{-1} in a forward pass and applies L^{-T}
-  in a backward pass (Sec. 1.1, Alg. 1.5):
-      for i = 0..m-2:  u_i := T_i u_i;  u_{i+1} := u_{i+1} - J_{i+1,i} u_i
-      u_{m-1} := T_{m-1} u_{m-1}
-      for i = m-2..0:  u_i := u_i - T_i (J_{i+1,i}^T u_{i+1})
-  where J_{i+1,i} is the block of the damped operator J coupling panel i to
-  panel i+1.
+* The sweep (Sec. 1.1, Alg. 1.5) is a block forward and backward
+  substitution over the panels of the block LDL^T form of J, with each exact
+  inverse Schur complement replaced by T_i.  Going up, every panel's block is
+  multiplied by its T_i and its coupling to the panel above is subtracted
+  from that panel's block.  Going down, every panel but the last subtracts
+  T_i applied to the transposed coupling of the already final block above it.
+  The coupling blocks J_{i+1,i} are those of the damped operator J.
 
 The solves with H_i use SciPy's sparse LU (a library primitive); nothing is
 blocked or reordered beyond the steps above.  `exact=True` replaces every H_i

@@ -8,6 +8,7 @@ split; dependent right-hand sides fall back to GMRES per column; a zero
 right-hand side returns zero.
 """
 
+import math
 import numpy as np
 import pytest
 
@@ -61,7 +62,7 @@ def test_block_gmres_on_the_forcings_matches_oracle(model, prec):
         if prec == "c128":
             assert abs(info["iters"][r] - ref[r]) <= 1, (info["iters"], list(ref))
         else:
-            assert info["iters"][r] <= 1.2 * ref[r] + 1, (info["iters"], list(ref))
+            assert info["iters"][r] <= math.floor(1.2 * ref[r] + 1e-9), (info["iters"], list(ref))
 
 
 def test_block_gmres_with_restarts_matches_oracle():

@@ -10,6 +10,7 @@ count against the oracle's stored count (written by
 tests/golden/make_oracle_iterations.py, which calls only the oracle).
 """
 
+import math
 import json
 import os
 
@@ -99,7 +100,7 @@ def test_solve_full_size_matches_oracle_iterations(grf50, prec):
     if prec == "c128":
         assert abs(it - ref["iters"]) <= 1, (it, ref["iters"])
     else:
-        assert it <= 1.2 * ref["iters"] + 1, (it, ref["iters"])
+        assert it <= math.floor(1.2 * ref["iters"] + 1e-9), (it, ref["iters"])
 
 
 def test_20cubed_solve_matches_oracle_iterations():
@@ -121,7 +122,7 @@ def test_layered100_sixteen_shots_as_one_block():
     """The 100^3 layered workload, 16 surface shots solved as one block (the
     matrix-core passes): every shot reaches the FP64 true residual 1e-5 with
     the oracle's operator, and complex64 needs at most 1.2x the complex128
-    iterations (plus one)."""
+    iterations."""
     P = wl.make_problem("layered100")
     b = wl.sources(P)
     A = hz.helmholtz_operator(P["c"], P["h"], P["omega"], P["gamma"], P["C"], 0.0)
@@ -134,7 +135,7 @@ def test_layered100_sixteen_shots_as_one_block():
         for r in range(P["nrhs"]):
             assert np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r]) < 1e-5, (prec, r)
         its[prec] = max(info["iters"])
-    assert its["c64"] <= 1.2 * its["c128"] + 1, its
+    assert its["c64"] <= math.floor(1.2 * its["c128"] + 1e-9), its
 
 
 def test_batch48_uneven_batch_full_size():
@@ -143,7 +144,7 @@ def test_batch48_uneven_batch_full_size():
     solve in complex64 (the factors are inverted in place: two copies do not
     fit).  Every shot reaches rel-res 1e-5; for three sampled problems the FP64
     true residual is checked with the oracle's operator, and complex64 needs at
-    most 1.2x the complex128 iterations of those problems plus one."""
+    most 1.2x the complex128 iterations of those problems."""
     from paper_1204_0111_amd.hsweep import Solver
     Ps = [wl.make_problem("batch48", sub=k) for k in range(48)]
     bs = [wl.sources(P) for P in Ps]
@@ -169,4 +170,4 @@ def test_batch48_uneven_batch_full_size():
         for r in range(4):
             b = bs[k][r]
             assert np.linalg.norm(b - A @ x[k][r]) / np.linalg.norm(b) < 1e-5, (k, r)
-            assert info["iters"][4 * k + r] <= 1.2 * info2["iters"][4 * j + r] + 1, (k, r)
+            assert info["iters"][4 * k + r] <= math.floor(1.2 * info2["iters"][4 * j + r] + 1e-9), (k, r)
