@@ -27,3 +27,17 @@ def rel(a, b):
 
 
 TOL = {"c128": 1e-12, "c64": 1e-4}
+
+
+# Constant velocity, no PML, alpha = 0 and omega^2 = 6 c^2 / h^2: every
+# diagonal entry 6/h^2 - omega^2/c^2 of the 7-point operator is zero.  With
+# this h, 1/h^2 is exactly 24 in floating point and omega^2 = 144, so the
+# entries are exact zeros.
+H_ZERO_DIAG = 0.2041241452319315
+OMEGA_ZERO_DIAG = 12.0
+
+
+def zero_diagonal_problem():
+    n = (8, 7, 6)
+    return dict(name="constant", src="paper", n=n, h=H_ZERO_DIAG, c=np.ones((n[2], n[1], n[0])),
+                omega=OMEGA_ZERO_DIAG, alpha=0.0, gamma=2, C=0.0, d=2, leaf=3)

@@ -75,6 +75,47 @@ def test_middle_panel_solve_matches_oracle(grf50, prec):
     assert rel(y, ref) <= TOL[prec]
 
 
+_PANEL_REFS = {}
+
+
+def _panel_reference(name, i, nrhs=17, seed=31):
+    """Panel i of a workload, nrhs seeded random panel vectors and T_i of each
+    by SciPy's sparse LU of H_i (computed once per module)."""
+    import scipy.sparse.linalg as spla
+    key = (name, i, nrhs, seed)
+    if key not in _PANEL_REFS:
+        P = wl.make_problem(name)
+        H, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
+                                        P["d"], i)
+        N = hz.padded_shape(P["n"], P["gamma"])
+        plane = N[0] * N[1]
+        v = wl.random_complex((nrhs, (hi - lo) * plane), seed)
+        ext = np.zeros((H.shape[0], nrhs), dtype=np.complex128)
+        ext[ga * plane:] = v.T
+        lu = spla.splu(H.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        ref = lu.solve(ext)[ga * plane:].T.copy()
+        del lu
+        _PANEL_REFS[key] = (P, v, ref)
+    return _PANEL_REFS[key]
+
+
+@pytest.mark.parametrize("name", ["grf50", "layered100"])
+@pytest.mark.parametrize("nrhs", [16, 17])
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_middle_panel_many_rhs_matrix_core_passes_match_oracle(name, nrhs, prec):
+    """T_i of a full-size middle panel for 16 and 17 right-hand sides, the
+    matrix-core passes (Sec. 2.4, many right-hand sides), against the
+    oracle's sparse LU per right-hand side.  The layered 100^3 panel has the
+    longest contractions of the benchmark (root front s = 1680 pivots)."""
+    P, v, ref = _panel_reference(name, 5)
+    S = _solver(P, prec)
+    y = S.panel_solve(0, 5, torch.as_tensor(v[:nrhs]).to("cuda")).cpu().numpy()
+    S.close()
+    errs = [rel(y[r], ref[r]) for r in range(nrhs)]
+    print("%s %s nrhs=%d: worst T_i relative error %.3e" % (name, prec, nrhs, max(errs)))
+    assert max(errs) <= TOL[prec], errs
+
+
 def test_matvec_full_size(grf50):
     P, _ = grf50
     S = _solver(P, "c64")

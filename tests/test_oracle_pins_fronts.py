@@ -21,6 +21,7 @@ from oracle import ldlt as ld
 from oracle import nd
 from oracle import panels as pn
 from paper_1204_0111_amd import workloads as wl
+from tests._cases import zero_diagonal_problem
 
 
 def _unit_lower(s, seed):
@@ -276,3 +277,20 @@ def test_pins_reject_planted_artificial_pml_mistakes(mut):
             assert _quasi_1d_T(16, 80.0, tables=_mutated_tables(**mut)) > 0.5
     finally:
         del pn._orig_tables
+
+
+# ------------------------------------------- breakdown without pivoting (Sec. 2.5)
+def test_zero_diagonal_case_breaks_the_unpivoted_factorisation():
+    """At omega^2 = 6 c^2 / h^2 without PML the operator's diagonal is zero;
+    the unpivoted LDL^T of panel 0 breaks down at its first pivot.  The
+    parameters make the entries exact zeros in floating point."""
+    P = zero_diagonal_problem()
+    assert 1.0 / (P["h"] * P["h"]) == 24.0
+    H, lo, hi, ga = pn.aux_operator(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"],
+                                    P["d"], 0)
+    assert np.abs(H.diagonal()).max() == 0.0
+    N = hz.padded_shape(P["n"], P["gamma"])
+    nodes = nd.nested_dissection(N[0], N[1], P["leaf"])
+    perm = nd.elimination_order(nodes, N[0], N[1], ga + hi - lo)
+    with pytest.raises(ld.BreakdownError, match="pivot at 0"):
+        ld.ldlt_unpivoted(H[perm][:, perm].toarray())
