@@ -119,6 +119,12 @@ struct Lane {
     hipStream_t st = nullptr;
     void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;  // panel-solve workspace
     int nrhs_cap = 0;
+    // workspace of the matrix-core passes, [entry][16] blocks per group of 16
+    // right-hand sides: x_mid, update-set values, the child-contribution
+    // slots of every panel class (each class its own zeroed region) and the
+    // right-hand side in elimination order (likewise per class)
+    void *d_mxmid = nullptr, *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;
+    int mm_groups = 0;
     std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
 };
 
@@ -154,6 +160,12 @@ struct hsw_ctx {
     int64_t L_size = 0, D_size = 0;
     int max_naux = 0;
     int64_t max_wsize = 0, max_c2 = 0;
+    // per class: first entry of its region of the matrix-core passes'
+    // child-contribution slots (sum of the earlier classes' c2size); the
+    // right-hand-side region uses cls_perm_off
+    std::vector<int64_t> cls_c2_base;
+    int64_t total_c2 = 0, total_naux = 0;
+    std::vector<char> cls_mixed_ga;  // the class serves panels with different auxiliary depths
     int64_t et_size = 0;
     std::vector<int64_t> et_prob_off, et_panel_off;
 
@@ -256,11 +268,12 @@ static void free_lane(Lane& L, bool own_stream) {
     for (auto& w : L.gws)
         if (w.first) (void)hipFree(w.first);
     L.gws.clear();
-    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2}) {
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxmid, &L.d_mxu, &L.d_mc2, &L.d_mh2}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     L.nrhs_cap = 0;
+    L.mm_groups = 0;
     if (own_stream && L.st) (void)hipStreamDestroy(L.st);
 }
 
@@ -388,7 +401,18 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
         ctx->max_naux = std::max(ctx->max_naux, c.naux);
         ctx->max_wsize = std::max(ctx->max_wsize, c.wsize);
         ctx->max_c2 = std::max(ctx->max_c2, c.c2size);
+        ctx->cls_c2_base.push_back(ctx->total_c2);
+        ctx->total_c2 += c.c2size;
+        ctx->total_naux += c.naux;
         ctx->maxdepth = std::max(ctx->maxdepth, c.maxdepth);
+    }
+    ctx->cls_mixed_ga.assign(ctx->classes.size(), 0);
+    {
+        std::vector<int> ga_seen(ctx->classes.size(), -1);
+        for (const PanelDev& P : ctx->pan_h) {
+            if (ga_seen[P.cls] >= 0 && ga_seen[P.cls] != P.ga) ctx->cls_mixed_ga[P.cls] = 1;
+            ga_seen[P.cls] = P.ga;
+        }
     }
     // front instances
     int64_t loff = 0, doff = 0;
@@ -1169,7 +1193,14 @@ extern "C" hsw_status hsw_setup(hsw_ctx* ctx) {
 
 // ---------------------------------------------------------------------------
 template <typename T>
+static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups);
+
+template <typename T>
 static hsw_status ensure_solve_ws(hsw_ctx* ctx, Lane& L, int nrhs) {
+    if (nrhs >= MM_MIN_RHS) {
+        hsw_status s = ensure_mm_ws<T>(ctx, L, (nrhs + 15) / 16);
+        if (s != HSW_OK) return s;
+    }
     if (nrhs <= L.nrhs_cap) return HSW_OK;
     HIPCHK(hipStreamSynchronize(L.st));
     if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
@@ -1182,6 +1213,33 @@ static hsw_status ensure_solve_ws(hsw_ctx* ctx, Lane& L, int nrhs) {
     HIPCHK(hipMalloc(&L.d_xu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
     HIPCHK(hipMalloc(&L.d_c2, e * (size_t)std::max<int64_t>(ctx->max_c2, 1)));
     L.nrhs_cap = nrhs;
+    return HSW_OK;
+}
+
+// Workspace of the matrix-core passes for `groups` groups of 16 right-hand
+// sides.  The child-contribution and right-hand-side regions start zeroed:
+// entries no child writes, and the auxiliary-plane entries of the right-hand
+// side, are read as zeros by the passes and never written.
+template <typename T>
+static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
+    if (groups <= L.mm_groups) return HSW_OK;
+    HIPCHK(hipStreamSynchronize(L.st));
+    if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
+    for (void** p : {&L.d_mxmid, &L.d_mxu, &L.d_mc2, &L.d_mh2}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    L.mm_groups = 0;
+    const size_t e = sizeof(Cx<T>) * 16 * (size_t)groups;
+    const size_t bc2 = e * (size_t)std::max<int64_t>(ctx->total_c2, 1);
+    const size_t bh2 = e * (size_t)std::max<int64_t>(ctx->total_naux, 1);
+    HIPCHK(hipMalloc(&L.d_mxmid, e * (size_t)ctx->max_naux));
+    HIPCHK(hipMalloc(&L.d_mxu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
+    HIPCHK(hipMalloc(&L.d_mc2, bc2));
+    HIPCHK(hipMalloc(&L.d_mh2, bh2));
+    HIPCHK(hipMemsetAsync(L.d_mc2, 0, bc2, L.st));
+    HIPCHK(hipMemsetAsync(L.d_mh2, 0, bh2, L.st));
+    L.mm_groups = groups;
     return HSW_OK;
 }
 
@@ -1261,7 +1319,23 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     PassArgs<T> AT = A;
     AT.G = (const Cx<T>*)ctx->d_L + f0.loff;
     if (nrhs >= MM_MIN_RHS && force_f < 0 && !tri_all) {  // matrix-core passes, 16 right-hand sides per group
+        const int64_t cls_c2 = ctx->cls_c2_base[P.cls], cls_h2 = ctx->cls_perm_off[P.cls];
+        A.xmid = (Cx<T>*)ln.d_mxmid;
+        A.xu = (Cx<T>*)ln.d_mxu;
+        A.c2 = (Cx<T>*)ln.d_mc2 + 16 * cls_c2;
+        A.h2 = (Cx<T>*)ln.d_mh2 + 16 * cls_h2;
+        A.perm = ctx->d_perm + P.perm_off;
+        A.zero_aux = ctx->cls_mixed_ga[P.cls];
+        A.gs_x = 16 * (int64_t)ctx->max_naux;
+        A.gs_u = 16 * std::max<int64_t>(ctx->max_wsize, 1);
+        A.gs_c2 = 16 * std::max<int64_t>(ctx->total_c2, 1);
+        A.gs_h2 = 16 * std::max<int64_t>(ctx->total_naux, 1);
         A.mode = gmode;
+        // the right-hand side in elimination order: read the panel planes (or
+        // the next plane) once, write 16 right-hand sides per entry
+        run("scatter", 1, (double)c.naux * ((nrhs + 15) / 16) * 16 * es + 16.0 * nrhs * P.Nx * P.Ny *
+                                                                               (gmode == 0 ? P.hi - P.lo : 1),
+            0.0, [&] { launch_rhs_scatter<T>(A, st); });
         for (int d = c.maxdepth; d >= 0; --d) {
             const int fs = mm_fwd_shape<T>();
             A.items = ctx->d_sitems + lv[d].foff[fs];
@@ -1440,6 +1514,11 @@ static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* 
         gl.d_xu = ln.d_xu;
         gl.d_c2 = ln.d_c2;
         gl.nrhs_cap = ln.nrhs_cap;
+        gl.d_mxmid = ln.d_mxmid;
+        gl.d_mxu = ln.d_mxu;
+        gl.d_mc2 = ln.d_mc2;
+        gl.d_mh2 = ln.d_mh2;
+        gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             for (int i = 0; i < h.m; ++i)
@@ -2225,8 +2304,8 @@ extern "C" hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_
                                         int64_t* launches, double* seconds, double* bytes,
                                         double* flops) {
     if (!ctx || !kernel) return HSW_E_INVAL;
-    static const char* known[] = {"fwd", "bwd", "diag", "panel", "trailing", "schur", "assemble",
-                                  "inverse", "matvec"};
+    static const char* known[] = {"fwd", "bwd", "scatter", "diag", "panel", "trailing", "schur",
+                                  "assemble", "inverse", "matvec"};
     bool ok = false;
     for (const char* k : known) ok = ok || std::strcmp(k, kernel) == 0;
     if (!ok) return fail(ctx, HSW_E_INVAL, std::string("unknown kernel class ") + kernel);

@@ -60,6 +60,9 @@ template <typename T>
 void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t st);
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
+// the panel's right-hand side into h2, in elimination order (matrix-core passes)
+template <typename T>
+void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st);
 template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
 template <typename T>

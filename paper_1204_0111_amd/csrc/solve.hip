@@ -384,70 +384,120 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
 // ---------------------------------------------------------------------------
 // Passes for groups of 16 right-hand sides on the matrix cores: the products
 // G v_S and G^T [x_S; -x_U] of the panel solves become GEMMs with 16 columns
-// (the sweeps of many sources applied at once).  A workgroup covers 64 rows
-// (forward) or 16 columns (backward) of one front for 16 right-hand sides;
-// its four waves split the contraction into interleaved 16-entry chunks, each
-// wave with its own LDS staging and the next chunk's loads in flight, and
-// their partial 16 x 16 blocks are summed through LDS at the end.  Complex
-// products are four real 16 x 16 x 4 products (FP32 for complex64, FP64 for
-// complex128).  Inputs, outputs and the exchanges between fronts are those of
-// k_fwd / k_bwd.
+// (the sweeps of many sources applied at once).  Every vector of these passes
+// is held as [entry][16] blocks (the 16 right-hand sides of an entry
+// contiguous, one block of entries per group), so each operand chunk is a
+// dense, coalesced read:
+//   * at the start of a panel solve the scatter puts the panel's right-hand
+//     side, in elimination order, into h2 (zero extension over the auxiliary
+//     planes, or the coupling J_{i+1,i}^T of the next plane on the last one);
+//   * a front's vector v_S is h2 on its pivots plus the two halves of its
+//     child-contribution slots, which lie in a region of the panel class's
+//     own whose entries no child writes stay zero, so no extend-add map is
+//     read in the products.
+// Nothing a product loads decides a branch: the next chunk's loads stay in
+// flight during the current chunk's products.  A workgroup covers 16 RT rows
+// (forward) or 16 columns (backward) of one front; its NW waves split the
+// contraction into interleaved 16-entry chunks and sum their partial blocks
+// through LDS at the end.  Complex products are four real 16 x 16 x 4
+// products (FP32 for complex64, FP64 for complex128).
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// h2 := the panel's right-hand side in elimination order, 64 positions per
+// workgroup and one group of 16 right-hand sides per blockIdx.y.  Mode 0
+// writes the panel's own planes (q >= ga); mode 1 writes J_{i+1,i}^T of the
+// next plane on the last plane and zeros on the other panel planes.  The
+// auxiliary planes (q < ga) stay zero: they are written (as zeros) only when
+// the class also serves a panel with fewer auxiliary planes (zero_aux).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
+    __shared__ T Sre[64][17], Sim[64][17];
+    __shared__ int wr[64];
+    const int e0 = blockIdx.x * 64, grp = blockIdx.y;
+    const int tid = threadIdx.x, el = tid & 63;
+    const int e = e0 + el;
+    int64_t goff = -1;
+    Cx<double> cf = cx<double>(1, 0);
+    bool write = false;
+    if (e < A.naux) {
+        const int b = A.perm[e];
+        const int q = b / A.NxNy, lat = b - q * A.NxNy;
+        write = q >= A.ga || A.zero_aux;
+        if (A.mode == 0) {
+            if (q >= A.ga) goff = (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
+        } else if (q == A.nz - 1) {
+            goff = (int64_t)(A.hi - A.plane0) * A.NxNy + lat;
+            cf = plane_coupling(A, lat);
+        }
+    }
+    // read with consecutive threads on consecutive positions (runs of grid nodes)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = (tid >> 6) + 4 * j;
+        const int64_t rr = (int64_t)grp * 16 + r;
+        Cx<T> v = cx<T>(0, 0);
+        if (goff >= 0 && rr < A.nrhs) {
+            const Cx<double> x = A.src[rr * A.ld + goff];
+            v = ccast<T>(A.mode == 0 ? x : cf * x);
+        }
+        Sre[el][r] = v.re;
+        Sim[el][r] = v.im;
+    }
+    if (tid < 64) wr[tid] = write;
+    __syncthreads();
+    // write whole [entry][16] blocks, sixteen consecutive threads per entry
+    Cx<T>* h2 = A.h2 + grp * A.gs_h2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j;
+        const int l = idx >> 4, r = idx & 15;
+        if (e0 + l < A.naux && wr[l]) h2[(int64_t)(e0 + l) * 16 + r] = cx<T>(Sre[l][r], Sim[l][r]);
+    }
+}
+
 // RT row tiles of 16 per workgroup: each of the NW waves updates all of them
-// over every NW-th chunk of the contraction (the front vector is staged once
-// per RT tiles).  Launches with few workgroups (the upper depths, with long
-// contractions) take the wide form, NW = 8, to shorten each wave's chain of
-// chunks.
+// over every NW-th chunk of the contraction.  Launches with few workgroups
+// (the upper depths, with long contractions) take the wide form, NW = 8, to
+// shorten each wave's chain of chunks.
 template <typename T, int RT, int NW>
 __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
     const SolveItem it = A.items[blockIdx.x];  // items of 16 RT rows
     const int n = it.n, s = it.s;
-    const int rhs0 = blockIdx.y * 16;
+    const int grp = blockIdx.y;
+    const int64_t rhs0 = (int64_t)grp * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int kend = (it.blk + 16 * RT <= s) ? it.blk + 16 * RT : s;
-    __shared__ T Vre[NW][KC][17], Vim[NW][KC][17];  // per wave: front-vector chunk [entry][rhs]
     __shared__ T Yre[16 * RT][17], Yim[16 * RT][17];  // the block's sum [row][rhs]
-    const int* map0 = A.cmap + it.moff;
-    const int* map1 = map0 + n;
-    auto vget = [&](int k, int r) -> Cx<T> {
-        const int64_t rr = rhs0 + r;
-        if (k >= kend || rr >= A.nrhs) return cx<T>(0, 0);
-        const int b = pivot_box(it, A.Nx, A.NxNy, k);
-        const int q = b / A.NxNy, lat = b - q * A.NxNy;
-        const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
-        Cx<T> v = keep(map0[k] >= 0, cc[k]) + keep(map1[k] >= 0, cc[n + k]);
-        if (A.mode == 0) {
-            if (q >= A.ga)
-                v = v + ccast<T>(A.src[rr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat]);
-        } else if (q == A.nz - 1) {
-            v = v + ccast<T>(plane_coupling(A, lat) * A.src[rr * A.ld + (int64_t)(A.hi - A.plane0) * A.NxNy + lat]);
-        }
-        return v;
-    };
-    // this lane feeds rows blk + 16 t + li (t < RT) to the products
+    // the front's slices of the group: children's halves [0, n) and [n, 2n),
+    // right-hand side on its pivots
+    const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
+    const Cx<T>* h2f = A.h2 + grp * A.gs_h2 + (int64_t)it.start * 16;
     const Cx<T>* g = A.G + it.loff;
-    auto gget = [&](int t, int k) -> Cx<T> {
-        const int row = it.blk + 16 * t + li;
-        return (row < n && k < kend) ? g[(int64_t)k * n + row] : cx<T>(0, 0);
-    };
-    Cx<T> ga[RT][4], gn[RT][4], vv[4], vn[4];
-    auto load = [&](int c, Cx<T>(&gx)[RT][4], Cx<T>(&vx)[4]) {
+    // lane operands: A(row, k) = G(blk + 16 t + li, c + 4 q + lk) and
+    // B(k, rhs) = v_S(c + 4 q + lk, li)
+    Cx<T> ga[RT][4], gn[RT][4], va[4], vn[4], ca[4], cn[4], da[4], dn[4];
+    auto load = [&](int c, Cx<T>(&gx)[RT][4], Cx<T>(&vx)[4], Cx<T>(&cx0)[4], Cx<T>(&cx1)[4]) {
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) gx[t][q] = gget(t, c + 4 * q + lk);
+            for (int q = 0; q < 4; ++q) {
+                const int row = it.blk + 16 * t + li, k = c + 4 * q + lk;
+                gx[t][q] = (row < n && k < kend) ? g[(int64_t)k * n + row] : cx<T>(0, 0);
+            }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = lane + 64 * j;
-            vx[j] = vget(c + (e >> 4), e & 15);
+        for (int q = 0; q < 4; ++q) {
+            const int k = c + 4 * q + lk;
+            const bool ok = k < kend;
+            vx[q] = ok ? h2f[(int64_t)k * 16 + li] : cx<T>(0, 0);
+            cx0[q] = ok ? c2f[(int64_t)k * 16 + li] : cx<T>(0, 0);
+            cx1[q] = ok ? c2f[(int64_t)(n + k) * 16 + li] : cx<T>(0, 0);
         }
     };
     V4 are[RT], aim[RT];
@@ -460,39 +510,35 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     const int kb = (leaf_first_live(A, it) / KC) * KC;
     const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
     int ch = wave;
-    if (ch < nch) load(kb + ch * KC, ga, vv);
+    if (ch < nch) load(kb + ch * KC, ga, va, ca, da);
     for (; ch < nch; ch += NW) {
         const bool more = ch + NW < nch;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = lane + 64 * j;
-            Vre[wave][e >> 4][e & 15] = vv[j].re;
-            Vim[wave][e >> 4][e & 15] = vv[j].im;
-        }
-        wave_lds_sync();
-        if (more) load(kb + (ch + NW) * KC, gn, vn);
+        if (more) load(kb + (ch + NW) * KC, gn, vn, cn, dn);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T br = Vre[wave][4 * q + lk][li], bi = Vim[wave][4 * q + lk][li];
+            const Cx<T> b = va[q] + ca[q] + da[q];
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                are[t] = mfma4(ga[t][q].re, br, are[t]);
-                aim[t] = mfma4(ga[t][q].re, bi, aim[t]);
+                are[t] = mfma4(ga[t][q].re, b.re, are[t]);
+                aim[t] = mfma4(ga[t][q].re, b.im, aim[t]);
             }
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                are[t] = mfma4(-ga[t][q].im, bi, are[t]);
-                aim[t] = mfma4(ga[t][q].im, br, aim[t]);
+                are[t] = mfma4(-ga[t][q].im, b.im, are[t]);
+                aim[t] = mfma4(ga[t][q].im, b.re, aim[t]);
             }
         }
-        wave_lds_sync();
         if (more) {
 #pragma unroll
             for (int t = 0; t < RT; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) ga[t][q] = gn[t][q];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) vv[j] = vn[j];
+            for (int q = 0; q < 4; ++q) {
+                va[q] = vn[q];
+                ca[q] = cn[q];
+                da[q] = dn[q];
+            }
         }
     }
     // sum the waves' partial blocks in LDS, one wave at a time
@@ -514,26 +560,30 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         }
         __syncthreads();
     }
-    // thread tid < 256: rows blk + tid / 16 + 16 t, right-hand side rhs0 + tid % 16
-    const int64_t orr = rhs0 + (tid & 15);
-    if (tid >= 256 || orr >= A.nrhs) return;
+    // thread tid < 256: right-hand side rhs0 + tid % 16 of rows blk + tid / 16 + 16 t
+    // (a row's 16 right-hand sides are one contiguous block)
+    const int r = tid & 15;
+    if (tid >= 256 || rhs0 + r >= A.nrhs) return;
+    Cx<T>* xm = A.xmid + grp * A.gs_x;
+    Cx<T>* c2g = A.c2 + grp * A.gs_c2;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int lrow = (tid >> 4) + 16 * t, row = it.blk + lrow;
         if (row >= n) continue;
-        const Cx<T> y = cx<T>(Yre[lrow][tid & 15], Yim[lrow][tid & 15]);
+        const Cx<T> y = cx<T>(Yre[lrow][r], Yim[lrow][r]);
         if (row < s) {
-            A.xmid[orr * A.naux + it.start + row] = y * A.dinv[it.start + row];
+            xm[(int64_t)(it.start + row) * 16 + r] = y * A.dinv[it.start + row];
         } else {
-            const Cx<T>* cc = A.c2 + orr * A.c2ld + it.c2;
-            const Cx<T> pre = keep(map0[row] >= 0, cc[row]) + keep(map1[row] >= 0, cc[n + row]);
-            A.c2[orr * A.c2ld + it.push + A.pmap[it.pmap + row - s]] = pre - y;
+            const Cx<T> pre = c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
+            c2g[(int64_t)(it.push + A.pmap[it.pmap + row - s]) * 16 + r] = pre - y;
         }
     }
 }
 
 // NW waves split the rows of the contraction by chunks; the wide form serves
-// launches with few workgroups, as for k_fwd_mm.
+// launches with few workgroups, as for k_fwd_mm.  G^T is read by columns, so
+// each wave stages its G chunk through LDS; [x_S; -x_U] comes straight from
+// the [entry][16] blocks.
 template <typename T, int NW>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
@@ -541,44 +591,46 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     const SolveItem it = A.items[blockIdx.x];  // items of 16 columns
     if (leaf_aux_block(it, A.ga, it.blk, 16)) return;
     const int n = it.n, s = it.s;
-    const int rhs0 = blockIdx.y * 16;
+    const int grp = blockIdx.y;
+    const int64_t rhs0 = (int64_t)grp * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int c0 = it.blk;
     __shared__ T Gre[NW][KC][17], Gim[NW][KC][17];  // per wave: G chunk [row][column]
-    __shared__ T Rre[NW][KC][17], Rim[NW][KC][17];  // per wave: [x_S; -x_U] chunk [row][rhs]
     __shared__ T Yre[16][17], Yim[16][17];          // the waves' partial blocks, summed [column][rhs]
+    Cx<T>* xu = A.xu + grp * A.gs_u;
+    const Cx<T>* xm = A.xmid + grp * A.gs_x + (int64_t)it.start * 16;
+    const Cx<T>* xuf = xu + (int64_t)it.xu * 16;
     // the first column block hands the update-set values on to the children
     if (c0 == 0 && (it.cxu0 >= 0 || it.cxu1 >= 0)) {
         for (int idx = tid; idx < (n - s) * 16; idx += 64 * NW) {
-            const int i = s + (idx >> 4);
-            const int64_t rr = rhs0 + (idx & 15);
-            if (rr >= A.nrhs) continue;
-            const Cx<T> xv = A.xu[rr * A.xuld + it.xu + i - s];
+            const int i = s + (idx >> 4), r = idx & 15;
+            const Cx<T> xv = xuf[(int64_t)(i - s) * 16 + r];
             if (it.cxu0 >= 0) {
                 const int p0 = A.cmap[it.moff + i];
-                if (p0 >= 0) A.xu[rr * A.xuld + it.cxu0 + p0] = xv;
+                if (p0 >= 0) xu[(int64_t)(it.cxu0 + p0) * 16 + r] = xv;
             }
             if (it.cxu1 >= 0) {
                 const int p1 = A.cmap[it.moff + n + i];
-                if (p1 >= 0) A.xu[rr * A.xuld + it.cxu1 + p1] = xv;
+                if (p1 >= 0) xu[(int64_t)(it.cxu1 + p1) * 16 + r] = xv;
             }
         }
     }
     const Cx<T>* gb = A.G + it.loff;
-    auto rget = [&](int i, int r) -> Cx<T> {
-        const int64_t rr = rhs0 + r;
-        if (i >= n || rr >= A.nrhs) return cx<T>(0, 0);
-        return i < s ? A.xmid[rr * A.naux + it.start + i] : -A.xu[rr * A.xuld + it.xu + i - s];
-    };
     auto gget = [&](int i, int j) -> Cx<T> { return (i < n && j < s) ? gb[(int64_t)j * n + i] : cx<T>(0, 0); };
+    // B(k, rhs) = [x_S; -x_U](i0 + 4 q + lk, li); the sign is applied at use
+    auto rget = [&](int i) -> Cx<T> {
+        if (i >= n) return cx<T>(0, 0);
+        const Cx<T>* p = i < s ? xm + (int64_t)i * 16 : xuf + (int64_t)(i - s) * 16;
+        return p[li];
+    };
     Cx<T> gv[4], gn[4], rv[4], rn[4];
     auto load = [&](int i0, Cx<T>(&gx)[4], Cx<T>(&rx)[4]) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int e = lane + 64 * j;
             gx[j] = gget(i0 + (e & 15), c0 + (e >> 4));  // 16 consecutive rows of a column
-            rx[j] = rget(i0 + (e >> 4), e & 15);
+            rx[j] = rget(i0 + 4 * j + lk);
         }
     };
     V4 are = V4{0, 0, 0, 0}, aim = V4{0, 0, 0, 0};
@@ -587,13 +639,12 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     if (ch < nch) load(c0 + ch * KC, gv, rv);
     for (; ch < nch; ch += NW) {
         const bool more = ch + NW < nch;
+        const int i0 = c0 + ch * KC;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int e = lane + 64 * j;
             Gre[wave][e & 15][e >> 4] = gv[j].re;
             Gim[wave][e & 15][e >> 4] = gv[j].im;
-            Rre[wave][e >> 4][e & 15] = rv[j].re;
-            Rim[wave][e >> 4][e & 15] = rv[j].im;
         }
         wave_lds_sync();
         if (more) load(c0 + (ch + NW) * KC, gn, rn);
@@ -601,11 +652,11 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         for (int q = 0; q < 4; ++q) {
             const int kk = 4 * q + lk;
             const T ar = Gre[wave][kk][li], ai = Gim[wave][kk][li];
-            const T br = Rre[wave][kk][li], bi = Rim[wave][kk][li];
-            are = mfma4(ar, br, are);
-            aim = mfma4(ar, bi, aim);
-            are = mfma4(-ai, bi, are);
-            aim = mfma4(ai, br, aim);
+            const Cx<T> b = i0 + kk < s ? rv[q] : -rv[q];
+            are = mfma4(ar, b.re, are);
+            aim = mfma4(ar, b.im, aim);
+            are = mfma4(-ai, b.im, are);
+            aim = mfma4(ai, b.re, aim);
         }
         wave_lds_sync();
         if (more) {
@@ -633,19 +684,27 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         }
         __syncthreads();
     }
-    // thread tid < 256: column c0 + tid / 16, right-hand side rhs0 + tid % 16
-    const int j = c0 + (tid >> 4);
-    const int64_t orr = rhs0 + (tid & 15);
-    if (tid >= 256 || j >= s || orr >= A.nrhs) return;
-    const Cx<T> x = cx<T>(Yre[tid >> 4][tid & 15], Yim[tid >> 4][tid & 15]);
-    if (it.cxu0 >= 0) {
-        const int o0 = A.cmap[it.moff + j];
-        if (o0 >= 0) A.xu[orr * A.xuld + it.cxu0 + o0] = x;
+    if (tid >= 256) return;
+    // children's update-set values: a column's 16 right-hand sides are one block
+    {
+        const int jl = tid >> 4, r = tid & 15, j = c0 + jl;
+        if (j < s && rhs0 + r < A.nrhs) {
+            const Cx<T> x = cx<T>(Yre[jl][r], Yim[jl][r]);
+            if (it.cxu0 >= 0) {
+                const int o0 = A.cmap[it.moff + j];
+                if (o0 >= 0) xu[(int64_t)(it.cxu0 + o0) * 16 + r] = x;
+            }
+            if (it.cxu1 >= 0) {
+                const int o1 = A.cmap[it.moff + n + j];
+                if (o1 >= 0) xu[(int64_t)(it.cxu1 + o1) * 16 + r] = x;
+            }
+        }
     }
-    if (it.cxu1 >= 0) {
-        const int o1 = A.cmap[it.moff + n + j];
-        if (o1 >= 0) A.xu[orr * A.xuld + it.cxu1 + o1] = x;
-    }
+    // the padded grid: consecutive threads on consecutive pivots of one right-hand side
+    const int jl = tid & 15, j = c0 + jl;
+    const int64_t orr = rhs0 + (tid >> 4);
+    if (j >= s || orr >= A.nrhs) return;
+    const Cx<T> x = cx<T>(Yre[jl][tid >> 4], Yim[jl][tid >> 4]);
     const int b = pivot_box(it, A.Nx, A.NxNy, j);
     const int q = b / A.NxNy, lat = b - q * A.NxNy;
     if (q < A.ga) return;
@@ -1003,6 +1062,12 @@ template <typename T> struct MmWide {
 };
 
 template <typename T>
+void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st) {
+    if (A.naux <= 0) return;
+    const dim3 grid((A.naux + 63) / 64, (A.nrhs + 15) / 16);
+    HSW_LAUNCH(k_rhs_scatter<T>, grid, dim3(256), 0, st, A);
+}
+template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
@@ -1028,6 +1093,7 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
     template void launch_fwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
+    template void launch_rhs_scatter<T>(const PassArgs<T>&, hipStream_t);                    \
     template void launch_bwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
     template int solve_rhs_chunk<T>(int, int);
 HSW_INST(float)
