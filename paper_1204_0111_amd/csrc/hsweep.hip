@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -72,6 +73,9 @@ struct SolveLevel {
     int64_t toff = 0;
     int tcount = 0;
     int smax = 0, nmax = 0;
+    // matrix-core passes: items of 64 rows / columns (0) or of 16 (1) per
+    // pass, picked by the autotuner; -1: the fixed rule
+    int mm_f = -1, mm_b = -1;
     // algorithmic traffic: bytes per right-hand side of the vectors each pass
     // reads and writes, and the G entries a pass needs (also its complex
     // multiply-adds per right-hand side): those of the fronts with children,
@@ -188,6 +192,7 @@ struct hsw_ctx {
     std::mutex err_mu;
     bool autotune = true;
     bool tuned[N_RHS_KEYS] = {};
+    bool tuned_mm = false;  // the matrix-core passes' item sizes
     // triangular passes with the kept factors: 0 never, 1 at every depth,
     // 2 where the autotuner finds them faster than the inverse passes
     int tri_mode = 2;
@@ -1260,7 +1265,8 @@ static bool tri_available(const hsw_ctx* ctx) {
 template <typename T>
 static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx<double>* src,
                          int64_t ld, int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
-                         int force_f = -1, int force_b = -1, hipEvent_t* ev = nullptr) {
+                         int force_f = -1, int force_b = -1, hipEvent_t* ev = nullptr, int mm_force_f = -1,
+                         int mm_force_b = -1) {
     hipStream_t st = ln.st;
     const PanelDev& P = ctx->pan_h[gpanel];
     const ProbDev& Q = ctx->prob_h[P.prob];
@@ -1332,21 +1338,41 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         A.gs_h2 = 16 * std::max<int64_t>(ctx->total_naux, 1);
         A.mode = gmode;
         // the right-hand side in elimination order: read the panel planes (or
-        // the next plane) once, write 16 right-hand sides per entry
-        run("scatter", 1, (double)c.naux * ((nrhs + 15) / 16) * 16 * es + 16.0 * nrhs * P.Nx * P.Ny *
-                                                                               (gmode == 0 ? P.hi - P.lo : 1),
-            0.0, [&] { launch_rhs_scatter<T>(A, st); });
+        // the next plane) once, write 16 right-hand sides per entry (untimed
+        // while the autotuner times the passes)
+        if (ev)
+            launch_rhs_scatter<T>(A, st);
+        else
+            run("scatter", 1, (double)c.naux * ((nrhs + 15) / 16) * 16 * es +
+                                  16.0 * nrhs * P.Nx * P.Ny * (gmode == 0 ? P.hi - P.lo : 1),
+                0.0, [&] { launch_rhs_scatter<T>(A, st); });
+        const int groups = (nrhs + 15) / 16;
         for (int d = c.maxdepth; d >= 0; --d) {
-            const int fs = mm_fwd_shape<T>();
+            // 64-row items, or 16-row ones (the tuned choice, else where 64-row
+            // items give few workgroups; complex128 always takes 16-row items)
+            int fs = mm_fwd_shape<T>(), rt = MmFwdTiles<T>::value;
+            const int pick = mm_force_f >= 0 ? mm_force_f : lv[d].mm_f;
+            if (rt == 4 && (pick == 1 || (pick < 0 && lv[d].fcount[fs] * groups < MM_NARROW_BELOW))) {
+                fs = 1;
+                rt = 1;
+            }
             A.items = ctx->d_sitems + lv[d].foff[fs];
-            run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * ((nrhs + 15) / 16) + nrhs * lv[d].fwd_vec_bytes,
-                8.0 * nrhs * lv[d].g_need(pf), [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], st); });
+            run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pf), [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], rt, st); });
         }
         A.mode = emode;
         for (int d = 0; d <= c.maxdepth; ++d) {
-            A.items = ctx->d_sitems + lv[d].boff[MM_BWD_SHAPE];
-            run("bwd", lv[d].bcount[MM_BWD_SHAPE], es * lv[d].g_need(pb) * ((nrhs + 15) / 16) + nrhs * lv[d].bwd_vec_bytes,
-                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[MM_BWD_SHAPE], st); });
+            // 64-column items (the tuned choice, else where they give enough
+            // workgroups), or 16-column ones
+            int bs = MM_BWD_SHAPE, ct = 1;
+            const int bpick = mm_force_b >= 0 ? mm_force_b : lv[d].mm_b;
+            if (bpick == 0 || (bpick < 0 && lv[d].bcount[MM_BWD_SHAPE64] * groups >= MM_TILES4_FROM)) {
+                bs = MM_BWD_SHAPE64;
+                ct = 4;
+            }
+            A.items = ctx->d_sitems + lv[d].boff[bs];
+            run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec_bytes,
+                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[bs], ct, st); });
         }
         return;
     }
@@ -1389,10 +1415,14 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
 // group.  Runs once per group, at the first solve after a setup; the plan
 // and the factors' values do not affect the choice.
 template <typename T>
+static hsw_status tune_solve_mm(hsw_ctx* ctx);
+
+template <typename T>
 static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     const int key = rhs_key(nrhs);
+    if (nrhs >= MM_MIN_RHS) return tune_solve_mm<T>(ctx);
     // inside a multi-lane solve the shapes are fixed (tuning runs on lane 0 before it)
-    if (!ctx->autotune || ctx->tuned[key] || nrhs >= MM_MIN_RHS || ctx->in_lanes) return HSW_OK;
+    if (!ctx->autotune || ctx->tuned[key] || ctx->in_lanes) return HSW_OK;
     constexpr int REPS = 3;
     // candidates: every block shape, plus the triangular passes when the factors are kept
     const bool tri = tri_available(ctx);
@@ -1460,6 +1490,78 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     cleanup();
     ctx->tuned[key] = true;
     return status;
+}
+
+// Autotuner of the matrix-core passes: for every panel class and tree depth,
+// time items of 64 and of 16 rows (forward) and of 64 and of 16 columns
+// (backward) inside whole panel solves of one group of 16 right-hand sides,
+// cycling over the class's panels, and keep the faster of each.  Runs once,
+// at the first solve with 16 or more right-hand sides after a setup.
+template <typename T>
+static hsw_status tune_solve_mm(hsw_ctx* ctx) {
+    if (!ctx->autotune || ctx->tuned_mm || ctx->in_lanes) return HSW_OK;
+    constexpr int REPS = 3, NR = MM_MIN_RHS;
+    hsw_status st = ensure_solve_ws<T>(ctx, ctx->lanes[0], NR);
+    if (st != HSW_OK) return st;
+    int64_t plen = 1;
+    for (const PanelDev& P : ctx->pan_h) plen = std::max<int64_t>(plen, (int64_t)(P.hi - P.lo) * P.Nx * P.Ny);
+    Cx<double>* v = nullptr;
+    const int nl = 2 * (ctx->maxdepth + 1);
+    std::vector<hipEvent_t> ev(2 * nl, nullptr);
+    auto cleanup = [&] {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (v) (void)hipFree(v);
+    };
+#define TCHK(expr)                                                         \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) {                                            \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);  \
+            cleanup();                                                     \
+            return HSW_E_DEVICE;                                           \
+        }                                                                  \
+    } while (0)
+    TCHK(hipMalloc(&v, 16 * (size_t)plen * NR));
+    TCHK(hipMemsetAsync(v, 0, 16 * (size_t)plen * NR, ctx->st));
+    for (hipEvent_t& e : ev) TCHK(hipEventCreate(&e));
+    for (size_t ci = 0; ci < ctx->classes.size(); ++ci) {
+        const PanelClass& c = ctx->classes[ci];
+        std::vector<int> panels;
+        for (size_t g = 0; g < ctx->pan_h.size(); ++g)
+            if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
+        const int D = c.maxdepth;
+        std::vector<std::array<float, 2>> tf(D + 1, {1e30f, 1e30f}), tb(D + 1, {1e30f, 1e30f});
+        int run = 0;
+        for (int rep = 0; rep < REPS; ++rep)
+            for (int k = 0; k < 2; ++k, ++run) {
+                const int gp = panels[run % panels.size()];
+                const PanelDev& P = ctx->pan_h[gp];
+                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(), k, k);
+                TCHK(hipGetLastError());
+                TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
+                for (int l = 0; l < 2 * (D + 1); ++l) {
+                    float ms = 0;
+                    TCHK(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
+                    if (l <= D) {
+                        float& t = tf[D - l][k];
+                        t = std::min(t, ms);
+                    } else {
+                        float& t = tb[l - (D + 1)][k];
+                        t = std::min(t, ms);
+                    }
+                }
+            }
+        for (int d = 0; d <= D; ++d) {
+            SolveLevel& sl = ctx->slevels[ci][d];
+            sl.mm_f = tf[d][1] < tf[d][0] ? 1 : 0;
+            sl.mm_b = tb[d][1] < tb[d][0] ? 1 : 0;
+        }
+    }
+#undef TCHK
+    cleanup();
+    ctx->tuned_mm = true;
+    return HSW_OK;
 }
 
 // z := M^{-1} r (Alg. 1.5), r may equal z.

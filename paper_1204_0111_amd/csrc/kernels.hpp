@@ -58,13 +58,15 @@ template <typename T>
 void launch_fwd(const PassArgs<T>& A, int nwork, int rb, int smax, int nmax, hipStream_t st);
 template <typename T>
 void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t st);
+// rt: row tiles of 16 per workgroup, 4 (items of 64 rows) or 1 (items of 16)
 template <typename T>
-void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st);
 // the panel's right-hand side into h2, in elimination order (matrix-core passes)
 template <typename T>
 void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st);
+// ct: column tiles of 16 per workgroup, 4 (items of 64 columns) or 1 (items of 16)
 template <typename T>
-void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st);
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st);
 template <typename T>
 int solve_rhs_chunk(int nrhs, int nmax);
 // triangular passes with the kept factors (fwd: forward pass, else backward),

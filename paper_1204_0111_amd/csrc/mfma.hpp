@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace hsw {
 
 typedef float mf4 __attribute__((ext_vector_type(4)));
@@ -28,5 +30,31 @@ __device__ inline md4 mfma4(double a, double b, md4 c) {
 template <typename T> __device__ inline int mfma_out_row(int lk, int r);
 template <> __device__ inline int mfma_out_row<float>(int lk, int r) { return 4 * lk + r; }
 template <> __device__ inline int mfma_out_row<double>(int lk, int r) { return lk + 4 * r; }
+
+// Buffer loads through a resource descriptor of `bytes` bytes at p: a load
+// whose offset lies past the end (offsets are unsigned, so a negative one
+// does too) returns zeros instead of touching memory.  Dword 3 selects the
+// 32-bit data format that untyped loads need on this architecture.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+__device__ inline BufRsrc buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> struct BufCx;
+template <> struct BufCx<float> {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    __device__ static inline void load(BufRsrc r, uint32_t off, float& re, float& im) {
+        const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+        re = v.x;
+        im = v.y;
+    }
+};
+template <> struct BufCx<double> {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    __device__ static inline void load(BufRsrc r, uint32_t off, double& re, double& im) {
+        const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+        re = v.x;
+        im = v.y;
+    }
+};
 
 }  // namespace hsw

@@ -39,10 +39,16 @@ constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, 
                                                 {64, 256}, {2, 128}, {4, 128}};
 // Groups of at least this many right-hand sides use the matrix-core passes,
 // 16 right-hand sides per group: forward 64 rows per workgroup in complex64
-// (shape 0), 16 in complex128 (shape 1, fewer registers); backward 16
-// columns (shape 4).
+// (shape 0), 16 in complex128 (shape 1, fewer registers) and in complex64
+// launches that would have fewer than MM_NARROW_BELOW workgroups of 64 rows;
+// backward 64 columns (shape 6) in launches of at least MM_TILES4_FROM
+// workgroups of 64 columns, else 16 columns (shape 4).
 constexpr int MM_MIN_RHS = 16;
-constexpr int MM_BWD_SHAPE = 4;
+constexpr int MM_BWD_SHAPE = 4, MM_BWD_SHAPE64 = 6;
+constexpr int MM_NARROW_BELOW = 256, MM_TILES4_FROM = 512;
+static_assert(FWD_SHAPES[0].block == 64 && FWD_SHAPES[1].block == 16 && BWD_SHAPES[MM_BWD_SHAPE].block == 16 &&
+                  BWD_SHAPES[MM_BWD_SHAPE64].block == 64,
+              "the matrix-core passes take items of 64 or 16 rows (forward) and 16 or 64 columns (backward)");
 template <typename T> struct MmFwdTiles { static constexpr int value = sizeof(T) == 4 ? 4 : 1; };
 template <typename T> constexpr int mm_fwd_shape() { return MmFwdTiles<T>::value == 4 ? 0 : 1; }
 constexpr int SOLVE_SMALL_BLOCK_N = 512;

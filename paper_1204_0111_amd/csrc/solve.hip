@@ -479,66 +479,76 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // right-hand side on its pivots
     const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
     const Cx<T>* h2f = A.h2 + grp * A.gs_h2 + (int64_t)it.start * 16;
-    const Cx<T>* g = A.G + it.loff;
+    constexpr uint32_t ES = sizeof(Cx<T>);
+    // Operand descriptors cut at the contraction's end kend: G's first kend
+    // columns and the first kend entries of each part of v_S.  Loads past
+    // them read zeros, so every chunk issues the same loads (the next
+    // chunk's stay in flight during this one's products) and needs no bounds
+    // test; rows past n give product rows that are never stored.
+    const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)kend * n * ES);
+    const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
+    const BufRsrc r0 = buf_rsrc(c2f, (uint32_t)kend * 16 * ES);
+    const BufRsrc r1 = buf_rsrc(c2f + (int64_t)n * 16, (uint32_t)kend * 16 * ES);
     // lane operands: A(row, k) = G(blk + 16 t + li, c + 4 q + lk) and
     // B(k, rhs) = v_S(c + 4 q + lk, li)
-    Cx<T> ga[RT][4], gn[RT][4], va[4], vn[4], ca[4], cn[4], da[4], dn[4];
-    auto load = [&](int c, Cx<T>(&gx)[RT][4], Cx<T>(&vx)[4], Cx<T>(&cx0)[4], Cx<T>(&cx1)[4]) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = it.blk + 16 * t + li, k = c + 4 * q + lk;
-                gx[t][q] = (row < n && k < kend) ? g[(int64_t)k * n + row] : cx<T>(0, 0);
-            }
+    T gre[RT][4], gim[RT][4];
+    T vre[3][4], vim[3][4];
+    auto load = [&](int c, T(&gr)[RT][4], T(&gi)[RT][4], T(&br)[3][4], T(&bi)[3][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = c + 4 * q + lk;
-            const bool ok = k < kend;
-            vx[q] = ok ? h2f[(int64_t)k * 16 + li] : cx<T>(0, 0);
-            cx0[q] = ok ? c2f[(int64_t)k * 16 + li] : cx<T>(0, 0);
-            cx1[q] = ok ? c2f[(int64_t)(n + k) * 16 + li] : cx<T>(0, 0);
+            const uint32_t col = (uint32_t)(c + 4 * q + lk);
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                BufCx<T>::load(rg, (col * n + it.blk + 16 * t + li) * ES, gr[t][q], gi[t][q]);
+            const uint32_t vo = (col * 16 + li) * ES;
+            BufCx<T>::load(rh, vo, br[0][q], bi[0][q]);
+            BufCx<T>::load(r0, vo, br[1][q], bi[1][q]);
+            BufCx<T>::load(r1, vo, br[2][q], bi[2][q]);
         }
     };
-    V4 are[RT], aim[RT];
+    // accumulators: with one row tile the real and imaginary parts each take
+    // two (products of the real and of the imaginary part of G), so that four
+    // independent chains share the matrix core instead of two
+    constexpr int SPLIT = RT == 1 ? 2 : 1;
+    V4 are[RT][SPLIT], aim[RT][SPLIT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        are[t] = V4{0, 0, 0, 0};
-        aim[t] = V4{0, 0, 0, 0};
-    }
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int h = 0; h < SPLIT; ++h) {
+            are[t][h] = V4{0, 0, 0, 0};
+            aim[t][h] = V4{0, 0, 0, 0};
+        }
     // chunks from the one holding the first live pivot (entries before it are zeros)
     const int kb = (leaf_first_live(A, it) / KC) * KC;
     const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
-    int ch = wave;
-    if (ch < nch) load(kb + ch * KC, ga, va, ca, da);
-    for (; ch < nch; ch += NW) {
-        const bool more = ch + NW < nch;
-        if (more) load(kb + (ch + NW) * KC, gn, vn, cn, dn);
+    auto products = [&](const T(&gr)[RT][4], const T(&gi)[RT][4], const T(&vr)[3][4], const T(&vi)[3][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const Cx<T> b = va[q] + ca[q] + da[q];
+            const T br = vr[0][q] + vr[1][q] + vr[2][q], bi = vi[0][q] + vi[1][q] + vi[2][q];
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                are[t] = mfma4(ga[t][q].re, b.re, are[t]);
-                aim[t] = mfma4(ga[t][q].re, b.im, aim[t]);
+                are[t][0] = mfma4(gr[t][q], br, are[t][0]);
+                aim[t][0] = mfma4(gr[t][q], bi, aim[t][0]);
             }
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                are[t] = mfma4(-ga[t][q].im, b.im, are[t]);
-                aim[t] = mfma4(ga[t][q].im, b.re, aim[t]);
+                are[t][SPLIT - 1] = mfma4(-gi[t][q], bi, are[t][SPLIT - 1]);
+                aim[t][SPLIT - 1] = mfma4(gi[t][q], br, aim[t][SPLIT - 1]);
             }
         }
-        if (more) {
+    };
+    // one chunk at a time per wave: the loads of the waves sharing a SIMD
+    // overlap each other's products (a few waves per SIMD at this register
+    // count); a load past the contraction's end reads zeros
+    for (int ch = wave; ch < nch; ch += NW) {
+        load(kb + ch * KC, gre, gim, vre, vim);
+        products(gre, gim, vre, vim);
+    }
+    if (SPLIT == 2) {
 #pragma unroll
-            for (int t = 0; t < RT; ++t)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) ga[t][q] = gn[t][q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                va[q] = vn[q];
-                ca[q] = cn[q];
-                da[q] = dn[q];
-            }
+        for (int t = 0; t < RT; ++t) {
+            are[t][0] += are[t][SPLIT - 1];
+            aim[t][0] += aim[t][SPLIT - 1];
         }
     }
     // sum the waves' partial blocks in LDS, one wave at a time
@@ -550,11 +560,11 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * t + mfma_out_row<T>(lk, r);
                     if (w == 0) {
-                        Yre[row][li] = are[t][r];
-                        Yim[row][li] = aim[t][r];
+                        Yre[row][li] = are[t][0][r];
+                        Yim[row][li] = aim[t][0][r];
                     } else {
-                        Yre[row][li] += are[t][r];
-                        Yim[row][li] += aim[t][r];
+                        Yre[row][li] += are[t][0][r];
+                        Yim[row][li] += aim[t][0][r];
                     }
                 }
         }
@@ -580,141 +590,167 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     }
 }
 
-// NW waves split the rows of the contraction by chunks; the wide form serves
-// launches with few workgroups, as for k_fwd_mm.  G^T is read by columns, so
-// each wave stages its G chunk through LDS; [x_S; -x_U] comes straight from
-// the [entry][16] blocks.
-template <typename T, int NW>
+// CT column tiles of 16 per workgroup; NW waves split the rows of the
+// contraction by chunks (the wide form, CT = 1 and more waves, serves
+// launches with few workgroups).  The contraction index of each 16-row chunk
+// is relabelled so that lane (li, lk) of the four products m = 0..3 holds
+// rows i0 + 4 lk + m: a lane then reads four consecutive rows of one column
+// of G in one access, and sixteen lanes read one 128-byte run of [x_S; -x_U],
+// so both operands come straight from memory, with no LDS staging.
+template <typename T, int CT, int NW>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    const SolveItem it = A.items[blockIdx.x];  // items of 16 columns
-    if (leaf_aux_block(it, A.ga, it.blk, 16)) return;
+    const SolveItem it = A.items[blockIdx.x];  // items of 16 CT columns
+    if (leaf_aux_block(it, A.ga, it.blk, 16 * CT)) return;
     const int n = it.n, s = it.s;
     const int grp = blockIdx.y;
     const int64_t rhs0 = (int64_t)grp * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int c0 = it.blk;
-    __shared__ T Gre[NW][KC][17], Gim[NW][KC][17];  // per wave: G chunk [row][column]
-    __shared__ T Yre[16][17], Yim[16][17];          // the waves' partial blocks, summed [column][rhs]
+    __shared__ T Yre[16 * CT][17], Yim[16 * CT][17];  // the waves' partial blocks, summed [column][rhs]
     Cx<T>* xu = A.xu + grp * A.gs_u;
     const Cx<T>* xm = A.xmid + grp * A.gs_x + (int64_t)it.start * 16;
     const Cx<T>* xuf = xu + (int64_t)it.xu * 16;
-    // the first column block hands the update-set values on to the children
-    if (c0 == 0 && (it.cxu0 >= 0 || it.cxu1 >= 0)) {
-        for (int idx = tid; idx < (n - s) * 16; idx += 64 * NW) {
-            const int i = s + (idx >> 4), r = idx & 15;
-            const Cx<T> xv = xuf[(int64_t)(i - s) * 16 + r];
-            if (it.cxu0 >= 0) {
-                const int p0 = A.cmap[it.moff + i];
-                if (p0 >= 0) xu[(int64_t)(it.cxu0 + p0) * 16 + r] = xv;
+    // The update-set values go on to the children.  The front's column blocks
+    // share its u rows, sixteen threads per row (one per right-hand side),
+    // and each thread issues the loads of four rows before their stores, so
+    // the map lookups do not form one long chain of memory round trips.
+    if (it.cxu0 >= 0 || it.cxu1 >= 0) {
+        const int u = n - s;
+        const int nb = (s + 16 * CT - 1) / (16 * CT), b = c0 / (16 * CT);
+        const int per = (u + nb - 1) / nb;
+        const int i_lo = s + b * per, i_hi = min(n, i_lo + per);
+        constexpr int ROWS = 4 * NW;  // rows per pass of the workgroup
+        const int r = tid & 15;
+        for (int i0 = i_lo + (tid >> 4); i0 < i_hi; i0 += 4 * ROWS) {
+            Cx<T> xv[4];
+            int p0[4], p1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * ROWS;
+                const bool ok = i < i_hi;
+                p0[k] = ok && it.cxu0 >= 0 ? A.cmap[it.moff + i] : -1;
+                p1[k] = ok && it.cxu1 >= 0 ? A.cmap[it.moff + n + i] : -1;
+                xv[k] = ok ? xuf[(int64_t)(i - s) * 16 + r] : cx<T>(0, 0);
             }
-            if (it.cxu1 >= 0) {
-                const int p1 = A.cmap[it.moff + n + i];
-                if (p1 >= 0) xu[(int64_t)(it.cxu1 + p1) * 16 + r] = xv;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (p0[k] >= 0) xu[(int64_t)(it.cxu0 + p0[k]) * 16 + r] = xv[k];
+                if (p1[k] >= 0) xu[(int64_t)(it.cxu1 + p1[k]) * 16 + r] = xv[k];
             }
         }
     }
-    const Cx<T>* gb = A.G + it.loff;
-    auto gget = [&](int i, int j) -> Cx<T> { return (i < n && j < s) ? gb[(int64_t)j * n + i] : cx<T>(0, 0); };
-    // B(k, rhs) = [x_S; -x_U](i0 + 4 q + lk, li); the sign is applied at use
-    auto rget = [&](int i) -> Cx<T> {
-        if (i >= n) return cx<T>(0, 0);
-        const Cx<T>* p = i < s ? xm + (int64_t)i * 16 : xuf + (int64_t)(i - s) * 16;
-        return p[li];
-    };
-    Cx<T> gv[4], gn[4], rv[4], rn[4];
-    auto load = [&](int i0, Cx<T>(&gx)[4], Cx<T>(&rx)[4]) {
+    // Operand descriptors cut at the front's ends: G's s columns, x_S's s
+    // entries and x_U's u entries.  Loads past them read zeros, so no chunk
+    // tests bounds: [x_S; -x_U](i) is the x_S load minus the x_U load (one of
+    // them reads past its end, the x_U offset of a pivot row being
+    // negative), zero past row n; columns past s give results never stored.
+    constexpr uint32_t ES = sizeof(Cx<T>);
+    const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)s * n * ES);
+    const BufRsrc rs = buf_rsrc(xm, (uint32_t)s * 16 * ES);
+    const BufRsrc ru = buf_rsrc(xuf, (uint32_t)(n - s) * 16 * ES);
+    T gre[CT][4], gim[CT][4], sre[4], sim[4], ure[4], uim[4];
+    // with one column tile, four accumulator chains instead of two (as in k_fwd_mm)
+    constexpr int SPLIT = CT == 1 ? 2 : 1;
+    V4 are[CT][SPLIT], aim[CT][SPLIT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = lane + 64 * j;
-            gx[j] = gget(i0 + (e & 15), c0 + (e >> 4));  // 16 consecutive rows of a column
-            rx[j] = rget(i0 + 4 * j + lk);
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int h = 0; h < SPLIT; ++h) {
+            are[t][h] = V4{0, 0, 0, 0};
+            aim[t][h] = V4{0, 0, 0, 0};
         }
-    };
-    V4 are = V4{0, 0, 0, 0}, aim = V4{0, 0, 0, 0};
     const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
-    int ch = wave;
-    if (ch < nch) load(c0 + ch * KC, gv, rv);
-    for (; ch < nch; ch += NW) {
-        const bool more = ch + NW < nch;
-        const int i0 = c0 + ch * KC;
+    for (int ch = wave; ch < nch; ch += NW) {
+        const int i0 = c0 + ch * KC + 4 * lk;  // this lane's four rows i0 .. i0 + 3
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = lane + 64 * j;
-            Gre[wave][e & 15][e >> 4] = gv[j].re;
-            Gim[wave][e & 15][e >> 4] = gv[j].im;
+        for (int t = 0; t < CT; ++t) {
+            const uint32_t off = ((uint32_t)(c0 + 16 * t + li) * n + (uint32_t)i0) * ES;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) BufCx<T>::load(rg, off + m * ES, gre[t][m], gim[t][m]);
         }
-        wave_lds_sync();
-        if (more) load(c0 + (ch + NW) * KC, gn, rn);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int kk = 4 * q + lk;
-            const T ar = Gre[wave][kk][li], ai = Gim[wave][kk][li];
-            const Cx<T> b = i0 + kk < s ? rv[q] : -rv[q];
-            are = mfma4(ar, b.re, are);
-            aim = mfma4(ar, b.im, aim);
-            are = mfma4(-ai, b.im, are);
-            aim = mfma4(ai, b.re, aim);
+        for (int m = 0; m < 4; ++m) {
+            BufCx<T>::load(rs, (uint32_t)((i0 + m) * 16 + li) * ES, sre[m], sim[m]);
+            BufCx<T>::load(ru, (uint32_t)((i0 + m - s) * 16 + li) * ES, ure[m], uim[m]);
         }
-        wave_lds_sync();
-        if (more) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                gv[j] = gn[j];
-                rv[j] = rn[j];
+        for (int m = 0; m < 4; ++m) {
+            const T br = sre[m] - ure[m], bi = sim[m] - uim[m];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                are[t][0] = mfma4(gre[t][m], br, are[t][0]);
+                aim[t][0] = mfma4(gre[t][m], bi, aim[t][0]);
             }
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                are[t][SPLIT - 1] = mfma4(-gim[t][m], bi, are[t][SPLIT - 1]);
+                aim[t][SPLIT - 1] = mfma4(gim[t][m], br, aim[t][SPLIT - 1]);
+            }
+        }
+    }
+    if (SPLIT == 2) {
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            are[t][0] += are[t][SPLIT - 1];
+            aim[t][0] += aim[t][SPLIT - 1];
         }
     }
     // sum the waves' partial blocks in LDS, one wave at a time
     for (int w = 0; w < NW; ++w) {
         if (wave == w) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int col = mfma_out_row<T>(lk, r);
-                if (w == 0) {
-                    Yre[col][li] = are[r];
-                    Yim[col][li] = aim[r];
-                } else {
-                    Yre[col][li] += are[r];
-                    Yim[col][li] += aim[r];
+            for (int t = 0; t < CT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = 16 * t + mfma_out_row<T>(lk, r);
+                    if (w == 0) {
+                        Yre[col][li] = are[t][0][r];
+                        Yim[col][li] = aim[t][0][r];
+                    } else {
+                        Yre[col][li] += are[t][0][r];
+                        Yim[col][li] += aim[t][0][r];
+                    }
                 }
-            }
         }
         __syncthreads();
     }
     if (tid >= 256) return;
-    // children's update-set values: a column's 16 right-hand sides are one block
-    {
-        const int jl = tid >> 4, r = tid & 15, j = c0 + jl;
-        if (j < s && rhs0 + r < A.nrhs) {
-            const Cx<T> x = cx<T>(Yre[jl][r], Yim[jl][r]);
-            if (it.cxu0 >= 0) {
-                const int o0 = A.cmap[it.moff + j];
-                if (o0 >= 0) xu[(int64_t)(it.cxu0 + o0) * 16 + r] = x;
-            }
-            if (it.cxu1 >= 0) {
-                const int o1 = A.cmap[it.moff + n + j];
-                if (o1 >= 0) xu[(int64_t)(it.cxu1 + o1) * 16 + r] = x;
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        // children's update-set values: a column's 16 right-hand sides are one block
+        {
+            const int jl = 16 * t + (tid >> 4), r = tid & 15, j = c0 + jl;
+            if (j < s && rhs0 + r < A.nrhs) {
+                const Cx<T> x = cx<T>(Yre[jl][r], Yim[jl][r]);
+                if (it.cxu0 >= 0) {
+                    const int o0 = A.cmap[it.moff + j];
+                    if (o0 >= 0) xu[(int64_t)(it.cxu0 + o0) * 16 + r] = x;
+                }
+                if (it.cxu1 >= 0) {
+                    const int o1 = A.cmap[it.moff + n + j];
+                    if (o1 >= 0) xu[(int64_t)(it.cxu1 + o1) * 16 + r] = x;
+                }
             }
         }
-    }
-    // the padded grid: consecutive threads on consecutive pivots of one right-hand side
-    const int jl = tid & 15, j = c0 + jl;
-    const int64_t orr = rhs0 + (tid >> 4);
-    if (j >= s || orr >= A.nrhs) return;
-    const Cx<T> x = cx<T>(Yre[jl][tid >> 4], Yim[jl][tid >> 4]);
-    const int b = pivot_box(it, A.Nx, A.NxNy, j);
-    const int q = b / A.NxNy, lat = b - q * A.NxNy;
-    if (q < A.ga) return;
-    Cx<double>* up = A.dst + orr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
-    const Cx<double> xd = ccast<double>(x);
-    if (A.mode == 0) {
-        *up = xd;
-        if (A.couple && q == A.nz - 1) up[A.NxNy] = up[A.NxNy] - plane_coupling(A, lat) * xd;
-    } else {
-        *up = *up - xd;
+        // the padded grid: consecutive threads on consecutive pivots of one right-hand side
+        const int jl = 16 * t + (tid & 15), j = c0 + jl;
+        const int64_t orr = rhs0 + (tid >> 4);
+        if (j >= s || orr >= A.nrhs) continue;
+        const Cx<T> x = cx<T>(Yre[jl][tid >> 4], Yim[jl][tid >> 4]);
+        const int b = pivot_box(it, A.Nx, A.NxNy, j);
+        const int q = b / A.NxNy, lat = b - q * A.NxNy;
+        if (q < A.ga) continue;
+        Cx<double>* up = A.dst + orr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
+        const Cx<double> xd = ccast<double>(x);
+        if (A.mode == 0) {
+            *up = xd;
+            if (A.couple && q == A.nz - 1) up[A.NxNy] = up[A.NxNy] - plane_coupling(A, lat) * xd;
+        } else {
+            *up = *up - xd;
+        }
     }
 }
 
@@ -1068,33 +1104,43 @@ void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st) {
     HSW_LAUNCH(k_rhs_scatter<T>, grid, dim3(256), 0, st, A);
 }
 template <typename T>
-void launch_fwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
     constexpr int W = MmWide<T>::fwd;
-    if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
-        HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value, W>), grid, dim3(64 * W), 0, st, A);
-    else
-        HSW_LAUNCH((k_fwd_mm<T, MmFwdTiles<T>::value, 4>), grid, dim3(256), 0, st, A);
+    const bool wide = (int)(grid.x * grid.y) < MM_WIDE_BELOW;
+    if (rt == 4) {
+        if (wide)
+            HSW_LAUNCH((k_fwd_mm<T, 4, W>), grid, dim3(64 * W), 0, st, A);
+        else
+            HSW_LAUNCH((k_fwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A);
+    } else {
+        if (wide)
+            HSW_LAUNCH((k_fwd_mm<T, 1, W>), grid, dim3(64 * W), 0, st, A);
+        else
+            HSW_LAUNCH((k_fwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A);
+    }
 }
 template <typename T>
-void launch_bwd_mm(const PassArgs<T>& A, int nwork, hipStream_t st) {
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
     constexpr int W = MmWide<T>::bwd;
-    if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
-        HSW_LAUNCH((k_bwd_mm<T, W>), grid, dim3(64 * W), 0, st, A);
+    if (ct == 4)
+        HSW_LAUNCH((k_bwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A);
+    else if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
+        HSW_LAUNCH((k_bwd_mm<T, 1, W>), grid, dim3(64 * W), 0, st, A);
     else
-        HSW_LAUNCH((k_bwd_mm<T, 4>), grid, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_bwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A);
 }
 
 #define HSW_INST(T)                                                                          \
     template void launch_tri<T>(const PassArgs<T>&, int, int, bool, hipStream_t);           \
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
-    template void launch_fwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
+    template void launch_fwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
     template void launch_rhs_scatter<T>(const PassArgs<T>&, hipStream_t);                    \
-    template void launch_bwd_mm<T>(const PassArgs<T>&, int, hipStream_t);                   \
+    template void launch_bwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
     template int solve_rhs_chunk<T>(int, int);
 HSW_INST(float)
 HSW_INST(double)
