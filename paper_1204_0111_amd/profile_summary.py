@@ -1,6 +1,7 @@
 """Summarise rocprofv3 CSV output into the short text files kept in profiles/.
 
-    python -m paper_1204_0111_amd.profile_summary stats <kernel_stats.csv> <out.txt> "<command>"
+    python -m paper_1204_0111_amd.profile_summary stats <kernel_stats.csv> <out.txt> "<command>" \
+        [<kernel_trace.csv>]
     python -m paper_1204_0111_amd.profile_summary pmc <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <kernel symbol> <workload> <out.txt> "<fetch command>" \
         "<write command>"
@@ -20,7 +21,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = {"k_fwd": "solve.hip", "k_bwd": "solve.hip", "k_trailing": "factor.hip",
+SRC = {"k_fwd": "solve.hip", "k_bwd": "solve.hip", "k_fwd_mm": "solve.hip", "k_bwd_mm": "solve.hip",
+       "k_rhs_scatter": "solve.hip", "k_trailing": "factor.hip",
        "k_update": "factor.hip", "k_inverse": "factor.hip", "k_panel_trsm": "factor.hip", "k_ldlt_diag": "factor.hip",
        "k_assemble": "factor.hip", "k_matvec": "krylov.hip"}
 COPY_BYTES = 512 * (1 << 20)
@@ -31,7 +33,26 @@ def src_hash(sym):
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def stats(csv_path, out, cmd):
+FAMILIES = ("hsw::k_fwd", "hsw::k_bwd", "hsw::k_fwd_mm", "hsw::k_bwd_mm", "hsw::k_rhs_scatter",
+            "hsw::k_update", "hsw::k_inverse", "hsw::k_ldlt_diag", "hsw::k_panel_trsm", "hsw::k_assemble",
+            "hsw::k_matvec")
+
+
+def last_step_families(trace_path):
+    """Per kernel (all template instances together) over the last step of a
+    kernel trace: the dispatches from the last velocity check on, which is
+    the step a benchmark times after its warm-up (and autotuning)."""
+    rows = sorted(csv.DictReader(open(trace_path)), key=lambda r: int(r["Start_Timestamp"]))
+    last = max(i for i, r in enumerate(rows) if "k_check_velocity" in r["Kernel_Name"])
+    fam = {}
+    for r in rows[last:]:
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").split("<")[0]
+        c, t = fam.get(k, (0, 0.0))
+        fam[k] = (c + 1, t + int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return fam
+
+
+def stats(csv_path, out, cmd, trace_path=None):
     rows = list(csv.DictReader(open(csv_path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     with open(out, "w") as f:
@@ -51,11 +72,18 @@ def stats(csv_path, out, cmd):
             k = r["Name"].split("(")[0].replace("void ", "").split("<")[0]
             c, t = fam.get(k, (0, 0.0))
             fam[k] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
-        for k in ("hsw::k_fwd", "hsw::k_bwd", "hsw::k_update", "hsw::k_inverse", "hsw::k_ldlt_diag",
-                  "hsw::k_panel_trsm", "hsw::k_assemble"):
+        for k in FAMILIES:
             if k in fam:
                 c, t = fam[k]
                 f.write("%-34s %7d %11.3f %10.3f\n" % (k, c, t / 1e6, t / c / 1e3))
+        if trace_path:
+            # the step the benchmark times: no warm-up, no autotuner trials
+            f.write("# last step only (kernel trace), all block shapes together\n")
+            last = last_step_families(trace_path)
+            for k in FAMILIES:
+                if k in last:
+                    c, t = last[k]
+                    f.write("%-34s %7d %11.3f %10.3f\n" % (k, c, t / 1e6, t / c / 1e3))
 
 
 def per_kernel(path):
@@ -154,6 +182,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "sq":
         sq(*sys.argv[2:6])
     elif sys.argv[1] == "stats":
-        stats(*sys.argv[2:5])
+        stats(*sys.argv[2:6])
     else:
         pmc(*sys.argv[2:9])

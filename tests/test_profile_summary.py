@@ -53,3 +53,20 @@ def test_sq_divides_the_active_cycles_by_the_xcds(tmp_path):
     ps.sq(str(c), "toy", str(out), "cmd")
     line = [l for l in open(out) if l.startswith("k_update")][0].split()
     assert line[2] == "50.0%" and line[3] == "0.250"
+
+
+def test_last_step_families_start_at_the_last_velocity_check(tmp_path):
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = [("void hsw::k_bwd_mm<float, 1, 4>(x)", 10, 20),      # an earlier step
+            ("hsw::k_check_velocity(x)", 30, 31),
+            ("void hsw::k_bwd_mm<float, 1, 16>(x)", 40, 50),
+            ("void hsw::k_bwd_mm<float, 4, 4>(x)", 60, 90),
+            ("void hsw::k_fwd_mm<float, 4, 4>(x)", 100, 105)]
+    p = tmp_path / "t.csv"
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+    fam = ps.last_step_families(str(p))
+    assert fam["hsw::k_bwd_mm"] == (2, 40) and fam["hsw::k_fwd_mm"] == (1, 5)
