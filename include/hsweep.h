@@ -128,6 +128,30 @@ hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, hsw_c128* z,
                      int32_t nrhs, int64_t ld);
 
 /*
+ * hsw_apply without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops).  Same
+ * arguments and result as hsw_apply, except:
+ *   - nrhs is at most 15 (the single-right-hand-side passes), and the
+ *     panel-solve workspace, (max auxiliary size + max update size + max
+ *     child-slot size) x nrhs complex entries of the working precision,
+ *     must fit the library's 128 MiB device scratch: HSW_E_INVAL otherwise,
+ *     with the sizes in hsw_last_error;
+ *   - the workspace is a static device array that every call on a device
+ *     shares (each device holds its own copy from its first use until the
+ *     process ends): calls that overlap on one device race, so serialize
+ *     them (one stream, or events between streams);
+ *   - the solve block shapes are those already tuned by earlier
+ *     hsw_apply / hsw_solve calls, or the fixed rule: this call times
+ *     nothing and captures no graph;
+ *   - the context's device must be the current device (HSW_E_INVAL).
+ * It calls no hipMalloc / hipFree.  Nothing in the scratch needs to start at
+ * zero: every entry a pass reads was written earlier in the same call, or is
+ * masked by the extend-add maps.
+ */
+hsw_status hsw_apply_noalloc(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, hsw_c128* z,
+                             int32_t nrhs, int64_t ld);
+
+/*
  * y = T_i v: the approximate inverse Schur complement of panel i alone
  * (Sec. 1.1, Alg. 1.3: zero-extend over the artificial PML, solve with H_i,
  * extract).  v and y are device pointers to nrhs panel vectors (the panel's

@@ -1670,6 +1670,84 @@ extern "C" hsw_status hsw_apply(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, h
                : sweep_any<float>(ctx, ctx->lanes[0], prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld);
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free sweep: hsw_apply with the panel-solve workspace in a
+// file-scope device array instead of memory the library allocates.  Each
+// device the library runs on holds its own copy of the array until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch (looked up once per device).
+hipError_t scratch_address(int dev, void** out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+template <typename T>
+static hsw_status apply_noalloc_impl(hsw_ctx* ctx, int prob, const Cx<double>* r, Cx<double>* z, int nrhs,
+                                     int64_t ld, void* base) {
+    // the lane-0 workspace layout (x_mid, update-set values, child slots) in the scratch
+    const size_t e = sizeof(Cx<T>) * (size_t)nrhs;
+    const size_t bx = (e * (size_t)ctx->max_naux + 255) / 256 * 256;
+    const size_t bu = (e * (size_t)std::max<int64_t>(ctx->max_wsize, 1) + 255) / 256 * 256;
+    const size_t bc = e * (size_t)std::max<int64_t>(ctx->max_c2, 1);
+    if (bx + bu + bc > NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "apply_noalloc: %d right-hand sides need %.1f MB of workspace, the scratch "
+                 "holds %.1f MB", nrhs, (bx + bu + bc) / 1e6, NOALLOC_SCRATCH_BYTES / 1e6);
+        return fail(ctx, HSW_E_INVAL, buf);
+    }
+    Lane ln;
+    ln.st = ctx->st;
+    ln.d_xmid = base;
+    ln.d_xu = (unsigned char*)base + bx;
+    ln.d_c2 = (unsigned char*)base + bx + bu;
+    ln.nrhs_cap = nrhs;
+    const ProbHost& h = ctx->ph[prob];
+    HIPCHK(hipMemcpy2DAsync(z, 16 * ld, r, 16 * ld, 16 * h.Npad, nrhs, hipMemcpyDeviceToDevice, ctx->st));
+    for (int i = 0; i < h.m; ++i)
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs);
+    for (int i = h.m - 2; i >= 0; --i)
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs);
+    HIPCHK(hipGetLastError());
+    return HSW_OK;
+}
+
+extern "C" hsw_status hsw_apply_noalloc(hsw_ctx* ctx, int32_t prob, const hsw_c128* r, hsw_c128* z,
+                                        int32_t nrhs, int64_t ld) {
+    if (!ctx) return HSW_E_INVAL;
+    if (!ctx->factored) return fail(ctx, HSW_E_STATE, "apply before setup");
+    hsw_status s = check_vec_args(ctx, prob, r, z, nrhs, ld, ctx->ph[prob >= 0 && prob < (int)ctx->ph.size() ? prob : 0].Npad);
+    if (s != HSW_OK) return s;
+    if ((const void*)r == (const void*)z) return fail(ctx, HSW_E_INVAL, "r and z alias");
+    if (nrhs >= MM_MIN_RHS)
+        return fail(ctx, HSW_E_INVAL, "apply_noalloc takes at most 15 right-hand sides per call");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != ctx->device || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(ctx, HSW_E_INVAL, "apply_noalloc: make the context's device current");
+    void* base = nullptr;
+    HIPCHK(scratch_address(dev, &base));
+    return ctx->prec == HSW_C128
+               ? apply_noalloc_impl<double>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld, base)
+               : apply_noalloc_impl<float>(ctx, prob, (const Cx<double>*)r, (Cx<double>*)z, nrhs, ld, base);
+}
+
 extern "C" hsw_status hsw_panel_solve(hsw_ctx* ctx, int32_t prob, int32_t panel, const hsw_c128* v,
                                       hsw_c128* y, int32_t nrhs, int64_t ld) {
     if (!ctx) return HSW_E_INVAL;

@@ -62,6 +62,7 @@ def load_library():
         "hsw_assemble": (c_int32, [c_void_p, P(c_void_p)]),
         "hsw_setup": (c_int32, [c_void_p]),
         "hsw_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int64]),
+        "hsw_apply_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int64]),
         "hsw_panel_solve": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32,
                                       c_int64]),
         "hsw_matvec": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int64]),
@@ -188,6 +189,16 @@ class Solver:
         self._check(self.lib.hsw_apply(self.ctx, prob, c_void_p(r.data_ptr()),
                                        c_void_p(z.data_ptr()), r.shape[0], n))
         return z
+
+    def apply_noalloc(self, prob, r, out):
+        """hsw_apply_noalloc: the sweep with the library's static device
+        scratch as workspace (no allocation; at most 15 right-hand sides)."""
+        n = self.N_pad(prob)
+        r = self._cvec(r, n, "r")
+        out = self._cvec(out, n, "out")
+        self._check(self.lib.hsw_apply_noalloc(self.ctx, prob, c_void_p(r.data_ptr()),
+                                               c_void_p(out.data_ptr()), r.shape[0], n))
+        return out
 
     def matvec(self, prob, x):
         n = self.N_pad(prob)
