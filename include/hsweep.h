@@ -55,7 +55,8 @@ typedef enum {
 typedef enum {
     HSW_C128 = 0,        /* fronts, sweep and GMRES in complex FP64 */
     HSW_C64 = 1,         /* fronts and sweep in complex FP32, GMRES in FP64 */
-    HSW_C64_BF16GEMM = 2 /* as HSW_C64, Schur-update GEMM inputs rounded to bf16 */
+    HSW_C64_BF16GEMM = 2 /* as HSW_C64, the Schur-update GEMMs with complex BF16 inputs on the
+                            BF16 matrix cores, FP32 accumulation (option "bf16_mfma") */
 } hsw_precision;
 
 /* One problem: the grid, frequency and preconditioner parameters. */
@@ -311,8 +312,14 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              inverse passes at every depth and keeps the faster; 1: at
  *              every depth; 0: never.  They need the factors (keep_factors
  *              1); without them every depth runs the inverse passes.
- * Changing "keep_factors", "inverse_by_depth" or "full_inverse" requires a
- * new hsw_setup.
+ *   "bf16_mfma" (HSW_C64_BF16GEMM) 1 (default): the Schur-update GEMMs take
+ *              complex BF16 inputs (rounded to nearest even) on the BF16
+ *              matrix cores with FP32 accumulation; 0: the same rounded inputs
+ *              multiplied on the FP32 matrix cores (products of bf16 values
+ *              are exact in FP32, so the two agree to FP32 rounding of the
+ *              sums).
+ * Changing "keep_factors", "inverse_by_depth", "full_inverse" or "bf16_mfma"
+ * requires a new hsw_setup.
  * Returns HSW_E_INVAL for an unknown key or value.
  */
 hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t value);

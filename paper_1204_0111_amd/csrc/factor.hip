@@ -225,6 +225,98 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
 }
 
 // ---------------------------------------------------------------------------
+// The same 64 x 64 tile product with complex BF16 inputs on the BF16 matrix
+// cores (16 x 16 x 16 products, FP32 accumulation): the operands are rounded
+// to bf16 (nearest even) as they are staged, chunk by chunk of 16 k, in LDS
+// tiles [row][k] (k contiguous: lane l reads the four k = 4 (l/16) + 0..3 of
+// row l % 16 in one access, the bf16 instruction's operand layout).  The
+// output layout of the 16 x 16 blocks is that of the FP32 product, so
+// tile_cgemm's accumulators and the callers' epilogues serve both.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+constexpr int BK = 16, BKP = BK + 4;  // chunk of k, padded row length of the bf16 tiles
+
+__device__ inline unsigned short bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);  // inf / nan kept
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline mf4 mfma_bf16(bf4 a, bf4 b, mf4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void tile_cgemm_bf16(mf4 (&are)[2][2], mf4 (&aim)[2][2],
+                                       const unsigned short (*R)[64][BKP], const unsigned short (*C)[64][BKP]) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const int li = l & 15, lk = l >> 4;
+    bf4 cr[2], ci[2], cn[2], rr[2], ri[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        cr[q] = *reinterpret_cast<const bf4*>(&C[0][wc + 16 * q + li][4 * lk]);
+        ci[q] = *reinterpret_cast<const bf4*>(&C[1][wc + 16 * q + li][4 * lk]);
+        rr[q] = *reinterpret_cast<const bf4*>(&R[0][wr + 16 * q + li][4 * lk]);
+        ri[q] = *reinterpret_cast<const bf4*>(&R[1][wr + 16 * q + li][4 * lk]);
+        cn[q] = ci[q] ^ (bf4)(short)0x8000;  // -C_im: the sign bits flipped
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            are[bi][bj] = mfma_bf16(cr[bj], rr[bi], are[bi][bj]);
+            aim[bi][bj] = mfma_bf16(cr[bj], ri[bi], aim[bi][bj]);
+        }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            are[bi][bj] = mfma_bf16(cn[bj], ri[bi], are[bi][bj]);
+            aim[bi][bj] = mfma_bf16(ci[bj], rr[bi], aim[bi][bj]);
+        }
+}
+
+// acc += R C^T over k < K, as cgemm64_pipe (same loaders, same pipelining:
+// chunk c + 1 in flight while chunk c runs from the other LDS buffer), with
+// the operands rounded to bf16 and multiplied on the BF16 matrix cores.
+template <typename LR, typename LC>
+__device__ inline void cgemm64_pipe_bf16(mf4 (&are)[2][2], mf4 (&aim)[2][2], int K, LR ldR, LC ldC,
+                                         unsigned short (*R)[2][64][BKP], unsigned short (*C)[2][64][BKP]) {
+    constexpr int PER = BK * 64 / 256;
+    const int tid = threadIdx.x;
+    const int nch = (K + BK - 1) / BK;
+    if (nch <= 0) return;
+    Cx<float> r[PER], c[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q, a = idx & 63, kk = k0 + (idx >> 6);
+            r[q] = kk < K ? ldR(kk, a) : cx<float>(0, 0);
+            c[q] = kk < K ? ldC(kk, a) : cx<float>(0, 0);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q, a = idx & 63, m = idx >> 6;
+            R[buf][0][a][m] = bf16_bits(r[q].re);
+            R[buf][1][a][m] = bf16_bits(r[q].im);
+            C[buf][0][a][m] = bf16_bits(c[q].re);
+            C[buf][1][a][m] = bf16_bits(c[q].im);
+        }
+    };
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) fetch((ch + 1) * BK);
+        tile_cgemm_bf16(are, aim, R[buf], C[buf]);
+        if (ch + 1 < nch) put(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 16 x 16 complex tile product on the matrix cores, acc += A B over k < K
 // (K <= 16): lane l supplies A(l % 16, k) and B(k, l % 16) for k = kk + l / 16;
 // register r of lane l then holds row mfma_out_row<T>(l / 16, r), column l % 16.
@@ -682,7 +774,10 @@ __device__ inline float round_bf16(float x) {
 }
 __device__ inline double round_bf16(double x) { return x; }
 
-template <typename T>
+// bf16: 0 complex products in the working precision; 1 complex BF16 inputs
+// on the BF16 matrix cores (BF, complex64 only); 2 the same bf16-rounded
+// inputs on the FP32 matrix cores.
+template <typename T, bool BF>
 __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
                                                 const FrontInst* __restrict__ inst,
                                                 Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
@@ -714,7 +809,6 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
     }
     Cx<T>* L = Lb + f.loff;
     Cx<T>* W = Wcur + f.woff;
-    __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
     const int tid = threadIdx.x;
     const int l = tid & 63, wv = tid >> 6;
     const int li = l & 15, lk = l >> 4;
@@ -739,18 +833,31 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
-    auto rnd = [&](Cx<T> v) { return bf16 ? cx<T>(round_bf16(v.re), round_bf16(v.im)) : v; };
-    cgemm64_pipe<T, KC>(
-        are, aim, K,
-        [&](int m, int a) {
-            const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
-            return r0 + a < n ? rnd(col[r0 + a]) : cx<T>(0, 0);
-        },
-        [&](int m, int a) {
-            const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
-            return c0 + a < cend ? rnd(col[c0 + a] * col[kbeg + m]) : cx<T>(0, 0);  // L[j,m] d_m
-        },
-        Rre, Rim, Cre, Cim);
+    auto ldR = [&](int m, int a) {
+        const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
+        return r0 + a < n ? col[r0 + a] : cx<T>(0, 0);
+    };
+    auto ldC = [&](int m, int a) {
+        const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
+        return c0 + a < cend ? col[c0 + a] * col[kbeg + m] : cx<T>(0, 0);  // L[j,m] d_m
+    };
+    if constexpr (BF) {
+        // complex BF16 inputs on the BF16 matrix cores
+        __shared__ unsigned short Rb[2][2][64][BKP], Cb[2][2][64][BKP];
+        cgemm64_pipe_bf16(are, aim, K, ldR, ldC, Rb, Cb);
+    } else {
+        __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
+        if (bf16) {
+            // the same inputs rounded to bf16, multiplied on the FP32 matrix cores
+            // (products of bf16 values are exact in FP32: the reference of the path above)
+            auto rnd = [](Cx<T> v) { return cx<T>(round_bf16(v.re), round_bf16(v.im)); };
+            cgemm64_pipe<T, KC>(
+                are, aim, K, [&](int m, int a) { return rnd(ldR(m, a)); },
+                [&](int m, int a) { return rnd(ldC(m, a)); }, Rre, Rim, Cre, Cim);
+        } else {
+            cgemm64_pipe<T, KC>(are, aim, K, ldR, ldC, Rre, Rim, Cre, Cim);
+        }
+    }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -917,7 +1024,13 @@ template <typename T>
 void launch_update(const int2* work, int nwork, const FrontInst* inst, Cx<T>* Lb, Cx<T>* Wcur, int k,
                    int mode, int bf16, hipStream_t st) {
     if (nwork <= 0) return;
-    HSW_LAUNCH(k_update<T>, dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, mode, bf16);
+    if constexpr (sizeof(T) == 4) {
+        if (bf16 == 1) {
+            HSW_LAUNCH((k_update<T, true>), dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, mode, bf16);
+            return;
+        }
+    }
+    HSW_LAUNCH((k_update<T, false>), dim3(nwork), dim3(256), 0, st, work, inst, Lb, Wcur, k, mode, bf16);
 }
 template <typename T>
 void launch_inverse(const int2* work, int nwork, const FrontInst* inst, const Cx<T>* Lb, Cx<T>* Gb,

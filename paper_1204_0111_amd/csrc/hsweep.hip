@@ -200,6 +200,7 @@ struct hsw_ctx {
     bool use_graph = false;  // measured slower than stream launches for the sweep
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
+    bool bf16_mfma = true;     // HSW_C64_BF16GEMM: Schur updates on the BF16 matrix cores
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -973,6 +974,9 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->nlanes = (int)value;
     } else if (k == "block_gmres") {
         ctx->block_gmres = value != 0;
+    } else if (k == "bf16_mfma") {
+        ctx->bf16_mfma = value != 0;
+        ctx->factored = false;
     } else if (k == "inverse_by_depth") {
         const bool by = value != 0;
         if (by != ctx->inv_by_depth) {
@@ -1113,7 +1117,9 @@ static hsw_status setup_impl(hsw_ctx* ctx) {
                                ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist, ctx->d_cmap,
                                ctx->d_et, L, ws[d & 1], ws[(d + 1) & 1], st);
         });
-        const int bf16 = ctx->prec == HSW_C64_BF16GEMM;
+        // complex BF16 Schur-update inputs: on the BF16 matrix cores (1), or
+        // rounded and multiplied on the FP32 ones (2, option bf16_mfma 0)
+        const int bf16 = ctx->prec == HSW_C64_BF16GEMM ? (ctx->bf16_mfma ? 1 : 2) : 0;
         const int order = ctx->update_order;
         const bool left = order == 1;
         const bool hybrid = order == 2 || (order < 0);

@@ -440,6 +440,32 @@ def test_bf16_schur_inputs_change_factors_and_still_converge(medium):
     assert np.linalg.norm(b[0] - A @ x) / np.linalg.norm(b[0]) < 1e-5
 
 
+def test_bf16_matrix_cores_match_rounded_fp32_products(medium):
+    """The Schur updates on the BF16 matrix cores against the same bf16-rounded
+    inputs multiplied on the FP32 matrix cores (option bf16_mfma 0): products
+    of bf16 values are exact in FP32, so the two differ only by the FP32
+    rounding of the sums (a wrong operand layout would differ at O(1)), while
+    both differ from complex64 at the bf16 level."""
+    P = medium
+    r = _cuda(wl.random_complex((2, int(np.prod(hz.padded_shape(P["n"], P["gamma"])))), 17))
+    Sm = _solver(P, "c64_bf16")
+    Se = _solver(P, "c64_bf16")
+    Se.set_option("bf16_mfma", 0)
+    Se.setup()
+    S4 = _solver(P, "c64")
+    for S in (Sm, Se, S4):
+        S.set_option("autotune", 0)
+    zm = Sm.apply(0, r).cpu().numpy()
+    ze = Se.apply(0, r).cpu().numpy()
+    z4 = S4.apply(0, r).cpu().numpy()
+    d_me, d_e4 = rel(zm, ze), rel(ze, z4)
+    assert d_me <= 1e-4 and d_e4 > 100 * d_me, (d_me, d_e4)
+    for f in (0, 5, Sm.query(0, "fronts") - 1):
+        Dm = Sm.front(0, 1, f)[0]
+        De = Se.front(0, 1, f)[0]
+        assert rel(Dm, De) <= 1e-4, f
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_several_problems_in_one_context(prec):
     """Problems of different sizes share every setup launch; each matches its own oracle."""
