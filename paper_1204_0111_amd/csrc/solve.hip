@@ -539,7 +539,8 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     };
     // one chunk at a time per wave: the loads of the waves sharing a SIMD
     // overlap each other's products (a few waves per SIMD at this register
-    // count); a load past the contraction's end reads zeros
+    // count); a load past the contraction's end reads zeros.  (Two chunks in
+    // flight per wave, as in the backward pass, measured slower here.)
     for (int ch = wave; ch < nch; ch += NW) {
         load(kb + ch * KC, gre, gim, vre, vim);
         products(gre, gim, vre, vim);
@@ -663,32 +664,52 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             aim[t][h] = V4{0, 0, 0, 0};
         }
     const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
-    for (int ch = wave; ch < nch; ch += NW) {
-        const int i0 = c0 + ch * KC + 4 * lk;  // this lane's four rows i0 .. i0 + 3
+    // this lane's four rows i0 .. i0 + 3 of chunk ch
+    auto load = [&](int ch, T(&gr)[CT][4], T(&gi)[CT][4], T(&sr)[4], T(&si)[4], T(&ur)[4], T(&ui)[4]) {
+        const int i0 = c0 + ch * KC + 4 * lk;
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const uint32_t off = ((uint32_t)(c0 + 16 * t + li) * n + (uint32_t)i0) * ES;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) BufCx<T>::load(rg, off + m * ES, gre[t][m], gim[t][m]);
+            for (int m = 0; m < 4; ++m) BufCx<T>::load(rg, off + m * ES, gr[t][m], gi[t][m]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            BufCx<T>::load(rs, (uint32_t)((i0 + m) * 16 + li) * ES, sre[m], sim[m]);
-            BufCx<T>::load(ru, (uint32_t)((i0 + m - s) * 16 + li) * ES, ure[m], uim[m]);
+            BufCx<T>::load(rs, (uint32_t)((i0 + m) * 16 + li) * ES, sr[m], si[m]);
+            BufCx<T>::load(ru, (uint32_t)((i0 + m - s) * 16 + li) * ES, ur[m], ui[m]);
         }
+    };
+    auto products = [&](const T(&gr)[CT][4], const T(&gi)[CT][4], const T(&sr)[4], const T(&si)[4],
+                        const T(&ur)[4], const T(&ui)[4]) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const T br = sre[m] - ure[m], bi = sim[m] - uim[m];
+            const T br = sr[m] - ur[m], bi = si[m] - ui[m];
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-                are[t][0] = mfma4(gre[t][m], br, are[t][0]);
-                aim[t][0] = mfma4(gre[t][m], bi, aim[t][0]);
+                are[t][0] = mfma4(gr[t][m], br, are[t][0]);
+                aim[t][0] = mfma4(gr[t][m], bi, aim[t][0]);
             }
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-                are[t][SPLIT - 1] = mfma4(-gim[t][m], bi, are[t][SPLIT - 1]);
-                aim[t][SPLIT - 1] = mfma4(gim[t][m], br, aim[t][SPLIT - 1]);
+                are[t][SPLIT - 1] = mfma4(-gi[t][m], bi, are[t][SPLIT - 1]);
+                aim[t][SPLIT - 1] = mfma4(gi[t][m], br, aim[t][SPLIT - 1]);
             }
+        }
+    };
+    // with one column tile each wave issues two chunks' loads before their
+    // products (loads past the end read zeros), as in k_fwd_mm
+    if constexpr (CT == 1) {
+        T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4], ure2[4], uim2[4];
+        for (int ch = wave; ch < nch; ch += 2 * NW) {
+            load(ch, gre, gim, sre, sim, ure, uim);
+            load(ch + NW, gre2, gim2, sre2, sim2, ure2, uim2);
+            products(gre, gim, sre, sim, ure, uim);
+            products(gre2, gim2, sre2, sim2, ure2, uim2);
+        }
+    } else {
+        for (int ch = wave; ch < nch; ch += NW) {
+            load(ch, gre, gim, sre, sim, ure, uim);
+            products(gre, gim, sre, sim, ure, uim);
         }
     }
     if (SPLIT == 2) {
