@@ -277,29 +277,50 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
         if (it.cxu0 >= 0) o0 = A.cmap[it.moff + jl];
         if (it.cxu1 >= 0) o1 = A.cmap[it.moff + n + jl];
     }
-    // [x_S; -x_U] of this front; the first column block also hands the
-    // update-set values on to the children
+    // [x_S; -x_U] of this front (loads only: nothing in this loop waits on a
+    // loaded value before the next load)
     for (int i = c0 + tid; i < n; i += NT) {
-        int p0 = -1, p1 = -1;
-        if (i >= s && c0 == 0) {
-            if (it.cxu0 >= 0) p0 = A.cmap[it.moff + i];
-            if (it.cxu1 >= 0) p1 = A.cmap[it.moff + n + i];
-        }
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
             Cx<T> v = cx<T>(0, 0);
             if (r < nr) {
                 const int64_t rr = rhs0 + r;
-                if (i < s) {
-                    v = A.xmid[rr * A.naux + it.start + i];
-                } else {
-                    const Cx<T> xv = A.xu[rr * A.xuld + it.xu + i - s];
-                    if (p0 >= 0) A.xu[rr * A.xuld + it.cxu0 + p0] = xv;
-                    if (p1 >= 0) A.xu[rr * A.xuld + it.cxu1 + p1] = xv;
-                    v = -xv;
-                }
+                v = i < s ? A.xmid[rr * A.naux + it.start + i] : -A.xu[rr * A.xuld + it.xu + i - s];
             }
             rv[r * n + i] = v;
+        }
+    }
+    // The update-set values go on to the children.  The front's column
+    // blocks share its u rows, and each thread issues the loads of four rows
+    // before their stores, so the map lookups do not form one long chain of
+    // memory round trips.
+    if (it.cxu0 >= 0 || it.cxu1 >= 0) {
+        const int u = n - s;
+        const int nb = (s + CB - 1) / CB, b = c0 / CB;
+        const int per = (u + nb - 1) / nb;
+        const int i_lo = s + b * per, i_hi = min(n, i_lo + per);
+        for (int i0 = i_lo + tid; i0 < i_hi; i0 += 4 * NT) {
+            Cx<T> xv[4][RC];
+            int p0[4], p1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * NT;
+                const bool ok = i < i_hi;
+                p0[k] = ok && it.cxu0 >= 0 ? A.cmap[it.moff + i] : -1;
+                p1[k] = ok && it.cxu1 >= 0 ? A.cmap[it.moff + n + i] : -1;
+#pragma unroll
+                for (int r = 0; r < RC; ++r)
+                    xv[k][r] = ok && r < nr ? A.xu[(rhs0 + r) * A.xuld + it.xu + i - s] : cx<T>(0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int r = 0; r < RC; ++r) {
+                    if (r >= nr) break;
+                    const int64_t rr = rhs0 + r;
+                    if (p0[k] >= 0) A.xu[rr * A.xuld + it.cxu0 + p0[k]] = xv[k][r];
+                    if (p1[k] >= 0) A.xu[rr * A.xuld + it.cxu1 + p1[k]] = xv[k][r];
+                }
         }
     }
     __syncthreads();
