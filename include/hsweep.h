@@ -262,6 +262,14 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              pivots before it is factored, F_BR once at the end); 2 or -1
  *              (default) hybrid: right-looking over the pivot columns, F_BR
  *              once at the end.  The factors agree to rounding.
+ *   "mm_fwd_form", "mm_bwd_form" the form of the matrix-core passes (16 or
+ *              more right-hand sides) at every tree depth; -1 (default): the
+ *              autotuner's choice per panel class and depth.  Forward: 0
+ *              workgroups of 64 rows whose waves split the contraction, 1
+ *              workgroups of 16 rows, 2 row-split workgroups of 64 rows with
+ *              the front vector staged in LDS (depths whose largest front
+ *              needs more than 64 KB of it take form 0).  Backward: 0
+ *              workgroups of 64 columns, 1 of 16.
  *   "solve_lanes" 1..16 (default 4): hsw_solve spreads the problems of a
  *              context over this many lanes -- streams with their own
  *              workspaces, one host thread each -- so that the launch-latency

@@ -201,6 +201,10 @@ struct hsw_ctx {
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
     bool bf16_mfma = true;     // HSW_C64_BF16GEMM: Schur updates on the BF16 matrix cores
+    // matrix-core pass forms for every depth (-1: the tuned choice); forward
+    // 0 / 1: items of 64 / 16 rows, 2: row-split (where it fits); backward
+    // 0 / 1: items of 64 / 16 columns
+    int mm_fwd_form = -1, mm_bwd_form = -1;
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -1054,6 +1058,12 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             for (bool& t : ctx->tuned) t = false;  // the triangular passes come and go with the factors
             drop_graphs(ctx);
         }
+    } else if (k == "mm_fwd_form") {
+        if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1, 0, 1 or 2");
+        ctx->mm_fwd_form = (int)value;
+    } else if (k == "mm_bwd_form") {
+        if (value < -1 || value > 1) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1, 0 or 1");
+        ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
         ctx->update_order = (int)value;
@@ -1268,6 +1278,12 @@ static bool tri_available(const hsw_ctx* ctx) {
     return ctx->tri_mode != 0 && ctx->keep_factors && ctx->d_G != ctx->d_L;
 }
 
+// The row-split forward form stages up to 64 KB of LDS per workgroup.
+template <typename T>
+static bool fwd_rs_fits(int smax) {
+    return fwd_rs_lds_bytes<T>(smax) <= 65536;
+}
+
 template <typename T>
 static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx<double>* src,
                          int64_t ld, int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
@@ -1355,23 +1371,33 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         const int groups = (nrhs + 15) / 16;
         for (int d = c.maxdepth; d >= 0; --d) {
             // 64-row items, or 16-row ones (the tuned choice, else where 64-row
-            // items give few workgroups; complex128 always takes 16-row items)
+            // items give few workgroups; complex128 takes 16-row items), or
+            // the row-split form over 64-row items (tuned choice 2, where the
+            // depth's largest v_S fits in LDS)
             int fs = mm_fwd_shape<T>(), rt = MmFwdTiles<T>::value;
-            const int pick = mm_force_f >= 0 ? mm_force_f : lv[d].mm_f;
-            if (rt == 4 && (pick == 1 || (pick < 0 && lv[d].fcount[fs] * groups < MM_NARROW_BELOW))) {
+            const int pick = mm_force_f >= 0 ? mm_force_f : ctx->mm_fwd_form >= 0 ? ctx->mm_fwd_form : lv[d].mm_f;
+            const bool rs = pick == 2 && fwd_rs_fits<T>(lv[d].smax);
+            if (rs) {
+                fs = 0;
+            } else if (rt == 4 && (pick == 1 || (pick < 0 && lv[d].fcount[fs] * groups < MM_NARROW_BELOW))) {
                 fs = 1;
                 rt = 1;
             }
             A.items = ctx->d_sitems + lv[d].foff[fs];
             run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec_bytes,
-                8.0 * nrhs * lv[d].g_need(pf), [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], rt, st); });
+                8.0 * nrhs * lv[d].g_need(pf), [&] {
+                    if (rs)
+                        launch_fwd_rs<T>(A, lv[d].fcount[fs], lv[d].smax, st);
+                    else
+                        launch_fwd_mm<T>(A, lv[d].fcount[fs], rt, st);
+                });
         }
         A.mode = emode;
         for (int d = 0; d <= c.maxdepth; ++d) {
             // 64-column items (the tuned choice, else where they give enough
             // workgroups), or 16-column ones
             int bs = MM_BWD_SHAPE, ct = 1;
-            const int bpick = mm_force_b >= 0 ? mm_force_b : lv[d].mm_b;
+            const int bpick = mm_force_b >= 0 ? mm_force_b : ctx->mm_bwd_form >= 0 ? ctx->mm_bwd_form : lv[d].mm_b;
             if (bpick == 0 || (bpick < 0 && lv[d].bcount[MM_BWD_SHAPE64] * groups >= MM_TILES4_FROM)) {
                 bs = MM_BWD_SHAPE64;
                 ct = 4;
@@ -1499,10 +1525,11 @@ static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
 }
 
 // Autotuner of the matrix-core passes: for every panel class and tree depth,
-// time items of 64 and of 16 rows (forward) and of 64 and of 16 columns
-// (backward) inside whole panel solves of one group of 16 right-hand sides,
-// cycling over the class's panels, and keep the faster of each.  Runs once,
-// at the first solve with 16 or more right-hand sides after a setup.
+// time items of 64 and of 16 rows and the row-split form (forward) and items
+// of 64 and of 16 columns (backward) inside whole panel solves of one group of
+// 16 right-hand sides, cycling over the class's panels, and keep the fastest
+// of each.  Runs once, at the first solve with 16 or more right-hand sides
+// after a setup.
 template <typename T>
 static hsw_status tune_solve_mm(hsw_ctx* ctx) {
     if (!ctx->autotune || ctx->tuned_mm || ctx->in_lanes) return HSW_OK;
@@ -1537,13 +1564,16 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        std::vector<std::array<float, 2>> tf(D + 1, {1e30f, 1e30f}), tb(D + 1, {1e30f, 1e30f});
+        std::vector<std::array<float, 3>> tf(D + 1, {1e30f, 1e30f, 1e30f}), tb(D + 1, {1e30f, 1e30f, 1e30f});
         int run = 0;
         for (int rep = 0; rep < REPS; ++rep)
-            for (int k = 0; k < 2; ++k, ++run) {
+            for (int k = 0; k < 3; ++k, ++run) {
                 const int gp = panels[run % panels.size()];
                 const PanelDev& P = ctx->pan_h[gp];
-                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(), k, k);
+                // forward candidate k; backward candidates 0 and 1 (the third
+                // run repeats the second)
+                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(), k,
+                                std::min(k, 1));
                 TCHK(hipGetLastError());
                 TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
                 for (int l = 0; l < 2 * (D + 1); ++l) {
@@ -1553,14 +1583,17 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
                         float& t = tf[D - l][k];
                         t = std::min(t, ms);
                     } else {
-                        float& t = tb[l - (D + 1)][k];
+                        float& t = tb[l - (D + 1)][std::min(k, 1)];
                         t = std::min(t, ms);
                     }
                 }
             }
         for (int d = 0; d <= D; ++d) {
             SolveLevel& sl = ctx->slevels[ci][d];
-            sl.mm_f = tf[d][1] < tf[d][0] ? 1 : 0;
+            if (!fwd_rs_fits<T>(sl.smax)) tf[d][2] = 1e30f;
+            sl.mm_f = 0;
+            for (int k = 1; k < 3; ++k)
+                if (tf[d][k] < tf[d][sl.mm_f]) sl.mm_f = k;
             sl.mm_b = tb[d][1] < tb[d][0] ? 1 : 0;
         }
     }

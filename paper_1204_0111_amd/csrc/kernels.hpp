@@ -61,6 +61,12 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t s
 // rt: row tiles of 16 per workgroup, 4 (items of 64 rows) or 1 (items of 16)
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st);
+// row-split forward form (items of 64 rows, v_S staged in LDS), for depths
+// whose largest front fits: fwd_rs_lds_bytes(smax) bytes of LDS per workgroup
+template <typename T>
+void launch_fwd_rs(const PassArgs<T>& A, int nwork, int smax, hipStream_t st);
+template <typename T>
+size_t fwd_rs_lds_bytes(int smax);
 // the panel's right-hand side into h2, in elimination order (matrix-core passes)
 template <typename T>
 void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st);

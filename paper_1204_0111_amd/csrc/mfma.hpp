@@ -39,6 +39,9 @@ typedef __amdgpu_buffer_rsrc_t BufRsrc;
 __device__ inline BufRsrc buf_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
+__device__ inline int buf_load_i32(BufRsrc r, uint32_t off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
 template <typename T> struct BufCx;
 template <> struct BufCx<float> {
     typedef float v2 __attribute__((ext_vector_type(2)));

@@ -120,10 +120,10 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
             dv = A.dinv[it.start + row];
         } else {
             pm = A.pmap[it.pmap + row - s];
-            const bool h0 = map0[row] >= 0, h1 = map1[row] >= 0;
+            const bool h0 = !it.leaf && map0[row] >= 0, h1 = !it.leaf && map1[row] >= 0;
 #pragma unroll
             for (int r = 0; r < RC; ++r)
-                if (r < nr) {
+                if (r < nr && !it.leaf) {
                     const Cx<T>* cc = A.c2 + (int64_t)(rhs0 + r) * A.c2ld + it.c2;
                     const Cx<T> a0 = cc[row], a1 = cc[n + row];
                     pre[r] = keep(h0, a0) + keep(h1, a1);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     for (int k = k0 + tid; k < s; k += NT) {
         const int b = pivot_box(it, A.Nx, A.NxNy, k);
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
-        const bool h0 = map0[k] >= 0, h1 = map1[k] >= 0;
+        const bool h0 = !it.leaf && map0[k] >= 0, h1 = !it.leaf && map1[k] >= 0;
         bool live;
         int64_t gi;
         Cx<double> cf = cx<double>(1, 0);
@@ -152,9 +152,11 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
             Cx<T> v = cx<T>(0, 0);
             if (r < nr) {
                 const int64_t rr = rhs0 + r;
-                const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
-                const Cx<T> a0 = cc[k], a1 = cc[n + k];
-                v = keep(h0, a0) + keep(h1, a1);
+                if (!it.leaf) {
+                    const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
+                    const Cx<T> a0 = cc[k], a1 = cc[n + k];
+                    v = keep(h0, a0) + keep(h1, a1);
+                }
                 if (live) {
                     const Cx<double> x = A.src[rr * A.ld + gi];
                     v = v + ccast<T>(A.mode == 0 ? x : cf * x);
@@ -506,10 +508,13 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // them read zeros, so every chunk issues the same loads (the next
     // chunk's stay in flight during this one's products) and needs no bounds
     // test; rows past n give product rows that are never stored.
+    // A leaf has no children: its slots hold zeros and are not read (the
+    // descriptors of zero length return zeros without touching memory).
+    const uint32_t c2len = it.leaf ? 0u : (uint32_t)kend * 16 * ES;
     const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)kend * n * ES);
     const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
-    const BufRsrc r0 = buf_rsrc(c2f, (uint32_t)kend * 16 * ES);
-    const BufRsrc r1 = buf_rsrc(c2f + (int64_t)n * 16, (uint32_t)kend * 16 * ES);
+    const BufRsrc r0 = buf_rsrc(c2f, c2len);
+    const BufRsrc r1 = buf_rsrc(c2f + (int64_t)n * 16, c2len);
     // lane operands: A(row, k) = G(blk + 16 t + li, c + 4 q + lk) and
     // B(k, rhs) = v_S(c + 4 q + lk, li)
     T gre[RT][4], gim[RT][4];
@@ -606,10 +611,158 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         if (row < s) {
             xm[(int64_t)(it.start + row) * 16 + r] = y * A.dinv[it.start + row];
         } else {
-            const Cx<T> pre = c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
+            const Cx<T> pre = it.leaf ? cx<T>(0, 0) : c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
             c2g[(int64_t)(it.push + A.pmap[it.pmap + row - s]) * 16 + r] = pre - y;
         }
     }
+}
+
+// Row-split form of the forward matrix-core pass for fronts whose v_S fits
+// in LDS: the workgroup's 64 rows go one 16-row tile to each of its four
+// waves, so no partial sums are combined.  The workgroup stages its slice of
+// v_S (right-hand side plus the children's halves, summed) once in LDS,
+// together with what the epilogue needs (1/D of its pivot rows, the
+// children's contributions and parent positions of its update rows); each
+// wave then streams its rows of G with FP chunks of loads in flight, taking
+// the B operand from LDS.  The first FP chunks are issued before the staging
+// loads.  LDS: fwd_rs_lds_bytes.
+template <typename T, int FP>
+__global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
+    typedef typename MfmaAcc<T>::type V4;
+    constexpr int KC = 16, ROWS = 64;
+    constexpr uint32_t ES = sizeof(Cx<T>);
+    extern __shared__ unsigned char smem_raw[];
+    const SolveItem it = A.items[blockIdx.x];  // items of 64 rows
+    const int n = it.n, s = it.s;
+    const int grp = blockIdx.y;
+    const int64_t rhs0 = (int64_t)grp * 16;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: G's descriptor is scalar
+    const int li = lane & 15, lk = lane >> 4;
+    const int kend = min(it.blk + ROWS, s);
+    const int kb = (leaf_first_live(A, it) / KC) * KC;
+    const int nk16 = kend > kb ? (kend - kb + KC - 1) / KC * KC : 0;  // staged entries
+    Cx<T>* V = reinterpret_cast<Cx<T>*>(smem_raw);   // [nk16][16]
+    Cx<T>* E = V + (int64_t)nk16 * 16;               // [ROWS][16]
+    Cx<T>* Dv = E + ROWS * 16;                       // [ROWS]
+    int* PM = reinterpret_cast<int*>(Dv + ROWS);     // [ROWS], then one spare entry
+    const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
+    const Cx<T>* h2f = A.h2 + grp * A.gs_h2 + (int64_t)it.start * 16;
+    // this wave's rows r0 .. r0 + 15 need the columns below kw (the triangle
+    // of L_F^{-1} above; all s columns for update rows); its G descriptor is
+    // cut there, so the chunks issued past its end read zeros without
+    // touching memory
+    const int r0 = it.blk + 16 * wave;
+    const int kw = r0 < n ? min(r0 + 16, s) : 0;
+    const int nch = kw > kb ? (kw - kb + KC - 1) / KC : 0;
+    const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)kw * n * ES);
+    T gre[FP][4], gim[FP][4];
+    auto load = [&](int ch, T(&gr)[4], T(&gi)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t col = (uint32_t)(kb + ch * KC + 4 * q + lk);
+            BufCx<T>::load(rg, (col * n + r0 + li) * ES, gr[q], gi[q]);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < FP; ++j) load(j, gre[j], gim[j]);
+    // Staging.  Every load is unconditional and bounded by its descriptor
+    // (reads past the end give zeros), and values no one needs are stored to
+    // a spare LDS slot, so no load waits on a branch: the epilogue operands
+    // of the workgroup's rows, then v_S over [kb, kb + nk16) (zeros from kend
+    // on), summed from the right-hand side and the children's halves.
+    {
+        const uint32_t c2len = it.leaf ? 0u : (uint32_t)kend * 16 * ES;
+        const uint32_t c2all = it.leaf ? 0u : (uint32_t)n * 16 * ES;
+        const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
+        const BufRsrc ra = buf_rsrc(c2f, c2len), rb = buf_rsrc(c2f + (int64_t)n * 16, c2len);
+        const BufRsrc ea = buf_rsrc(c2f, c2all), eb = buf_rsrc(c2f + (int64_t)n * 16, c2all);
+        const BufRsrc rd = buf_rsrc(A.dinv + it.start, (uint32_t)s * ES);
+        const BufRsrc rp = buf_rsrc(A.pmap + it.pmap, (uint32_t)(n - s) * 4);
+        T er[4], ei[4], fr[4], fi[4], dr, di;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u, row = it.blk + (e >> 4);
+            const uint32_t off = (uint32_t)(row * 16 + (e & 15)) * ES;
+            BufCx<T>::load(ea, off, er[u], ei[u]);
+            BufCx<T>::load(eb, off, fr[u], fi[u]);
+        }
+        const int drow = it.blk + (tid & 63);
+        BufCx<T>::load(rd, (uint32_t)drow * ES, dr, di);  // zero from s on
+        const int pm = buf_load_i32(rp, (uint32_t)(drow - s) * 4);  // zero on pivot rows
+        Cx<T>* trash = reinterpret_cast<Cx<T>*>(PM + ROWS);  // 256 bytes past PM: aligned
+        const int tot = nk16 * 16;
+        for (int e0 = tid; e0 < tot; e0 += 4 * 256) {
+            T hr[4], hi[4], ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t off = (uint32_t)(kb * 16 + e0 + 256 * u) * ES;
+                BufCx<T>::load(rh, off, hr[u], hi[u]);
+                BufCx<T>::load(ra, off, ar[u], ai[u]);
+                BufCx<T>::load(rb, off, br[u], bi[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 256 * u;
+                *(e < tot ? V + e : trash) = cx<T>(hr[u] + ar[u] + br[u], hi[u] + ai[u] + bi[u]);
+            }
+        }
+        // pivot rows take no contribution (their slots hold the children's
+        // v_S parts, already summed above)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u, row = it.blk + (e >> 4);
+            E[e] = row >= s ? cx<T>(er[u] + fr[u], ei[u] + fi[u]) : cx<T>(0, 0);
+        }
+        if (tid < ROWS) {
+            Dv[tid] = cx<T>(dr, di);
+            PM[tid] = pm;
+        }
+    }
+    __syncthreads();
+    V4 a0 = V4{0, 0, 0, 0}, a1 = V4{0, 0, 0, 0}, b0 = V4{0, 0, 0, 0}, b1 = V4{0, 0, 0, 0};
+    auto products = [&](int ch, const T(&gr)[4], const T(&gi)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const Cx<T> v = V[(ch * KC + 4 * q + lk) * 16 + li];
+            a0 = mfma4(gr[q], v.re, a0);
+            b0 = mfma4(gr[q], v.im, b0);
+            a1 = mfma4(-gi[q], v.im, a1);
+            b1 = mfma4(gi[q], v.re, b1);
+        }
+    };
+    // chunk ch + j sits in buffer j; each buffer is refilled with the chunk
+    // FP ahead as soon as its products are issued
+    for (int ch = 0; ch < nch; ch += FP) {
+#pragma unroll
+        for (int j = 0; j < FP; ++j) {
+            if (ch + j < nch) products(ch + j, gre[j], gim[j]);
+            load(ch + j + FP, gre[j], gim[j]);
+        }
+    }
+    a0 += a1;
+    b0 += b1;
+    if (rhs0 + li >= A.nrhs) return;
+    Cx<T>* xm = A.xmid + grp * A.gs_x;
+    Cx<T>* c2g = A.c2 + grp * A.gs_c2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lrow = 16 * wave + mfma_out_row<T>(lk, r), row = it.blk + lrow;
+        if (row >= n) continue;
+        const Cx<T> y = cx<T>(a0[r], b0[r]);
+        if (row < s)
+            xm[(int64_t)(it.start + row) * 16 + li] = y * Dv[lrow];
+        else
+            c2g[(int64_t)(it.push + PM[lrow]) * 16 + li] = E[lrow * 16 + li] - y;
+    }
+}
+
+// LDS of k_fwd_rs for fronts of up to smax pivots (staged v_S, the
+// epilogue's contributions, 1/D and parent positions).
+template <typename T>
+size_t fwd_rs_lds_bytes(int smax) {
+    const size_t nk16 = (size_t)(smax + 15) / 16 * 16;
+    return (nk16 * 16 + 64 * 16 + 64 + 1) * sizeof(Cx<T>) + 64 * sizeof(int);
 }
 
 // CT column tiles of 16 per workgroup; NW waves split the rows of the
@@ -1164,6 +1317,13 @@ void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st) {
     }
 }
 template <typename T>
+void launch_fwd_rs(const PassArgs<T>& A, int nwork, int smax, hipStream_t st) {
+    if (nwork <= 0) return;
+    const dim3 grid(nwork, (A.nrhs + 15) / 16);
+    constexpr int FP = sizeof(T) == 4 ? 4 : 2;
+    HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A);
+}
+template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
@@ -1181,6 +1341,8 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st) {
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
     template void launch_fwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
+    template void launch_fwd_rs<T>(const PassArgs<T>&, int, int, hipStream_t);              \
+    template size_t fwd_rs_lds_bytes<T>(int);                                                \
     template void launch_rhs_scatter<T>(const PassArgs<T>&, hipStream_t);                    \
     template void launch_bwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
     template int solve_rhs_chunk<T>(int, int);

@@ -116,6 +116,22 @@ def test_middle_panel_many_rhs_matrix_core_passes_match_oracle(name, nrhs, prec)
     assert max(errs) <= TOL[prec], errs
 
 
+@pytest.mark.parametrize("name", ["grf50", "layered100"])
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_middle_panel_row_split_forward_form_matches_oracle(name, prec):
+    """The row-split forward form forced at every depth where it fits (the
+    others keep 64-row workgroups), 17 right-hand sides, against the oracle's
+    sparse LU per right-hand side."""
+    P, v, ref = _panel_reference(name, 5)
+    S = _solver(P, prec)
+    S.set_option("mm_fwd_form", 2)
+    y = S.panel_solve(0, 5, torch.as_tensor(v).to("cuda")).cpu().numpy()
+    S.close()
+    errs = [rel(y[r], ref[r]) for r in range(len(v))]
+    print("%s %s row-split: worst T_i relative error %.3e" % (name, prec, max(errs)))
+    assert max(errs) <= TOL[prec], errs
+
+
 def test_matvec_full_size(grf50):
     P, _ = grf50
     S = _solver(P, "c64")

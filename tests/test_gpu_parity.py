@@ -344,6 +344,25 @@ def test_sweep_matches_oracle(medium, prec, nrhs):
         assert rel(z[k], ref[k]) <= TOL[prec], k
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("fwd_form", [0, 1, 2])
+@pytest.mark.parametrize("bwd_form", [0, 1])
+def test_sweep_each_matrix_core_form_matches_oracle(medium, prec, fwd_form, bwd_form):
+    """Every form of the 16-right-hand-side passes, forced at every depth
+    (the autotuner picks among them per depth): the sweep of Alg. 1.5 for 17
+    right-hand sides (a full group and a ragged one) against the oracle."""
+    P = medium
+    S = _solver(P, prec)
+    S.set_option("mm_fwd_form", fwd_form)
+    S.set_option("mm_bwd_form", bwd_form)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((17, O.N_pad), 5)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    ref = O.apply(r.T).T
+    for k in range(17):
+        assert rel(z[k], ref[k]) <= TOL[prec], k
+
+
 def test_sweep_is_deterministic(medium):
     S = _solver(medium, "c64")
     r = _cuda(wl.random_complex((2, S.N_pad()), 4))
