@@ -132,17 +132,24 @@ struct PassArgs {
     int Nx, NxNy, nz, ga, lo, hi;
     int e1, e2, ie3hi;         // et offsets: e1 and e2 node tables, 1/e3 at the half plane below hi
     double inv_h2;
-    // Matrix-core passes (groups of 16 right-hand sides): xmid, xu and c2
-    // then hold [entry][16] blocks, one block of entries per group, the
-    // group's block of a buffer starting gs_* complex numbers after the
-    // previous one; c2 is the panel class's own region (zero where no child
-    // writes) and h2 holds the right-hand side in elimination order (zero
-    // on the auxiliary planes), written by the scatter at the start of a solve.
+    // Matrix-core passes (groups of 16 right-hand sides): xu and c2 then
+    // hold [entry][16] blocks, one block of entries per group, the group's
+    // block of a buffer starting gs_* complex numbers after the previous one.
+    // xu holds each front's [x_S; -x_U] (x_S from the forward pass in front
+    // of the update-set values, which are stored negated; xmid is unused);
+    // c2 is the panel class's own region (zero where no child writes) and h2
+    // holds the right-hand side in elimination order (zero on the auxiliary
+    // planes), written by the scatter at the start of a solve.
     Cx<T>* h2;
     const int* perm;           // elimination position -> box index of the panel class
     int zero_aux;              // scatter: also write zeros on the auxiliary planes (a class
                                // shared by panels with different auxiliary depths)
-    int64_t gs_x, gs_u, gs_c2, gs_h2;
+    int64_t gs_u, gs_c2, gs_h2;
+    // split contraction (forms that divide each item's contraction over
+    // nsplit workgroups): partial 64 x 16 blocks, item-major, then group,
+    // then split; a finishing launch sums them in split order
+    Cx<T>* part;
+    int nsplit;
 };
 
 struct PanelDev {

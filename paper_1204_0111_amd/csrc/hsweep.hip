@@ -127,7 +127,8 @@ struct Lane {
     // right-hand sides: x_mid, update-set values, the child-contribution
     // slots of every panel class (each class its own zeroed region) and the
     // right-hand side in elimination order (likewise per class)
-    void *d_mxmid = nullptr, *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;
+    void *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;  // [x_S; -x_U] per front, slots, h2
+    void* d_mpart = nullptr;  // partial blocks of the split-contraction forms
     int mm_groups = 0;
     std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
 };
@@ -201,9 +202,8 @@ struct hsw_ctx {
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
     bool bf16_mfma = true;     // HSW_C64_BF16GEMM: Schur updates on the BF16 matrix cores
-    // matrix-core pass forms for every depth (-1: the tuned choice); forward
-    // 0 / 1: items of 64 / 16 rows, 2: row-split (where it fits); backward
-    // 0 / 1: items of 64 / 16 columns
+    // matrix-core pass forms for every depth (-1: the tuned choice; the
+    // forms of launch_fwd_mm and launch_bwd_mm)
     int mm_fwd_form = -1, mm_bwd_form = -1;
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
@@ -278,7 +278,7 @@ static void free_lane(Lane& L, bool own_stream) {
     for (auto& w : L.gws)
         if (w.first) (void)hipFree(w.first);
     L.gws.clear();
-    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxmid, &L.d_mxu, &L.d_mc2, &L.d_mh2}) {
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1059,10 +1059,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             drop_graphs(ctx);
         }
     } else if (k == "mm_fwd_form") {
-        if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1, 0, 1 or 2");
+        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..5");
         ctx->mm_fwd_form = (int)value;
     } else if (k == "mm_bwd_form") {
-        if (value < -1 || value > 1) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1, 0 or 1");
+        if (value < -1 || value > 4) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..4");
         ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
@@ -1246,7 +1246,7 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     if (groups <= L.mm_groups) return HSW_OK;
     HIPCHK(hipStreamSynchronize(L.st));
     if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
-    for (void** p : {&L.d_mxmid, &L.d_mxu, &L.d_mc2, &L.d_mh2}) {
+    for (void** p : {&L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1254,10 +1254,17 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     const size_t e = sizeof(Cx<T>) * 16 * (size_t)groups;
     const size_t bc2 = e * (size_t)std::max<int64_t>(ctx->total_c2, 1);
     const size_t bh2 = e * (size_t)std::max<int64_t>(ctx->total_naux, 1);
-    HIPCHK(hipMalloc(&L.d_mxmid, e * (size_t)ctx->max_naux));
+    // partial blocks: the largest (items x splits) of any depth's 64-row or
+    // 64-column launch, 1024 entries per item, group and split
+    int64_t parts = 1;
+    for (const auto& lv : ctx->slevels)
+        for (const SolveLevel& sl : lv)
+            for (int cnt : {sl.fcount[0], sl.bcount[MM_BWD_SHAPE64]})
+                parts = std::max<int64_t>(parts, (int64_t)cnt * groups * mm_split(cnt, groups));
     HIPCHK(hipMalloc(&L.d_mxu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
     HIPCHK(hipMalloc(&L.d_mc2, bc2));
     HIPCHK(hipMalloc(&L.d_mh2, bh2));
+    HIPCHK(hipMalloc(&L.d_mpart, sizeof(Cx<T>) * 1024 * (size_t)parts));
     HIPCHK(hipMemsetAsync(L.d_mc2, 0, bc2, L.st));
     HIPCHK(hipMemsetAsync(L.d_mh2, 0, bh2, L.st));
     L.mm_groups = groups;
@@ -1348,13 +1355,13 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     AT.G = (const Cx<T>*)ctx->d_L + f0.loff;
     if (nrhs >= MM_MIN_RHS && force_f < 0 && !tri_all) {  // matrix-core passes, 16 right-hand sides per group
         const int64_t cls_c2 = ctx->cls_c2_base[P.cls], cls_h2 = ctx->cls_perm_off[P.cls];
-        A.xmid = (Cx<T>*)ln.d_mxmid;
+        A.xmid = nullptr;  // x_S sits in front of x_U, in xu
         A.xu = (Cx<T>*)ln.d_mxu;
         A.c2 = (Cx<T>*)ln.d_mc2 + 16 * cls_c2;
         A.h2 = (Cx<T>*)ln.d_mh2 + 16 * cls_h2;
+        A.part = (Cx<T>*)ln.d_mpart;
         A.perm = ctx->d_perm + P.perm_off;
         A.zero_aux = ctx->cls_mixed_ga[P.cls];
-        A.gs_x = 16 * (int64_t)ctx->max_naux;
         A.gs_u = 16 * std::max<int64_t>(ctx->max_wsize, 1);
         A.gs_c2 = 16 * std::max<int64_t>(ctx->total_c2, 1);
         A.gs_h2 = 16 * std::max<int64_t>(ctx->total_naux, 1);
@@ -1370,41 +1377,40 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 0.0, [&] { launch_rhs_scatter<T>(A, st); });
         const int groups = (nrhs + 15) / 16;
         for (int d = c.maxdepth; d >= 0; --d) {
-            // 64-row items, or 16-row ones (the tuned choice, else where 64-row
-            // items give few workgroups; complex128 takes 16-row items), or
-            // the row-split form over 64-row items (tuned choice 2, where the
-            // depth's largest v_S fits in LDS)
-            int fs = mm_fwd_shape<T>(), rt = MmFwdTiles<T>::value;
-            const int pick = mm_force_f >= 0 ? mm_force_f : ctx->mm_fwd_form >= 0 ? ctx->mm_fwd_form : lv[d].mm_f;
-            const bool rs = pick == 2 && fwd_rs_fits<T>(lv[d].smax);
-            if (rs) {
-                fs = 0;
-            } else if (rt == 4 && (pick == 1 || (pick < 0 && lv[d].fcount[fs] * groups < MM_NARROW_BELOW))) {
-                fs = 1;
-                rt = 1;
+            // the form: forced, tuned, or the default rule (64-row items
+            // unless they give few workgroups, complex128 16-row ones; 8
+            // waves below 512 workgroups)
+            int form = mm_force_f >= 0 ? mm_force_f : ctx->mm_fwd_form >= 0 ? ctx->mm_fwd_form : lv[d].mm_f;
+            if (form == 2 && !fwd_rs_fits<T>(lv[d].smax)) form = 0;
+            if (form < 0) {
+                const bool rt4 = sizeof(T) == 4 && lv[d].fcount[0] * groups >= MM_NARROW_BELOW;
+                form = rt4 ? 0 : 1;
+                if (lv[d].fcount[rt4 ? 0 : 1] * groups < MM_WIDE_BELOW) form += 3;
             }
+            const int fs = (form == 1 || form == 4) ? 1 : 0;
             A.items = ctx->d_sitems + lv[d].foff[fs];
+            A.nsplit = mm_split(lv[d].fcount[fs], groups);
             run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec_bytes,
-                8.0 * nrhs * lv[d].g_need(pf), [&] {
-                    if (rs)
-                        launch_fwd_rs<T>(A, lv[d].fcount[fs], lv[d].smax, st);
-                    else
-                        launch_fwd_mm<T>(A, lv[d].fcount[fs], rt, st);
-                });
+                8.0 * nrhs * lv[d].g_need(pf),
+                [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], form, lv[d].smax, st); });
         }
         A.mode = emode;
         for (int d = 0; d <= c.maxdepth; ++d) {
-            // 64-column items (the tuned choice, else where they give enough
-            // workgroups), or 16-column ones
-            int bs = MM_BWD_SHAPE, ct = 1;
-            const int bpick = mm_force_b >= 0 ? mm_force_b : ctx->mm_bwd_form >= 0 ? ctx->mm_bwd_form : lv[d].mm_b;
-            if (bpick == 0 || (bpick < 0 && lv[d].bcount[MM_BWD_SHAPE64] * groups >= MM_TILES4_FROM)) {
-                bs = MM_BWD_SHAPE64;
-                ct = 4;
+            // the form: forced, tuned, or the default rule (64-column items
+            // where they give enough workgroups, else 16-column ones, with 16
+            // waves (complex64) below 512 workgroups)
+            int form = mm_force_b >= 0 ? mm_force_b : ctx->mm_bwd_form >= 0 ? ctx->mm_bwd_form : lv[d].mm_b;
+            if (form < 0) {
+                if (lv[d].bcount[MM_BWD_SHAPE64] * groups >= MM_TILES4_FROM)
+                    form = 0;
+                else
+                    form = sizeof(T) == 4 && lv[d].bcount[MM_BWD_SHAPE] * groups < MM_WIDE_BELOW ? 3 : 1;
             }
+            const int bs = (form == 0 || form == 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
             A.items = ctx->d_sitems + lv[d].boff[bs];
+            A.nsplit = mm_split(lv[d].bcount[bs], groups);
             run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec_bytes,
-                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[bs], ct, st); });
+                8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[bs], form, st); });
         }
         return;
     }
@@ -1564,16 +1570,18 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        std::vector<std::array<float, 3>> tf(D + 1, {1e30f, 1e30f, 1e30f}), tb(D + 1, {1e30f, 1e30f, 1e30f});
+        constexpr int NF = 6, NB = 5;  // forward and backward forms
+        std::vector<std::array<float, NF>> tf(D + 1), tb(D + 1);
+        for (auto& a : tf) a.fill(1e30f);
+        for (auto& a : tb) a.fill(1e30f);
         int run = 0;
         for (int rep = 0; rep < REPS; ++rep)
-            for (int k = 0; k < 3; ++k, ++run) {
+            for (int k = 0; k < NF; ++k, ++run) {
                 const int gp = panels[run % panels.size()];
                 const PanelDev& P = ctx->pan_h[gp];
-                // forward candidate k; backward candidates 0 and 1 (the third
-                // run repeats the second)
+                // forward form k and backward form min(k, NB - 1) at every depth
                 panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(), k,
-                                std::min(k, 1));
+                                std::min(k, NB - 1));
                 TCHK(hipGetLastError());
                 TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
                 for (int l = 0; l < 2 * (D + 1); ++l) {
@@ -1583,18 +1591,20 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
                         float& t = tf[D - l][k];
                         t = std::min(t, ms);
                     } else {
-                        float& t = tb[l - (D + 1)][std::min(k, 1)];
+                        float& t = tb[l - (D + 1)][std::min(k, NB - 1)];
                         t = std::min(t, ms);
                     }
                 }
             }
         for (int d = 0; d <= D; ++d) {
             SolveLevel& sl = ctx->slevels[ci][d];
-            if (!fwd_rs_fits<T>(sl.smax)) tf[d][2] = 1e30f;
+            if (!fwd_rs_fits<T>(sl.smax)) tf[d][2] = 1e30f;  // ran as form 0
             sl.mm_f = 0;
-            for (int k = 1; k < 3; ++k)
+            for (int k = 1; k < NF; ++k)
                 if (tf[d][k] < tf[d][sl.mm_f]) sl.mm_f = k;
-            sl.mm_b = tb[d][1] < tb[d][0] ? 1 : 0;
+            sl.mm_b = 0;
+            for (int k = 1; k < NB; ++k)
+                if (tb[d][k] < tb[d][sl.mm_b]) sl.mm_b = k;
         }
     }
 #undef TCHK
@@ -1655,10 +1665,10 @@ static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* 
         gl.d_xu = ln.d_xu;
         gl.d_c2 = ln.d_c2;
         gl.nrhs_cap = ln.nrhs_cap;
-        gl.d_mxmid = ln.d_mxmid;
         gl.d_mxu = ln.d_mxu;
         gl.d_mc2 = ln.d_mc2;
         gl.d_mh2 = ln.d_mh2;
+        gl.d_mpart = ln.d_mpart;
         gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {

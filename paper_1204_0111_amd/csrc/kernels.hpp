@@ -8,8 +8,10 @@
 
 namespace hsw {
 
-// Events that the next launch records at its own start and end
-// (hipExtLaunchKernelGGL), set by the driver while a kernel class is timed.
+// Events that the launches record (hipExtLaunchKernelGGL), set by the driver
+// while a kernel class is timed: `start` at the start of the first launch
+// after it is set (the launch clears it), `stop` at the end of every launch,
+// so a group of launches (a pass and its finishing launch) is timed whole.
 struct LaunchTiming {
     hipEvent_t start = nullptr, stop = nullptr;
 };
@@ -20,11 +22,13 @@ LaunchTiming& launch_timing();
 #define HSW_LAUNCH(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                     \
     do {                                                                                     \
         ::hsw::LaunchTiming& lt_ = ::hsw::launch_timing();                                   \
-        if (lt_.start)                                                                       \
+        if (lt_.stop) {                                                                      \
             hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, lt_.start, lt_.stop, 0,  \
                                   __VA_ARGS__);                                              \
-        else                                                                                 \
+            lt_.start = nullptr;                                                             \
+        } else {                                                                             \
             hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);               \
+        }                                                                                    \
     } while (0)
 
 namespace hsw {
@@ -58,21 +62,23 @@ template <typename T>
 void launch_fwd(const PassArgs<T>& A, int nwork, int rb, int smax, int nmax, hipStream_t st);
 template <typename T>
 void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t st);
-// rt: row tiles of 16 per workgroup, 4 (items of 64 rows) or 1 (items of 16)
+// forward matrix-core pass: form 0 / 3 (items of 64 rows, 4 / 8 waves splitting
+// the contraction), 1 / 4 (items of 16 rows, 4 / 8 waves), 2 (row-split, items
+// of 64 rows, fwd_rs_lds_bytes(smax) bytes of LDS per workgroup), 5 (items of
+// 64 rows, contraction split over A.nsplit workgroups; A.part holds
+// nwork x groups x nsplit x 1024 partial entries)
 template <typename T>
-void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st);
-// row-split forward form (items of 64 rows, v_S staged in LDS), for depths
-// whose largest front fits: fwd_rs_lds_bytes(smax) bytes of LDS per workgroup
-template <typename T>
-void launch_fwd_rs(const PassArgs<T>& A, int nwork, int smax, hipStream_t st);
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStream_t st);
 template <typename T>
 size_t fwd_rs_lds_bytes(int smax);
 // the panel's right-hand side into h2, in elimination order (matrix-core passes)
 template <typename T>
 void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st);
-// ct: column tiles of 16 per workgroup, 4 (items of 64 columns) or 1 (items of 16)
+// backward matrix-core pass: form 0 (items of 64 columns, 4 waves), 1 / 2 / 3
+// (items of 16 columns, 4 / 8 / 16 waves; complex128: 8) or 4 (items of 64
+// columns, contraction split over A.nsplit workgroups, as forward form 5)
 template <typename T>
-void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st);
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st);
 template <typename T>
 int solve_rhs_chunk(int nrhs, int nmax);
 // triangular passes with the kept factors (fwd: forward pass, else backward),

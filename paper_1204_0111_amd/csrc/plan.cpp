@@ -205,8 +205,10 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
         double s = pc.s[k], u = pc.u[k];
         pc.loff[k] = pc.lsize;
         pc.lsize += (int64_t)(pc.s[k] + pc.u[k]) * pc.s[k];
-        pc.woff[k] = (int)pc.wsize;
-        pc.wsize += pc.u[k];
+        // each front's vector region holds its s pivot entries, then its u
+        // update-set entries (woff points at the latter)
+        pc.woff[k] = (int)(pc.wsize + pc.s[k]);
+        pc.wsize += pc.s[k] + pc.u[k];
         pc.at_depth[pc.depth[k]].push_back(k);
         pc.factor_cmac += s * s * s / 6 + s * s * u / 2 + s * u * u / 2;
     }

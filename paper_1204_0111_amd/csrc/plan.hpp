@@ -13,6 +13,7 @@
 // in elimination order.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -38,19 +39,27 @@ constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512},
 constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256},
                                                 {64, 256}, {2, 128}, {4, 128}};
 // Groups of at least this many right-hand sides use the matrix-core passes,
-// 16 right-hand sides per group: forward 64 rows per workgroup in complex64
-// (shape 0), 16 in complex128 (shape 1, fewer registers) and in complex64
-// launches that would have fewer than MM_NARROW_BELOW workgroups of 64 rows;
-// backward 64 columns (shape 6) in launches of at least MM_TILES4_FROM
-// workgroups of 64 columns, else 16 columns (shape 4).
+// 16 right-hand sides per group.  Without tuning, the forward pass takes
+// items of 64 rows (shape 0) in complex64, or of 16 rows (shape 1) in
+// complex128 and in complex64 launches that would have fewer than
+// MM_NARROW_BELOW workgroups of 64 rows; the backward pass takes 64 columns
+// (shape 6) in launches of at least MM_TILES4_FROM workgroups of 64 columns,
+// else 16 columns (shape 4).  Launches of fewer than MM_WIDE_BELOW
+// workgroups take more waves per workgroup.
 constexpr int MM_MIN_RHS = 16;
 constexpr int MM_BWD_SHAPE = 4, MM_BWD_SHAPE64 = 6;
-constexpr int MM_NARROW_BELOW = 256, MM_TILES4_FROM = 512;
+constexpr int MM_NARROW_BELOW = 256, MM_TILES4_FROM = 512, MM_WIDE_BELOW = 512;
+// The split-contraction forms divide each item's contraction over
+// mm_split(items, groups) workgroups: about MM_SPLIT_TARGET workgroups per
+// launch, at most MM_SPLIT_MAX shares per item.
+constexpr int MM_SPLIT_TARGET = 512, MM_SPLIT_MAX = 8;
+inline int mm_split(int items, int groups) {
+    const int64_t w = std::max<int64_t>(1, (int64_t)items * groups);
+    return (int)std::min<int64_t>(MM_SPLIT_MAX, std::max<int64_t>(1, (MM_SPLIT_TARGET + w - 1) / w));
+}
 static_assert(FWD_SHAPES[0].block == 64 && FWD_SHAPES[1].block == 16 && BWD_SHAPES[MM_BWD_SHAPE].block == 16 &&
                   BWD_SHAPES[MM_BWD_SHAPE64].block == 64,
               "the matrix-core passes take items of 64 or 16 rows (forward) and 16 or 64 columns (backward)");
-template <typename T> struct MmFwdTiles { static constexpr int value = sizeof(T) == 4 ? 4 : 1; };
-template <typename T> constexpr int mm_fwd_shape() { return MmFwdTiles<T>::value == 4 ? 0 : 1; }
 constexpr int SOLVE_SMALL_BLOCK_N = 512;
 // Depths with at least this many fronts (over all panels and problems) apply
 // the Schur updates left-looking: each block column once, before its pivots
@@ -95,9 +104,10 @@ struct PanelClass {
     std::vector<int> c2off;        // per front: offset of its 2 (s+u) child-contribution slots
     int64_t c2size = 0;            // sum 2 (s+u)
     std::vector<int64_t> loff;     // per front: offset of its (s+u) x s block, relative to the panel
-    std::vector<int> woff;         // per front: offset of its update vector (u entries per rhs)
+    std::vector<int> woff;         // per front: offset of its update vector (u entries per rhs),
+                                   // which follows s entries of the front's own
     int64_t lsize = 0;             // sum (s+u) s
-    int64_t wsize = 0;             // sum u
+    int64_t wsize = 0;             // sum of s + u
     std::vector<std::vector<int>> at_depth;
     double factor_cmac = 0;  // complex multiply-adds of the panel's partial factorisations
 };

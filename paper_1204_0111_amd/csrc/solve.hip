@@ -482,15 +482,96 @@ __global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
     }
 }
 
+// Sum the NW waves' partial 16R x 16 blocks (accumulator layout: lane
+// (li, lk) holds column li of rows mfma_out_row(lk, r)) into Y[16R][17].
+// When every wave's block fits in the LDS array P (PAR), the waves store
+// theirs at once and the workgroup adds them after one barrier; otherwise
+// the waves add theirs to Y in turn.  Ends with a barrier.
+template <typename T, int R, int NW>
+struct WaveSum {
+    static constexpr bool PAR = (R == 1 || NW >= 8) && NW * 16 * R * 17 * 2 * (int)sizeof(T) <= 40960;
+    static constexpr int PLEN = PAR ? NW * 16 * R * 17 : 1;
+};
+template <typename T, int R, int NW, typename V4>
+__device__ inline void sum_wave_blocks(const V4 (&acr)[R], const V4 (&aci)[R], T (&Yre)[16 * R][17],
+                                       T (&Yim)[16 * R][17], T* Pre, T* Pim, int wave, int li, int lk,
+                                       int tid) {
+    if constexpr (WaveSum<T, R, NW>::PAR) {
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = (wave * 16 * R + 16 * t + mfma_out_row<T>(lk, r)) * 17 + li;
+                Pre[o] = acr[t][r];
+                Pim[o] = aci[t][r];
+            }
+        __syncthreads();
+        for (int e = tid; e < 16 * R * 16; e += 64 * NW) {
+            const int row = e >> 4, c = e & 15;
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                sr += Pre[(w * 16 * R + row) * 17 + c];
+                si += Pim[(w * 16 * R + row) * 17 + c];
+            }
+            Yre[row][c] = sr;
+            Yim[row][c] = si;
+        }
+        __syncthreads();
+    } else {
+        for (int w = 0; w < NW; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int t = 0; t < R; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * t + mfma_out_row<T>(lk, r);
+                        if (w == 0) {
+                            Yre[row][li] = acr[t][r];
+                            Yim[row][li] = aci[t][r];
+                        } else {
+                            Yre[row][li] += acr[t][r];
+                            Yim[row][li] += aci[t][r];
+                        }
+                    }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // RT row tiles of 16 per workgroup: each of the NW waves updates all of them
 // over every NW-th chunk of the contraction.  Launches with few workgroups
 // (the upper depths, with long contractions) take the wide form, NW = 8, to
 // shorten each wave's chain of chunks.
-template <typename T, int RT, int NW>
+// The forward epilogue of one output (row, right-hand side r of the group):
+// x_S := D^{-1} y on a pivot row, the update part (the children's
+// contributions minus y) to the front's slot in its parent otherwise.
+template <typename T>
+__device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int grp, int row, int r, Cx<T> y) {
+    const int n = it.n, s = it.s;
+    if (row >= n) return;
+    if (row < s) {
+        A.xu[grp * A.gs_u + (int64_t)(it.xu - s + row) * 16 + r] = y * A.dinv[it.start + row];
+    } else {
+        const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
+        const Cx<T> pre = it.leaf ? cx<T>(0, 0) : c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
+        A.c2[grp * A.gs_c2 + (int64_t)(it.push + A.pmap[it.pmap + row - s]) * 16 + r] = pre - y;
+    }
+}
+
+// SK: split contraction.  Workgroup b takes item b / nsplit and the
+// (b mod nsplit)-th share of its chunks, and stores its partial block
+// instead of the epilogue (k_fwd_fin sums the shares).
+template <typename T, int RT, int NW, bool SK = false>
 __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    const SolveItem it = A.items[blockIdx.x];  // items of 16 RT rows
+    static_assert(!SK || (RT == 4 && NW == 4), "split contraction: 64-row items, 4 waves");
+    const int S = SK ? A.nsplit : 1;
+    const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
+    const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    const SolveItem it = A.items[ib];  // items of 16 RT rows
     const int n = it.n, s = it.s;
     const int grp = blockIdx.y;
     const int64_t rhs0 = (int64_t)grp * 16;
@@ -515,6 +596,22 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
     const BufRsrc r0 = buf_rsrc(c2f, c2len);
     const BufRsrc r1 = buf_rsrc(c2f + (int64_t)n * 16, c2len);
+    // With one row tile, the epilogue's operands (1/D of a pivot row, or the
+    // children's contributions and the parent position of an update row)
+    // are loaded first, bounded so that every load is unconditional: they
+    // arrive during the products instead of after them.
+    const int erow = it.blk + (tid >> 4), er = tid & 15;
+    Cx<T> e_d = cx<T>(0, 0), e_a = cx<T>(0, 0), e_b = cx<T>(0, 0);
+    int e_pm = 0;
+    if constexpr (RT == 1) {
+        const BufRsrc rd = buf_rsrc(A.dinv + it.start, (uint32_t)s * ES);
+        const BufRsrc rp = buf_rsrc(A.pmap + it.pmap, (uint32_t)(n - s) * 4);
+        const BufRsrc rc = buf_rsrc(c2f, it.leaf ? 0u : (uint32_t)(2 * n) * 16 * ES);
+        BufCx<T>::load(rd, (uint32_t)erow * ES, e_d.re, e_d.im);
+        e_pm = buf_load_i32(rp, (uint32_t)(erow - s) * 4);
+        BufCx<T>::load(rc, (uint32_t)(erow * 16 + er) * ES, e_a.re, e_a.im);
+        BufCx<T>::load(rc, (uint32_t)((n + erow) * 16 + er) * ES, e_b.re, e_b.im);
+    }
     // lane operands: A(row, k) = G(blk + 16 t + li, c + 4 q + lk) and
     // B(k, rhs) = v_S(c + 4 q + lk, li)
     T gre[RT][4], gim[RT][4];
@@ -567,7 +664,8 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // overlap each other's products (a few waves per SIMD at this register
     // count); a load past the contraction's end reads zeros.  (Two chunks in
     // flight per wave, as in the backward pass, measured slower here.)
-    for (int ch = wave; ch < nch; ch += NW) {
+    const int per = (nch + S - 1) / S, c_lo = z * per, c_hi = min(nch, c_lo + per);
+    for (int ch = c_lo + wave; ch < c_hi; ch += NW) {
         load(kb + ch * KC, gre, gim, vre, vim);
         products(gre, gim, vre, vim);
     }
@@ -578,43 +676,81 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
             aim[t][0] += aim[t][SPLIT - 1];
         }
     }
-    // sum the waves' partial blocks in LDS, one wave at a time
-    for (int w = 0; w < NW; ++w) {
-        if (wave == w) {
+    // sum the waves' partial blocks
+    {
+        __shared__ T Pre[WaveSum<T, RT, NW>::PLEN], Pim[WaveSum<T, RT, NW>::PLEN];
+        V4 acr[RT], aci[RT];
 #pragma unroll
-            for (int t = 0; t < RT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * t + mfma_out_row<T>(lk, r);
-                    if (w == 0) {
-                        Yre[row][li] = are[t][0][r];
-                        Yim[row][li] = aim[t][0][r];
-                    } else {
-                        Yre[row][li] += are[t][0][r];
-                        Yim[row][li] += aim[t][0][r];
-                    }
-                }
+        for (int t = 0; t < RT; ++t) {
+            acr[t] = are[t][0];
+            aci[t] = aim[t][0];
         }
-        __syncthreads();
+        sum_wave_blocks<T, RT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
+    }
+    if constexpr (SK) {
+        Cx<T>* pp = A.part + ((int64_t)(ib * gridDim.y + grp) * S + z) * (256 * RT);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int e = tid + 256 * t;
+            pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
+        }
+        return;
     }
     // thread tid < 256: right-hand side rhs0 + tid % 16 of rows blk + tid / 16 + 16 t
     // (a row's 16 right-hand sides are one contiguous block)
     const int r = tid & 15;
     if (tid >= 256 || rhs0 + r >= A.nrhs) return;
-    Cx<T>* xm = A.xmid + grp * A.gs_x;
+    Cx<T>* xs = A.xu + grp * A.gs_u + (int64_t)(it.xu - s) * 16;  // the front's [x_S; -x_U]
     Cx<T>* c2g = A.c2 + grp * A.gs_c2;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int lrow = (tid >> 4) + 16 * t, row = it.blk + lrow;
         if (row >= n) continue;
         const Cx<T> y = cx<T>(Yre[lrow][r], Yim[lrow][r]);
-        if (row < s) {
-            xm[(int64_t)(it.start + row) * 16 + r] = y * A.dinv[it.start + row];
+        if constexpr (RT == 1) {
+            if (row < s)
+                xs[(int64_t)row * 16 + r] = y * e_d;
+            else
+                c2g[(int64_t)(it.push + e_pm) * 16 + r] = (e_a + e_b) - y;
         } else {
-            const Cx<T> pre = it.leaf ? cx<T>(0, 0) : c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
-            c2g[(int64_t)(it.push + A.pmap[it.pmap + row - s]) * 16 + r] = pre - y;
+            fwd_store(A, it, grp, row, r, y);
         }
     }
+}
+
+// y[t] := sum over the S partial blocks at pp (1024 entries apart) of entry
+// tid + 256 t, added in split order; the loads of eight splits are issued
+// before their sums.
+template <typename T>
+__device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) y[t] = cx<T>(0, 0);
+    for (int z0 = 0; z0 < S; z0 += 8) {
+        Cx<T> v[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)  // unconditional loads (clamped split, dropped below)
+                v[u][t] = pp[(int64_t)min(z0 + u, S - 1) * 1024 + tid + 256 * t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (z0 + u < S) y[t] = y[t] + v[u][t];
+    }
+}
+
+// Sums the nsplit partial blocks of each 64-row item (in split order, so the
+// result does not depend on timing) and applies the forward epilogue.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_fin(PassArgs<T> A) {
+    const SolveItem it = A.items[blockIdx.x];
+    const int grp = blockIdx.y, tid = threadIdx.x, r = tid & 15, S = A.nsplit;
+    if ((int64_t)grp * 16 + r >= A.nrhs) return;
+    Cx<T> y[4];
+    split_sums(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * 1024, S, tid, y);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) fwd_store(A, it, grp, it.blk + ((tid + 256 * t) >> 4), r, y[t]);
 }
 
 // Row-split form of the forward matrix-core pass for fronts whose v_S fits
@@ -743,7 +879,7 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
     a0 += a1;
     b0 += b1;
     if (rhs0 + li >= A.nrhs) return;
-    Cx<T>* xm = A.xmid + grp * A.gs_x;
+    Cx<T>* xs = A.xu + grp * A.gs_u + (int64_t)(it.xu - s) * 16;  // the front's [x_S; -x_U]
     Cx<T>* c2g = A.c2 + grp * A.gs_c2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -751,7 +887,7 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         if (row >= n) continue;
         const Cx<T> y = cx<T>(a0[r], b0[r]);
         if (row < s)
-            xm[(int64_t)(it.start + row) * 16 + li] = y * Dv[lrow];
+            xs[(int64_t)row * 16 + li] = y * Dv[lrow];
         else
             c2g[(int64_t)(it.push + PM[lrow]) * 16 + li] = E[lrow * 16 + li] - y;
     }
@@ -772,11 +908,52 @@ size_t fwd_rs_lds_bytes(int smax) {
 // rows i0 + 4 lk + m: a lane then reads four consecutive rows of one column
 // of G in one access, and sixteen lanes read one 128-byte run of [x_S; -x_U],
 // so both operands come straight from memory, with no LDS staging.
-template <typename T, int CT, int NW>
+// The backward epilogue: x_S(j) of right-hand side r of the group goes to
+// the children's update-set values (stored negated: a front's vector holds
+// [x_S; -x_U]) ...
+template <typename T>
+__device__ inline void bwd_push(const PassArgs<T>& A, const SolveItem& it, int grp, int j, int r, Cx<T> x) {
+    Cx<T>* xu = A.xu + grp * A.gs_u;
+    if (it.cxu0 >= 0) {
+        const int o0 = A.cmap[it.moff + j];
+        if (o0 >= 0) xu[(int64_t)(it.cxu0 + o0) * 16 + r] = -x;
+    }
+    if (it.cxu1 >= 0) {
+        const int o1 = A.cmap[it.moff + it.n + j];
+        if (o1 >= 0) xu[(int64_t)(it.cxu1 + o1) * 16 + r] = -x;
+    }
+}
+// ... and (right-hand side orr) to the panel's planes of the padded grid:
+// stored (mode 0, with the coupling into the next plane when asked) or
+// subtracted (mode 1).
+template <typename T>
+__device__ inline void bwd_grid(const PassArgs<T>& A, const SolveItem& it, int j, int64_t orr, Cx<T> x) {
+    const int b = pivot_box(it, A.Nx, A.NxNy, j);
+    const int q = b / A.NxNy, lat = b - q * A.NxNy;
+    if (q < A.ga) return;
+    Cx<double>* up = A.dst + orr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
+    const Cx<double> xd = ccast<double>(x);
+    if (A.mode == 0) {
+        *up = xd;
+        if (A.couple && q == A.nz - 1) up[A.NxNy] = up[A.NxNy] - plane_coupling(A, lat) * xd;
+    } else {
+        *up = *up - xd;
+    }
+}
+
+// SK: split contraction.  Workgroup b takes item b / nsplit and the
+// (b mod nsplit)-th share of its row chunks (and of the front's hand-on),
+// and stores its partial block instead of the epilogue (k_bwd_fin sums the
+// shares).
+template <typename T, int CT, int NW, bool SK = false>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    const SolveItem it = A.items[blockIdx.x];  // items of 16 CT columns
+    static_assert(!SK || (CT == 4 && NW == 4), "split contraction: 64-column items, 4 waves");
+    const int S = SK ? A.nsplit : 1;
+    const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
+    const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    const SolveItem it = A.items[ib];  // items of 16 CT columns
     if (leaf_aux_block(it, A.ga, it.blk, 16 * CT)) return;
     const int n = it.n, s = it.s;
     const int grp = blockIdx.y;
@@ -785,16 +962,44 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     const int li = lane & 15, lk = lane >> 4;
     const int c0 = it.blk;
     __shared__ T Yre[16 * CT][17], Yim[16 * CT][17];  // the waves' partial blocks, summed [column][rhs]
+    // the front's [x_S; -x_U]: x_S from the forward pass, -x_U from the
+    // parent's backward pass (entry i at xsu + 16 i, the x_U part at xuf)
     Cx<T>* xu = A.xu + grp * A.gs_u;
-    const Cx<T>* xm = A.xmid + grp * A.gs_x + (int64_t)it.start * 16;
+    const Cx<T>* xsu = xu + (int64_t)(it.xu - s) * 16;
     const Cx<T>* xuf = xu + (int64_t)it.xu * 16;
+    // With one column tile, the epilogue's operands that do not depend on the
+    // products -- the children's positions of the block's pivots and the
+    // padded grid's old value (subtracted from in mode 1, the next plane's
+    // in mode 0 with the coupling) -- are loaded first and unconditionally
+    // (bounded descriptor, or the grid's base address where nothing is read
+    // back), so they arrive during the products.
+    int e_o0 = -1, e_o1 = -1;
+    Cx<double> e_old = cx<double>(0, 0);
+    Cx<double>* e_up = nullptr;
+    int e_q = -1, e_lat = 0;
+    if constexpr (CT == 1) {
+        const BufRsrc rm = buf_rsrc(A.cmap + it.moff, (uint32_t)(2 * n) * 4);
+        const int jc = c0 + (tid >> 4) % 16;
+        e_o0 = buf_load_i32(rm, (uint32_t)jc * 4);
+        e_o1 = buf_load_i32(rm, (uint32_t)(n + jc) * 4);
+        const int j = c0 + (tid & 15);
+        const int64_t orr = rhs0 + ((tid >> 4) & 15);
+        const int b = pivot_box(it, A.Nx, A.NxNy, j);
+        e_q = b / A.NxNy;
+        e_lat = b - e_q * A.NxNy;
+        const bool ok = j < s && orr < A.nrhs && e_q >= A.ga;
+        e_up = A.dst + orr * A.ld + (int64_t)(A.lo + e_q - A.ga - A.plane0) * A.NxNy + e_lat;
+        const bool rd = ok && (A.mode != 0 || (A.couple && e_q == A.nz - 1));
+        const Cx<double>* src = rd ? (A.mode != 0 ? e_up : e_up + A.NxNy) : A.dst;
+        e_old = *src;
+    }
     // The update-set values go on to the children.  The front's column blocks
     // share its u rows, sixteen threads per row (one per right-hand side),
     // and each thread issues the loads of four rows before their stores, so
     // the map lookups do not form one long chain of memory round trips.
     if (it.cxu0 >= 0 || it.cxu1 >= 0) {
         const int u = n - s;
-        const int nb = (s + 16 * CT - 1) / (16 * CT), b = c0 / (16 * CT);
+        const int nb = (s + 16 * CT - 1) / (16 * CT) * S, b = c0 / (16 * CT) * S + z;
         const int per = (u + nb - 1) / nb;
         const int i_lo = s + b * per, i_hi = min(n, i_lo + per);
         constexpr int ROWS = 4 * NW;  // rows per pass of the workgroup
@@ -817,16 +1022,13 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             }
         }
     }
-    // Operand descriptors cut at the front's ends: G's s columns, x_S's s
-    // entries and x_U's u entries.  Loads past them read zeros, so no chunk
-    // tests bounds: [x_S; -x_U](i) is the x_S load minus the x_U load (one of
-    // them reads past its end, the x_U offset of a pivot row being
-    // negative), zero past row n; columns past s give results never stored.
+    // Operand descriptors cut at the front's ends: G's s columns and the n
+    // entries of [x_S; -x_U].  Loads past them read zeros, so no chunk tests
+    // bounds; columns past s give results never stored.
     constexpr uint32_t ES = sizeof(Cx<T>);
     const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)s * n * ES);
-    const BufRsrc rs = buf_rsrc(xm, (uint32_t)s * 16 * ES);
-    const BufRsrc ru = buf_rsrc(xuf, (uint32_t)(n - s) * 16 * ES);
-    T gre[CT][4], gim[CT][4], sre[4], sim[4], ure[4], uim[4];
+    const BufRsrc rs = buf_rsrc(xsu, (uint32_t)n * 16 * ES);
+    T gre[CT][4], gim[CT][4], sre[4], sim[4];
     // with one column tile, four accumulator chains instead of two (as in k_fwd_mm)
     constexpr int SPLIT = CT == 1 ? 2 : 1;
     V4 are[CT][SPLIT], aim[CT][SPLIT];
@@ -839,7 +1041,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         }
     const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
     // this lane's four rows i0 .. i0 + 3 of chunk ch
-    auto load = [&](int ch, T(&gr)[CT][4], T(&gi)[CT][4], T(&sr)[4], T(&si)[4], T(&ur)[4], T(&ui)[4]) {
+    auto load = [&](int ch, T(&gr)[CT][4], T(&gi)[CT][4], T(&sr)[4], T(&si)[4]) {
         const int i0 = c0 + ch * KC + 4 * lk;
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
@@ -848,16 +1050,12 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             for (int m = 0; m < 4; ++m) BufCx<T>::load(rg, off + m * ES, gr[t][m], gi[t][m]);
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            BufCx<T>::load(rs, (uint32_t)((i0 + m) * 16 + li) * ES, sr[m], si[m]);
-            BufCx<T>::load(ru, (uint32_t)((i0 + m - s) * 16 + li) * ES, ur[m], ui[m]);
-        }
+        for (int m = 0; m < 4; ++m) BufCx<T>::load(rs, (uint32_t)((i0 + m) * 16 + li) * ES, sr[m], si[m]);
     };
-    auto products = [&](const T(&gr)[CT][4], const T(&gi)[CT][4], const T(&sr)[4], const T(&si)[4],
-                        const T(&ur)[4], const T(&ui)[4]) {
+    auto products = [&](const T(&gr)[CT][4], const T(&gi)[CT][4], const T(&sr)[4], const T(&si)[4]) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const T br = sr[m] - ur[m], bi = si[m] - ui[m];
+            const T br = sr[m], bi = si[m];
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
                 are[t][0] = mfma4(gr[t][m], br, are[t][0]);
@@ -873,17 +1071,18 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     // with one column tile each wave issues two chunks' loads before their
     // products (loads past the end read zeros), as in k_fwd_mm
     if constexpr (CT == 1) {
-        T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4], ure2[4], uim2[4];
+        T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4];
         for (int ch = wave; ch < nch; ch += 2 * NW) {
-            load(ch, gre, gim, sre, sim, ure, uim);
-            load(ch + NW, gre2, gim2, sre2, sim2, ure2, uim2);
-            products(gre, gim, sre, sim, ure, uim);
-            products(gre2, gim2, sre2, sim2, ure2, uim2);
+            load(ch, gre, gim, sre, sim);
+            load(ch + NW, gre2, gim2, sre2, sim2);
+            products(gre, gim, sre, sim);
+            products(gre2, gim2, sre2, sim2);
         }
     } else {
-        for (int ch = wave; ch < nch; ch += NW) {
-            load(ch, gre, gim, sre, sim, ure, uim);
-            products(gre, gim, sre, sim, ure, uim);
+        const int per = (nch + S - 1) / S, c_lo = z * per, c_hi = min(nch, c_lo + per);
+        for (int ch = c_lo + wave; ch < c_hi; ch += NW) {
+            load(ch, gre, gim, sre, sim);
+            products(gre, gim, sre, sim);
         }
     }
     if (SPLIT == 2) {
@@ -893,24 +1092,25 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             aim[t][0] += aim[t][SPLIT - 1];
         }
     }
-    // sum the waves' partial blocks in LDS, one wave at a time
-    for (int w = 0; w < NW; ++w) {
-        if (wave == w) {
+    // sum the waves' partial blocks
+    {
+        __shared__ T Pre[WaveSum<T, CT, NW>::PLEN], Pim[WaveSum<T, CT, NW>::PLEN];
+        V4 acr[CT], aci[CT];
 #pragma unroll
-            for (int t = 0; t < CT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int col = 16 * t + mfma_out_row<T>(lk, r);
-                    if (w == 0) {
-                        Yre[col][li] = are[t][0][r];
-                        Yim[col][li] = aim[t][0][r];
-                    } else {
-                        Yre[col][li] += are[t][0][r];
-                        Yim[col][li] += aim[t][0][r];
-                    }
-                }
+        for (int t = 0; t < CT; ++t) {
+            acr[t] = are[t][0];
+            aci[t] = aim[t][0];
         }
-        __syncthreads();
+        sum_wave_blocks<T, CT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
+    }
+    if constexpr (SK) {
+        Cx<T>* pp = A.part + ((int64_t)(ib * gridDim.y + grp) * S + z) * (256 * CT);
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            const int e = tid + 256 * t;
+            pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
+        }
+        return;
     }
     if (tid >= 256) return;
 #pragma unroll
@@ -920,13 +1120,11 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             const int jl = 16 * t + (tid >> 4), r = tid & 15, j = c0 + jl;
             if (j < s && rhs0 + r < A.nrhs) {
                 const Cx<T> x = cx<T>(Yre[jl][r], Yim[jl][r]);
-                if (it.cxu0 >= 0) {
-                    const int o0 = A.cmap[it.moff + j];
-                    if (o0 >= 0) xu[(int64_t)(it.cxu0 + o0) * 16 + r] = x;
-                }
-                if (it.cxu1 >= 0) {
-                    const int o1 = A.cmap[it.moff + n + j];
-                    if (o1 >= 0) xu[(int64_t)(it.cxu1 + o1) * 16 + r] = x;
+                if constexpr (CT == 1) {
+                    if (it.cxu0 >= 0 && e_o0 >= 0) xu[(int64_t)(it.cxu0 + e_o0) * 16 + r] = -x;
+                    if (it.cxu1 >= 0 && e_o1 >= 0) xu[(int64_t)(it.cxu1 + e_o1) * 16 + r] = -x;
+                } else {
+                    bwd_push(A, it, grp, j, r, x);
                 }
             }
         }
@@ -935,17 +1133,49 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         const int64_t orr = rhs0 + (tid >> 4);
         if (j >= s || orr >= A.nrhs) continue;
         const Cx<T> x = cx<T>(Yre[jl][tid >> 4], Yim[jl][tid >> 4]);
-        const int b = pivot_box(it, A.Nx, A.NxNy, j);
-        const int q = b / A.NxNy, lat = b - q * A.NxNy;
-        if (q < A.ga) continue;
-        Cx<double>* up = A.dst + orr * A.ld + (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
         const Cx<double> xd = ccast<double>(x);
-        if (A.mode == 0) {
-            *up = xd;
-            if (A.couple && q == A.nz - 1) up[A.NxNy] = up[A.NxNy] - plane_coupling(A, lat) * xd;
+        if constexpr (CT == 1) {
+            if (e_q < A.ga) continue;
+            if (A.mode == 0) {
+                *e_up = xd;
+                if (A.couple && e_q == A.nz - 1) e_up[A.NxNy] = e_old - plane_coupling(A, e_lat) * xd;
+            } else {
+                *e_up = e_old - xd;
+            }
         } else {
-            *up = *up - xd;
+            bwd_grid(A, it, j, orr, x);
         }
+    }
+}
+
+// Sums the nsplit partial blocks of each 64-column item (in split order) and
+// applies the backward epilogue.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_fin(PassArgs<T> A) {
+    const SolveItem it = A.items[blockIdx.x];
+    if (leaf_aux_block(it, A.ga, it.blk, 64)) return;
+    const int grp = blockIdx.y, tid = threadIdx.x, S = A.nsplit;
+    const int64_t rhs0 = (int64_t)grp * 16;
+    __shared__ T Yre[64][17], Yim[64][17];
+    Cx<T> y[4];
+    split_sums(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * 1024, S, tid, y);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int e = tid + 256 * t;
+        Yre[e >> 4][e & 15] = y[t].re;
+        Yim[e >> 4][e & 15] = y[t].im;
+    }
+    __syncthreads();
+    const int s = it.s, c0 = it.blk;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        {
+            const int jl = 16 * t + (tid >> 4), r = tid & 15, j = c0 + jl;
+            if (j < s && rhs0 + r < A.nrhs) bwd_push(A, it, grp, j, r, cx<T>(Yre[jl][r], Yim[jl][r]));
+        }
+        const int jl = 16 * t + (tid & 15), j = c0 + jl;
+        const int64_t orr = rhs0 + (tid >> 4);
+        if (j < s && orr < A.nrhs) bwd_grid(A, it, j, orr, cx<T>(Yre[jl][tid >> 4], Yim[jl][tid >> 4]));
     }
 }
 
@@ -1284,64 +1514,62 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cfg, int nmax, hipStream_t 
     bwd_pick<T, 0>(A, nwork, cfg, nmax, st);
 }
 
-// Waves per workgroup of the matrix-core passes: 4, or the wide form when a
-// launch has fewer than MM_WIDE_BELOW workgroups (LDS per wave and registers
-// bound it: 8 forward, 16 / 4 backward in complex64 / complex128).
-constexpr int MM_WIDE_BELOW = 512;
-template <typename T> struct MmWide {
-    static constexpr int fwd = 8, bwd = sizeof(T) == 4 ? 16 : 4;
-};
-
 template <typename T>
 void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st) {
     if (A.naux <= 0) return;
     const dim3 grid((A.naux + 63) / 64, (A.nrhs + 15) / 16);
     HSW_LAUNCH(k_rhs_scatter<T>, grid, dim3(256), 0, st, A);
 }
+// Forms of the forward matrix-core pass: 0 / 3: 64 rows per workgroup, 4 /
+// 8 waves splitting the contraction; 1 / 4: 16 rows, 4 / 8 waves; 2:
+// row-split (64 rows, needs fwd_rs_lds_bytes(smax) of LDS); 5: 64 rows with
+// each item's contraction split over A.nsplit workgroups, then a finishing
+// launch (A.part holds the partial blocks).
 template <typename T>
-void launch_fwd_mm(const PassArgs<T>& A, int nwork, int rt, hipStream_t st) {
-    if (nwork <= 0) return;
-    const dim3 grid(nwork, (A.nrhs + 15) / 16);
-    constexpr int W = MmWide<T>::fwd;
-    const bool wide = (int)(grid.x * grid.y) < MM_WIDE_BELOW;
-    if (rt == 4) {
-        if (wide)
-            HSW_LAUNCH((k_fwd_mm<T, 4, W>), grid, dim3(64 * W), 0, st, A);
-        else
-            HSW_LAUNCH((k_fwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A);
-    } else {
-        if (wide)
-            HSW_LAUNCH((k_fwd_mm<T, 1, W>), grid, dim3(64 * W), 0, st, A);
-        else
-            HSW_LAUNCH((k_fwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A);
-    }
-}
-template <typename T>
-void launch_fwd_rs(const PassArgs<T>& A, int nwork, int smax, hipStream_t st) {
+void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
     constexpr int FP = sizeof(T) == 4 ? 4 : 2;
-    HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A);
+    switch (form) {
+    case 0: HSW_LAUNCH((k_fwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A); break;
+    case 1: HSW_LAUNCH((k_fwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A); break;
+    case 2: HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A); break;
+    case 3: HSW_LAUNCH((k_fwd_mm<T, 4, 8>), grid, dim3(512), 0, st, A); break;
+    case 4: HSW_LAUNCH((k_fwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
+    default: {
+        const dim3 gs(nwork * A.nsplit, grid.y);
+        HSW_LAUNCH((k_fwd_mm<T, 4, 4, true>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH(k_fwd_fin<T>, grid, dim3(256), 0, st, A);
+    }
+    }
 }
+// Forms of the backward matrix-core pass: 0: 64 columns per workgroup, 4
+// waves; 1 / 2 / 3: 16 columns, 4 / 8 / 16 waves (complex128: 8 at most,
+// for registers); 4: 64 columns with each item's contraction split over
+// A.nsplit workgroups, then a finishing launch.
 template <typename T>
-void launch_bwd_mm(const PassArgs<T>& A, int nwork, int ct, hipStream_t st) {
+void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
     if (nwork <= 0) return;
     const dim3 grid(nwork, (A.nrhs + 15) / 16);
-    constexpr int W = MmWide<T>::bwd;
-    if (ct == 4)
-        HSW_LAUNCH((k_bwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A);
-    else if ((int)(grid.x * grid.y) < MM_WIDE_BELOW)
-        HSW_LAUNCH((k_bwd_mm<T, 1, W>), grid, dim3(64 * W), 0, st, A);
-    else
-        HSW_LAUNCH((k_bwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A);
+    constexpr int W16 = sizeof(T) == 4 ? 16 : 8;
+    switch (form) {
+    case 0: HSW_LAUNCH((k_bwd_mm<T, 4, 4>), grid, dim3(256), 0, st, A); break;
+    case 1: HSW_LAUNCH((k_bwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A); break;
+    case 2: HSW_LAUNCH((k_bwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
+    case 3: HSW_LAUNCH((k_bwd_mm<T, 1, W16>), grid, dim3(64 * W16), 0, st, A); break;
+    default: {
+        const dim3 gs(nwork * A.nsplit, grid.y);
+        HSW_LAUNCH((k_bwd_mm<T, 4, 4, true>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH(k_bwd_fin<T>, grid, dim3(256), 0, st, A);
+    }
+    }
 }
 
 #define HSW_INST(T)                                                                          \
     template void launch_tri<T>(const PassArgs<T>&, int, int, bool, hipStream_t);           \
     template void launch_fwd<T>(const PassArgs<T>&, int, int, int, int, hipStream_t);       \
     template void launch_bwd<T>(const PassArgs<T>&, int, int, int, hipStream_t);            \
-    template void launch_fwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
-    template void launch_fwd_rs<T>(const PassArgs<T>&, int, int, hipStream_t);              \
+    template void launch_fwd_mm<T>(const PassArgs<T>&, int, int, int, hipStream_t);         \
     template size_t fwd_rs_lds_bytes<T>(int);                                                \
     template void launch_rhs_scatter<T>(const PassArgs<T>&, hipStream_t);                    \
     template void launch_bwd_mm<T>(const PassArgs<T>&, int, int, hipStream_t);              \
