@@ -65,6 +65,15 @@ __device__ inline int leaf_first_live(const PassArgs<T>& A, const SolveItem& it)
 __device__ inline bool leaf_aux_block(const SolveItem& it, int ga, int c0, int cb) {
     return it.leaf && c0 + cb <= ga * (it.cellw >> 16);
 }
+// The pivots of a leaf on auxiliary planes (0 for other fronts).  In the
+// matrix-core passes their x_S (exact zeros in the forward pass: zero
+// right-hand side, no children) is neither stored nor read: the backward
+// pass of a leaf starts its contraction at the first pivot past them, since
+// the rows it skips meet only columns the upper triangle of L_F^{-1} zeros
+// or columns whose results are not kept.
+__device__ inline int leaf_aux_rows(const SolveItem& it, int ga) {
+    return it.leaf ? ga * (it.cellw >> 16) : 0;
+}
 
 // Loads in flight per thread: the G entries a thread consumes are issued in
 // rounds of QL before the previous round is used.
@@ -120,10 +129,10 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
             dv = A.dinv[it.start + row];
         } else {
             pm = A.pmap[it.pmap + row - s];
-            const bool h0 = !it.leaf && map0[row] >= 0, h1 = !it.leaf && map1[row] >= 0;
+            const bool h0 = map0[row] >= 0, h1 = map1[row] >= 0;
 #pragma unroll
             for (int r = 0; r < RC; ++r)
-                if (r < nr && !it.leaf) {
+                if (r < nr) {
                     const Cx<T>* cc = A.c2 + (int64_t)(rhs0 + r) * A.c2ld + it.c2;
                     const Cx<T> a0 = cc[row], a1 = cc[n + row];
                     pre[r] = keep(h0, a0) + keep(h1, a1);
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
     for (int k = k0 + tid; k < s; k += NT) {
         const int b = pivot_box(it, A.Nx, A.NxNy, k);
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
-        const bool h0 = !it.leaf && map0[k] >= 0, h1 = !it.leaf && map1[k] >= 0;
+        const bool h0 = map0[k] >= 0, h1 = map1[k] >= 0;
         bool live;
         int64_t gi;
         Cx<double> cf = cx<double>(1, 0);
@@ -152,11 +161,9 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
             Cx<T> v = cx<T>(0, 0);
             if (r < nr) {
                 const int64_t rr = rhs0 + r;
-                if (!it.leaf) {
-                    const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
-                    const Cx<T> a0 = cc[k], a1 = cc[n + k];
-                    v = keep(h0, a0) + keep(h1, a1);
-                }
+                const Cx<T>* cc = A.c2 + rr * A.c2ld + it.c2;
+                const Cx<T> a0 = cc[k], a1 = cc[n + k];
+                v = keep(h0, a0) + keep(h1, a1);
                 if (live) {
                     const Cx<double> x = A.src[rr * A.ld + gi];
                     v = v + ccast<T>(A.mode == 0 ? x : cf * x);
@@ -279,6 +286,16 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
         if (it.cxu0 >= 0) o0 = A.cmap[it.moff + jl];
         if (it.cxu1 >= 0) o1 = A.cmap[it.moff + n + jl];
     }
+    // the padded grid's old values the epilogue updates (mode 1: the pivot's
+    // own entry; mode 0 with the coupling: the next plane's), read now so
+    // that they arrive during the products
+    Cx<double> oold[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        oold[r] = cx<double>(0, 0);
+        if (own && oplane && r < nr && (A.mode != 0 || onext))
+            oold[r] = A.dst[(rhs0 + r) * A.ld + ogi + (A.mode != 0 ? 0 : A.NxNy)];
+    }
     // [x_S; -x_U] of this front (loads only: nothing in this loop waits on a
     // loaded value before the next load)
     for (int i = c0 + tid; i < n; i += NT) {
@@ -394,9 +411,9 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
                     const Cx<double> xd = ccast<double>(x);
                     if (A.mode == 0) {
                         *up = xd;
-                        if (onext) up[A.NxNy] = up[A.NxNy] - ocf * xd;
+                        if (onext) up[A.NxNy] = oold[r] - ocf * xd;
                     } else {
-                        *up = *up - xd;
+                        *up = oold[r] - xd;
                     }
                 }
             }
@@ -552,7 +569,8 @@ __device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int 
     const int n = it.n, s = it.s;
     if (row >= n) return;
     if (row < s) {
-        A.xu[grp * A.gs_u + (int64_t)(it.xu - s + row) * 16 + r] = y * A.dinv[it.start + row];
+        if (row >= leaf_aux_rows(it, A.ga))
+            A.xu[grp * A.gs_u + (int64_t)(it.xu - s + row) * 16 + r] = y * A.dinv[it.start + row];
     } else {
         const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
         const Cx<T> pre = it.leaf ? cx<T>(0, 0) : c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
@@ -572,6 +590,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
     const int z = SK ? (int)blockIdx.x - ib * S : 0;
     const SolveItem it = A.items[ib];  // items of 16 RT rows
+    if (it.blk + 16 * RT <= leaf_aux_rows(it, A.ga)) return;  // nothing to store
     const int n = it.n, s = it.s;
     const int grp = blockIdx.y;
     const int64_t rhs0 = (int64_t)grp * 16;
@@ -708,10 +727,11 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         if (row >= n) continue;
         const Cx<T> y = cx<T>(Yre[lrow][r], Yim[lrow][r]);
         if constexpr (RT == 1) {
-            if (row < s)
-                xs[(int64_t)row * 16 + r] = y * e_d;
-            else
+            if (row < s) {
+                if (row >= leaf_aux_rows(it, A.ga)) xs[(int64_t)row * 16 + r] = y * e_d;
+            } else {
                 c2g[(int64_t)(it.push + e_pm) * 16 + r] = (e_a + e_b) - y;
+            }
         } else {
             fwd_store(A, it, grp, row, r, y);
         }
@@ -769,6 +789,7 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
     constexpr uint32_t ES = sizeof(Cx<T>);
     extern __shared__ unsigned char smem_raw[];
     const SolveItem it = A.items[blockIdx.x];  // items of 64 rows
+    if (it.blk + ROWS <= leaf_aux_rows(it, A.ga)) return;  // nothing to store
     const int n = it.n, s = it.s;
     const int grp = blockIdx.y;
     const int64_t rhs0 = (int64_t)grp * 16;
@@ -886,10 +907,11 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         const int lrow = 16 * wave + mfma_out_row<T>(lk, r), row = it.blk + lrow;
         if (row >= n) continue;
         const Cx<T> y = cx<T>(a0[r], b0[r]);
-        if (row < s)
-            xs[(int64_t)row * 16 + li] = y * Dv[lrow];
-        else
+        if (row < s) {
+            if (row >= leaf_aux_rows(it, A.ga)) xs[(int64_t)row * 16 + li] = y * Dv[lrow];
+        } else {
             c2g[(int64_t)(it.push + PM[lrow]) * 16 + li] = E[lrow * 16 + li] - y;
+        }
     }
 }
 
@@ -1039,10 +1061,13 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             are[t][h] = V4{0, 0, 0, 0};
             aim[t][h] = V4{0, 0, 0, 0};
         }
-    const int nch = (n - c0 + KC - 1) / KC;  // rows above the block's first column are zeros of G_TL
+    // rows above the block's first column are zeros of G_TL; a leaf's
+    // auxiliary rows are skipped (leaf_aux_rows)
+    const int ib0 = max(c0, leaf_aux_rows(it, A.ga));
+    const int nch = (n - ib0 + KC - 1) / KC;
     // this lane's four rows i0 .. i0 + 3 of chunk ch
     auto load = [&](int ch, T(&gr)[CT][4], T(&gi)[CT][4], T(&sr)[4], T(&si)[4]) {
-        const int i0 = c0 + ch * KC + 4 * lk;
+        const int i0 = ib0 + ch * KC + 4 * lk;
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const uint32_t off = ((uint32_t)(c0 + 16 * t + li) * n + (uint32_t)i0) * ES;
