@@ -138,14 +138,17 @@ def converged(info):
     return info["status"] == "HSW_OK" and max(info["relres"]) < RTOL
 
 
-def run_path(Ps, bs, prec, steps, warmup, measure=False, rhs_group=0):
+def run_path(Ps, bs, prec, steps, warmup, measure=False, rhs_group=0, options=None):
     """Time whole solves of every problem of Ps in one context.  rhs_group > 0
     solves the right-hand sides in groups of that many columns (bounds the
     GMRES workspace of very large problems).  Every timed step's status and
-    residuals are kept: the rate counts only if all of them converged."""
+    residuals are kept: the rate counts only if all of them converged.
+    options: context options set before the first step."""
     import torch
     from paper_1204_0111_amd.hsweep import Solver
     S = Solver(Ps, precision=prec)
+    for key, val in (options or {}).items():
+        S.set_option(key, val)
     c_dev = [torch.as_tensor(P["c"]).to("cuda") for P in Ps]
     b_dev = [torch.as_tensor(b).to("cuda") for b in bs]
     nr = max(b.shape[0] for b in bs)
@@ -335,7 +338,7 @@ def cpu_baseline(name, iters, max_workers=None):
 
 # ------------------------------------------------------------------ records
 def measure_workload(name, steps, warmup, comparator=True, bf16=False, roofline=False, rhs_group=0,
-                     log=None):
+                     log=None, device_test=False):
     Ps, bs = workload(name)
     nrhs = max(b.shape[0] for b in bs)
     rec = dict(config=describe(Ps))
@@ -351,6 +354,17 @@ def measure_workload(name, steps, warmup, comparator=True, bf16=False, roofline=
         rec["bf16"] = run_path(Ps, bs, "c64_bf16", steps, warmup, rhs_group=rhs_group)
         if log:
             log("c64_bf16 %s" % name, rec["bf16"])
+    if device_test:
+        # GMRES with the convergence test on the device, one read per cycle,
+        # the cycle's steps issued one by one or replayed from a capture
+        rec["device_test"] = {}
+        for graph in (0, 1):
+            r = run_path(Ps, bs, "c64", steps, warmup, rhs_group=rhs_group,
+                         options=dict(gmres_device_test=1, graph=graph))
+            rec["device_test"]["captured" if graph else "issued"] = dict(
+                (k, r[k]) for k in ("value", "ms_per_step", "t_solve_ms", "converged", "iters"))
+            if log:
+                log("c64 device test graph=%d %s" % (graph, name), r)
     if comparator:
         try:
             rec["c128"] = run_path(Ps, bs, "c128", steps, warmup, rhs_group=rhs_group)
@@ -390,6 +404,8 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="worker processes of the oracle pool (default: the CPU share, at most 8)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-device-test", action="store_true",
+                    help="skip the GMRES variant with the convergence test on the device")
     ap.add_argument("--rhs-group", type=int, default=0,
                     help="solve the right-hand sides in groups of this many columns")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -416,7 +432,7 @@ def main():
         del src, dst
     head = measure_workload(args.workload, args.steps, args.warmup, comparator=not args.no_comparator,
                             bf16=not args.no_bf16, roofline=not args.no_roofline,
-                            rhs_group=args.rhs_group, log=log)
+                            rhs_group=args.rhs_group, log=log, device_test=not args.no_device_test)
     main_run, comp = head["c64"], head.get("c128")
     subs = {}
     for name in [s for s in args.sub.split(",") if s and s != args.workload]:
@@ -442,6 +458,7 @@ def main():
                 factor_bytes=main_run["factor_bytes"],
                 comparator=comp,
                 bf16_gemm_variant=head.get("bf16"),
+                gmres_device_test=head.get("device_test"),
                 speedup_vs_fp64=(main_run["value"] / comp["value"])
                 if ok and comp and comp.get("value") else None,
                 roofline=head.get("roofline"),

@@ -251,6 +251,19 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              a HIP graph captured at the first application for a (problem,
  *              right-hand-side count), on a context-owned copy of the vector;
  *              0 (default): launch its kernels one by one on the stream.
+ *   "gmres_device_test" 1: hsw_solve (GMRES(k) per right-hand side) tests
+ *              convergence on the device: after every Arnoldi step a kernel
+ *              counts the step and retires the right-hand sides whose
+ *              residual estimate fell below rtol, and once none is left a
+ *              device flag stops every later kernel of the cycle at its
+ *              first instruction.  The host issues the k steps of a cycle
+ *              without waiting and reads the counts back once per cycle,
+ *              with the residual norms.  With "graph" 1 as well, the k steps
+ *              are captured once per (problem, right-hand-side count, k) and
+ *              each cycle replays them (the context's own lane only).  The
+ *              iterates equal those of the default mode bit for bit; the
+ *              steps issued after convergence cost their launches.  0
+ *              (default): the host reads the estimates after every step.
  *   "autotune" 1 (default): at the first application for a right-hand-side
  *              group (1, 2, 3-4, 5+), time every block shape of the solve
  *              kernels per panel class and tree depth and keep the fastest;

@@ -150,6 +150,9 @@ struct PassArgs {
     // then split; a finishing launch sums them in split order
     Cx<T>* part;
     int nsplit;
+    // GMRES with the convergence test on the device: while *run is 0 (every
+    // right-hand side converged) the pass kernels return at once; NULL: always run
+    const int* run;
 };
 
 struct PanelDev {

@@ -101,6 +101,7 @@ struct SweepGraph {
     int prob = 0, nrhs = 0;
     hipGraphExec_t exec = nullptr;
     void* z = nullptr;
+    int cycle_k = 0;  // > 0: the k Arnoldi steps of a GMRES cycle (device-side test), not a sweep
 };
 
 struct ProbHost {
@@ -124,13 +125,14 @@ struct Lane {
     void *d_xmid = nullptr, *d_xu = nullptr, *d_c2 = nullptr;  // panel-solve workspace
     int nrhs_cap = 0;
     // workspace of the matrix-core passes, [entry][16] blocks per group of 16
-    // right-hand sides: x_mid, update-set values, the child-contribution
+    // right-hand sides: each front's [x_S; -x_U], the child-contribution
     // slots of every panel class (each class its own zeroed region) and the
     // right-hand side in elimination order (likewise per class)
     void *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;  // [x_S; -x_U] per front, slots, h2
     void* d_mpart = nullptr;  // partial blocks of the split-contraction forms
     int mm_groups = 0;
     std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
+    const int* run = nullptr;  // device flag the pass kernels test (GMRES cycles with the test on the device)
 };
 
 struct hsw_ctx {
@@ -201,6 +203,7 @@ struct hsw_ctx {
     bool use_graph = false;  // measured slower than stream launches for the sweep
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
+    bool gmres_device_test = false;  // GMRES: convergence tested on the device, one read per cycle
     bool bf16_mfma = true;     // HSW_C64_BF16GEMM: Schur updates on the BF16 matrix cores
     // matrix-core pass forms for every depth (-1: the tuned choice; the
     // forms of launch_fwd_mm and launch_bwd_mm)
@@ -978,6 +981,8 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         ctx->nlanes = (int)value;
     } else if (k == "block_gmres") {
         ctx->block_gmres = value != 0;
+    } else if (k == "gmres_device_test") {
+        ctx->gmres_device_test = value != 0;
     } else if (k == "bf16_mfma") {
         ctx->bf16_mfma = value != 0;
         ctx->factored = false;
@@ -1302,6 +1307,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     const PanelClass& c = ctx->classes[P.cls];
     const FrontInst& f0 = ctx->inst_h[P.inst_base];
     PassArgs<T> A{};
+    A.run = ln.run;
     A.G = (const Cx<T>*)ctx->d_G + f0.loff;
     A.dinv = (const Cx<T>*)ctx->d_dinv + f0.doff;
     A.cmap = ctx->d_cmap;
@@ -1621,7 +1627,9 @@ static hsw_status sweep_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
     if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
     if (s != HSW_OK) return s;
     const ProbHost& h = ctx->ph[prob];
-    if (r != z)
+    if (r != z && ln.run)
+        launch_copy_cols(r, z, ld, h.Npad, nrhs, ln.run, ln.st);
+    else if (r != z)
         HIPCHK(hipMemcpy2DAsync(z, 16 * ld, r, 16 * ld, 16 * h.Npad, nrhs, hipMemcpyDeviceToDevice,
                                 ln.st));
     for (int i = 0; i < h.m; ++i)
@@ -1652,7 +1660,7 @@ static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* 
     }
     SweepGraph* g = nullptr;
     for (SweepGraph& q : ctx->graphs)
-        if (q.prob == prob && q.nrhs == nrhs) g = &q;
+        if (q.prob == prob && q.nrhs == nrhs && q.cycle_k == 0) g = &q;
     if (!g) {
         SweepGraph ng;
         ng.prob = prob;
@@ -1843,6 +1851,98 @@ extern "C" hsw_status hsw_matvec(hsw_ctx* ctx, int32_t prob, const hsw_c128* x, 
 // ---------------------------------------------------------------------------
 // Flexible right-preconditioned GMRES(k) of one problem, all right-hand
 // sides advanced together; classical Gram-Schmidt applied twice.
+// The k Arnoldi steps of one GMRES cycle with the convergence test on the
+// device (k_conv after each step; every kernel stops at its start once
+// *run is 0).  With the option graph, on lane 0 and while no kernel class
+// is timed, the steps are captured once per (problem, right-hand-side
+// count, k) and replayed.
+template <typename T>
+static hsw_status gmres_cycle_device(hsw_ctx* ctx, Lane& ln, int prob, Cx<double>* V, Cx<double>* Z,
+                                     Cx<double>* H, Cx<double>* part, Cx<double>* coef, double* cs,
+                                     Cx<double>* sn, Cx<double>* g, const double* bn, double* est, double* nrm,
+                                     double* partn, int* act, int* jc, int* itd, int* run, int nrhs, int k,
+                                     const hsw_solve_opts& o) {
+    const ProbDev& Q = ctx->prob_h[prob];
+    const int64_t N = ctx->ph[prob].Npad, ld = N, vs = N * nrhs;
+    const int hld = (k + 1) * k;
+    auto steps = [&](Lane& L) -> hsw_status {
+        hipStream_t st = L.st;
+        L.run = run;
+        for (int j = 0; j < k; ++j) {
+            Cx<double>* Vj = V + (int64_t)j * vs;
+            Cx<double>* Vn = V + (int64_t)(j + 1) * vs;
+            Cx<double>* Zj = Z + (int64_t)j * vs;
+            hsw_status s = sweep_impl<T>(ctx, L, prob, Vj, Zj, nrhs, ld);
+            if (s != HSW_OK) {
+                L.run = nullptr;
+                return s;
+            }
+            timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
+                  [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st, act, run); });
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
+                            pass, st);
+                launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
+            }
+            launch_norm(Vn, ld, N, nrhs, act, partn, nrm, H + (int64_t)j * (k + 1) + j + 1, hld, st);
+            launch_scale(Vn, Vn, ld, N, nrhs, nrm, act, st);
+            launch_givens(j, k, nrhs, H, cs, sn, g, bn, est, act, st);
+            launch_conv(j, nrhs, est, o.rtol, o.maxit, act, itd, jc, run, st);
+        }
+        L.run = nullptr;
+        return HSW_OK;
+    };
+    if (&ln != &ctx->lanes[0] || !ctx->use_graph || ctx->timer.on || ctx->in_lanes) return steps(ln);
+    // workspaces and tuned shapes first: nothing may allocate or synchronise
+    // during the capture
+    hsw_status s = ensure_solve_ws<T>(ctx, ln, nrhs);
+    if (s == HSW_OK) s = tune_solve<T>(ctx, nrhs);
+    if (s != HSW_OK) return s;
+    if (!ctx->gst) {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->gst, hipStreamNonBlocking));
+        for (hipEvent_t& e : ctx->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    SweepGraph* gr = nullptr;
+    for (SweepGraph& q : ctx->graphs)
+        if (q.prob == prob && q.nrhs == nrhs && q.cycle_k == k) gr = &q;
+    if (!gr) {
+        SweepGraph ng;
+        ng.prob = prob;
+        ng.nrhs = nrhs;
+        ng.cycle_k = k;
+        Lane gl;  // lane 0's workspaces on the capture stream
+        gl.st = ctx->gst;
+        gl.d_xmid = ln.d_xmid;
+        gl.d_xu = ln.d_xu;
+        gl.d_c2 = ln.d_c2;
+        gl.nrhs_cap = ln.nrhs_cap;
+        gl.d_mxu = ln.d_mxu;
+        gl.d_mc2 = ln.d_mc2;
+        gl.d_mh2 = ln.d_mh2;
+        gl.d_mpart = ln.d_mpart;
+        gl.mm_groups = ln.mm_groups;
+        hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
+        hsw_status cs_ = HSW_OK;
+        if (e == hipSuccess) {
+            cs_ = steps(gl);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(ctx->gst, &graph);
+            if (e == hipSuccess && cs_ == HSW_OK) e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        if (cs_ != HSW_OK) return cs_;
+        if (e != hipSuccess) return fail(ctx, HSW_E_DEVICE, std::string("cycle capture: ") + hipGetErrorString(e));
+        ctx->graphs.push_back(ng);
+        gr = &ctx->graphs.back();
+    }
+    HIPCHK(hipEventRecord(ctx->gev[0], ln.st));
+    HIPCHK(hipStreamWaitEvent(ctx->gst, ctx->gev[0], 0));
+    HIPCHK(hipGraphLaunch(gr->exec, ctx->gst));
+    HIPCHK(hipEventRecord(ctx->gev[1], ctx->gst));
+    HIPCHK(hipStreamWaitEvent(ln.st, ctx->gev[1], 0));
+    return HSW_OK;
+}
+
 template <typename T>
 static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* b, Cx<double>* x,
                              int nrhs, const hsw_solve_opts& o, int* iters_out, double* relres_out) {
@@ -1857,7 +1957,7 @@ static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
     Cx<double> *V = nullptr, *Z = nullptr, *H = nullptr, *coef = nullptr, *sn = nullptr, *g = nullptr,
                *y = nullptr, *part = nullptr;
     double *cs = nullptr, *bn = nullptr, *beta = nullptr, *est = nullptr, *nrm = nullptr, *partn = nullptr;
-    int *act = nullptr, *jc = nullptr;
+    int *act = nullptr, *jc = nullptr, *itd = nullptr, *run = nullptr;
     auto cleanup = [&]() {};  // the workspace stays with the context
 #define GCHK(expr)                                                                     \
     do {                                                                               \
@@ -1870,17 +1970,19 @@ static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
     {
         void** slots[] = {(void**)&V, (void**)&Z, (void**)&H, (void**)&coef, (void**)&sn, (void**)&g,
                           (void**)&y, (void**)&part, (void**)&cs, (void**)&bn, (void**)&beta,
-                          (void**)&est, (void**)&nrm, (void**)&partn, (void**)&act, (void**)&jc};
+                          (void**)&est, (void**)&nrm, (void**)&partn, (void**)&act, (void**)&jc,
+                          (void**)&itd, (void**)&run};
         const size_t bytes[] = {16 * (size_t)vs * (k + 1), 16 * (size_t)vs * k, 16 * (size_t)nrhs * hld,
                                 16 * (size_t)nrhs * hld, 16 * (size_t)nrhs * k, 16 * (size_t)nrhs * (k + 1),
                                 16 * (size_t)nrhs * k, 16 * (size_t)nrhs * nch * (k + 1), 8 * (size_t)nrhs * k,
                                 8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs, 8 * (size_t)nrhs,
-                                8 * (size_t)nrhs * nch, 4 * (size_t)nrhs, 4 * (size_t)nrhs};
+                                8 * (size_t)nrhs * nch, 4 * (size_t)nrhs, 4 * (size_t)nrhs, 4 * (size_t)nrhs, 4};
         const size_t nslot = sizeof(bytes) / sizeof(bytes[0]);
         if (ln.gws.size() < nslot) ln.gws.resize(nslot, {nullptr, 0});
         for (size_t i = 0; i < nslot; ++i) {
             auto& w = ln.gws[i];
             if (w.second < bytes[i]) {
+                if (&ln == &ctx->lanes[0]) drop_graphs(ctx);  // captured cycles hold the old addresses
                 if (w.first) GCHK(hipFree(w.first));
                 w = {nullptr, 0};
                 GCHK(hipMalloc(&w.first, bytes[i]));
@@ -1902,12 +2004,23 @@ static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
         done[r] = !(bn_h[r] > 0);
         if (done[r]) rel[r] = 0.0;
     }
+    // With the test on the device (option gmres_device_test), the steps of a
+    // cycle are issued without reading anything back: k_conv counts each
+    // step and clears act[r] when a right-hand side converges, and once all
+    // have, the run flag stops every later kernel of the cycle at its start.
+    // The iteration counts come back with the next cycle's residual norms,
+    // so a cycle costs one read.  The cycle's steps can then be captured
+    // once and replayed (option graph, on the context's own lane).
+    const bool dev = ctx->gmres_device_test;
+    bool first = true;
     while (true) {
         // true residual r = b - A x into V_0
         launch_matvec(Q, ctx->d_et, x, V, b, ld, nrhs, 1, st);
         launch_norm(V, ld, N, nrhs, nullptr, partn, beta, nullptr, 0, st);
         GCHK(hipMemcpyAsync(beta_h.data(), beta, 8 * nrhs, hipMemcpyDeviceToHost, st));
+        if (dev && !first) GCHK(hipMemcpyAsync(it_h.data(), itd, 4 * nrhs, hipMemcpyDeviceToHost, st));
         GCHK(hipStreamSynchronize(st));
+        first = false;
         bool any = false;
         for (int r = 0; r < nrhs; ++r) {
             if (!(bn_h[r] > 0)) { act_h[r] = 0; continue; }
@@ -1921,6 +2034,19 @@ static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
         launch_scale(V, V, ld, N, nrhs, beta, act, st);
         launch_cycle_init(k, nrhs, beta, g, act, st);
         std::fill(jc_h.begin(), jc_h.end(), 0);
+        if (dev) {
+            const int one = 1;
+            GCHK(hipMemcpyAsync(itd, it_h.data(), 4 * nrhs, hipMemcpyHostToDevice, st));
+            GCHK(hipMemcpyAsync(jc, jc_h.data(), 4 * nrhs, hipMemcpyHostToDevice, st));
+            GCHK(hipMemcpyAsync(run, &one, 4, hipMemcpyHostToDevice, st));
+            s = gmres_cycle_device<T>(ctx, ln, prob, V, Z, H, part, coef, cs, sn, g, bn, est, nrm, partn,
+                                      act, jc, itd, run, nrhs, k, o);
+            if (s != HSW_OK) { cleanup(); return s; }
+            launch_lsq(k, nrhs, H, g, jc, y, st);
+            launch_axpy_multi(Z, vs, x, ld, N, k, y, k, jc, nullptr, 1, nrhs, st);
+            GCHK(hipGetLastError());
+            continue;
+        }
         for (int j = 0; j < k; ++j) {
             Cx<double>* Vj = V + (int64_t)j * vs;
             Cx<double>* Vn = V + (int64_t)(j + 1) * vs;

@@ -94,8 +94,10 @@ void launch_aux_table(Cx<double>* out, int n3, int g, int lo, int ga, int nz, do
 void launch_check_velocity(const double* c, int64_t n, int* bad, hipStream_t st);
 
 // krylov.hip
+// active (per right-hand side) and run: see k_matvec; NULL for all
 void launch_matvec(const ProbDev& Q, const Cx<double>* et, const Cx<double>* x, Cx<double>* y,
-                   const Cx<double>* b, int64_t ld, int nrhs, int mode, hipStream_t st);
+                   const Cx<double>* b, int64_t ld, int nrhs, int mode, hipStream_t st,
+                   const int* active = nullptr, const int* run = nullptr);
 int dots_chunks(int64_t N);
 void launch_dots(const Cx<double>* V, int64_t vstride, const Cx<double>* w, int64_t ld, int64_t N,
                  int nvec, int nrhs, const int* active, Cx<double>* partial, Cx<double>* h, int hld,
@@ -112,6 +114,12 @@ void launch_givens(int j, int k, int nrhs, Cx<double>* H, double* cs, Cx<double>
                    hipStream_t st);
 void launch_lsq(int k, int nrhs, const Cx<double>* H, const Cx<double>* g, const int* jcount,
                 Cx<double>* y, hipStream_t st);
+// z := x (nrhs columns of N entries, stride ld), skipped while *run is 0
+void launch_copy_cols(const Cx<double>* x, Cx<double>* z, int64_t ld, int64_t N, int nrhs, const int* run,
+                      hipStream_t st);
+// GMRES convergence test on the device after Arnoldi step j (k_conv)
+void launch_conv(int j, int nrhs, const double* est, double rtol, int maxit, int* active, int* iters,
+                 int* jcount, int* run, hipStream_t st);
 void launch_cycle_init(int k, int nrhs, const double* beta, Cx<double>* g, const int* active,
                        hipStream_t st);
 

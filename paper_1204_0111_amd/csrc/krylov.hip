@@ -14,11 +14,15 @@ namespace hsw {
 
 using C64 = Cx<double>;
 
-// y = A x (mode 0) or y = b - A x (mode 1), coefficients from the stretch tables.
+// y = A x (mode 0) or y = b - A x (mode 1), coefficients from the stretch
+// tables.  Right-hand sides with active[r] == 0 are skipped, and nothing is
+// done while *run is 0 (active and run may be NULL).
 __global__ __launch_bounds__(256) void k_matvec(ProbDev Q, const C64* __restrict__ et,
                                                 const C64* __restrict__ x, C64* __restrict__ y,
                                                 const C64* __restrict__ b, int64_t ld, int nrhs,
-                                                int mode) {
+                                                int mode, const int* __restrict__ active,
+                                                const int* __restrict__ run) {
+    if (run && !*run) return;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= Q.Npad) return;
     const int N1 = Q.N[0], N2 = Q.N[1], N3 = Q.N[2];
@@ -41,6 +45,7 @@ __global__ __launch_bounds__(256) void k_matvec(ProbDev Q, const C64* __restrict
     const bool h1m = a1 > 0, h1p = a1 + 1 < N1, h2m = a2 > 0, h2p = a2 + 1 < N2;
     const bool h3m = a3 > 0, h3p = a3 + 1 < N3;
     for (int r = 0; r < nrhs; ++r) {
+        if (active && !active[r]) continue;
         const C64* xr = x + r * ld + p;
         C64 acc = dg * xr[0];
         if (h1m) cfma(acc, cm[0], xr[-1]);
@@ -54,9 +59,9 @@ __global__ __launch_bounds__(256) void k_matvec(ProbDev Q, const C64* __restrict
 }
 
 void launch_matvec(const ProbDev& Q, const C64* et, const C64* x, C64* y, const C64* b, int64_t ld,
-                   int nrhs, int mode, hipStream_t st) {
+                   int nrhs, int mode, hipStream_t st, const int* active, const int* run) {
     const int64_t nb = (Q.Npad + 255) / 256;
-    HSW_LAUNCH(k_matvec, dim3((unsigned)nb), dim3(256), 0, st, Q, et, x, y, b, ld, nrhs, mode);
+    HSW_LAUNCH(k_matvec, dim3((unsigned)nb), dim3(256), 0, st, Q, et, x, y, b, ld, nrhs, mode, active, run);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,6 +268,42 @@ __global__ void k_lsq(int k, int nrhs, const C64* __restrict__ H, const C64* __r
     }
 }
 
+// z := x over N entries of nrhs columns (column r at r * ld); nothing while
+// *run is 0.
+__global__ __launch_bounds__(256) void k_copy_cols(const C64* __restrict__ x, C64* __restrict__ z, int64_t ld,
+                                                   int64_t N, const int* __restrict__ run) {
+    if (!*run) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < N) z[blockIdx.y * ld + p] = x[blockIdx.y * ld + p];
+}
+void launch_copy_cols(const C64* x, C64* z, int64_t ld, int64_t N, int nrhs, const int* run, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, z, ld, N, run);
+}
+
+// The convergence test of GMRES on the device, after Arnoldi step j: each
+// active right-hand side counts the step (iters, and jcount = the steps of
+// this cycle) and leaves when its residual estimate is below rtol (a NaN
+// estimate is not) or it has taken maxit steps; *run := whether any is still
+// active.  One workgroup.
+__global__ __launch_bounds__(256) void k_conv(int j, int nrhs, const double* __restrict__ est, double rtol,
+                                              int maxit, int* __restrict__ active, int* __restrict__ iters,
+                                              int* __restrict__ jcount, int* __restrict__ run) {
+    if (!*run) return;
+    int mine = 0;
+    for (int r = threadIdx.x; r < nrhs; r += 256) {
+        if (!active[r]) continue;
+        const int it = iters[r] + 1;
+        iters[r] = it;
+        jcount[r] = j + 1;
+        if (est[r] < rtol || it >= maxit)
+            active[r] = 0;
+        else
+            mine = 1;
+    }
+    const int any = __syncthreads_or(mine);
+    if (threadIdx.x == 0) *run = any;
+}
+
 // g = (beta, 0, ..., 0) for a new cycle.
 __global__ void k_cycle_init(int k, int nrhs, const double* __restrict__ beta, C64* __restrict__ g,
                              const int* __restrict__ active) {
@@ -310,6 +351,10 @@ void launch_givens(int j, int k, int nrhs, C64* H, double* cs, C64* sn, C64* g, 
 void launch_lsq(int k, int nrhs, const C64* H, const C64* g, const int* jcount, C64* y,
                 hipStream_t st) {
     hipLaunchKernelGGL(k_lsq, dim3((nrhs + 63) / 64), dim3(64), 0, st, k, nrhs, H, g, jcount, y);
+}
+void launch_conv(int j, int nrhs, const double* est, double rtol, int maxit, int* active, int* iters,
+                 int* jcount, int* run, hipStream_t st) {
+    hipLaunchKernelGGL(k_conv, dim3(1), dim3(256), 0, st, j, nrhs, est, rtol, maxit, active, iters, jcount, run);
 }
 void launch_cycle_init(int k, int nrhs, const double* beta, C64* g, const int* active,
                        hipStream_t st) {

@@ -97,6 +97,7 @@ __global__ __launch_bounds__(NT) void k_fwd(PassArgs<T> A) {
                   "shuffles within the wave, then one partial per wave");
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* sm = reinterpret_cast<Cx<T>*>(smem_raw);
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     const int n = it.n, s = it.s;
     const int rhs0 = blockIdx.y * RC;
@@ -246,6 +247,7 @@ __global__ __launch_bounds__(NT) void k_bwd(PassArgs<T> A) {
     static_assert(CW % QW == 0, "the passes must cover every column of the wave");
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* rv = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     if (leaf_aux_block(it, A.ga, it.blk, CB)) return;
     const int n = it.n, s = it.s;
@@ -455,6 +457,7 @@ __device__ inline void wave_lds_sync() {
 // the class also serves a panel with fewer auxiliary planes (zero_aux).
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
+    if (A.run && !*A.run) return;
     __shared__ T Sre[64][17], Sim[64][17];
     __shared__ int wr[64];
     const int e0 = blockIdx.x * 64, grp = blockIdx.y;
@@ -589,6 +592,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     const int S = SK ? A.nsplit : 1;
     const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
     const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[ib];  // items of 16 RT rows
     if (it.blk + 16 * RT <= leaf_aux_rows(it, A.ga)) return;  // nothing to store
     const int n = it.n, s = it.s;
@@ -764,6 +768,7 @@ __device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[4]
 // result does not depend on timing) and applies the forward epilogue.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_fin(PassArgs<T> A) {
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     const int grp = blockIdx.y, tid = threadIdx.x, r = tid & 15, S = A.nsplit;
     if ((int64_t)grp * 16 + r >= A.nrhs) return;
@@ -788,6 +793,7 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
     constexpr int KC = 16, ROWS = 64;
     constexpr uint32_t ES = sizeof(Cx<T>);
     extern __shared__ unsigned char smem_raw[];
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];  // items of 64 rows
     if (it.blk + ROWS <= leaf_aux_rows(it, A.ga)) return;  // nothing to store
     const int n = it.n, s = it.s;
@@ -975,6 +981,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     const int S = SK ? A.nsplit : 1;
     const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
     const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[ib];  // items of 16 CT columns
     if (leaf_aux_block(it, A.ga, it.blk, 16 * CT)) return;
     const int n = it.n, s = it.s;
@@ -1177,6 +1184,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
 // applies the backward epilogue.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_fin(PassArgs<T> A) {
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     if (leaf_aux_block(it, A.ga, it.blk, 64)) return;
     const int grp = blockIdx.y, tid = threadIdx.x, S = A.nsplit;
@@ -1221,6 +1229,7 @@ __global__ __launch_bounds__(TRI_NT) void k_fwd_tri(PassArgs<T> A) {
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* v = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]: the front vector, then x
     __shared__ Cx<T> xb[RC][64];
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     const int n = it.n, s = it.s;
     const int rhs0 = blockIdx.y * RC;
@@ -1332,6 +1341,7 @@ __global__ __launch_bounds__(TRI_NT) void k_bwd_tri(PassArgs<T> A) {
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* w = reinterpret_cast<Cx<T>*>(smem_raw);  // [RC][n]: x_mid and x_U, then x
     __shared__ Cx<T> tb[RC][64];
+    if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     const int n = it.n, s = it.s;
     const int rhs0 = blockIdx.y * RC;

@@ -391,6 +391,35 @@ def test_gmres_matches_oracle(medium, prec):
             assert info["iters"][r] <= 1.2 * it_o + 1, (info["iters"][r], it_o)
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [3, 17])
+def test_gmres_device_test_and_captured_cycles_match_host_test(medium, prec, nrhs):
+    """GMRES with its convergence test on the device (one read per cycle;
+    the steps after the last right-hand side converged stop at their first
+    instruction) gives the iterates of the host-driven test bit for bit, and
+    so do cycles captured once and replayed.  A short restart makes several
+    cycles, so the captured steps are replayed with eager work in between.
+    nrhs 17 takes the matrix-core passes (a full group and a ragged one)."""
+    P = medium
+    S = _solver(P, prec)
+    b = wl.gaussian_sources(P["n"], P["gamma"], P["h"],
+                            [[0.5, 0.5, 0.5], [0.3, 0.6, 0.2], [0.7, 0.2, 0.8]]).reshape(3, -1)
+    b = np.concatenate([b, wl.random_complex((nrhs - 3, b.shape[1]), 8)]) if nrhs > 3 else b
+    runs = []
+    for dev, graph in [(0, 0), (1, 0), (1, 1), (1, 1), (0, 0)]:
+        S.set_option("gmres_device_test", dev)
+        S.set_option("graph", graph)
+        xs, info = S.solve([_cuda(b)], rtol=1e-6, restart=4)
+        runs.append((xs[0].cpu().numpy(), info["iters"], info["relres"], info["status"]))
+    S.close()
+    x0, it0, rr0, st0 = runs[0]
+    assert st0 == "HSW_OK" and max(it0) > 4, it0  # converged, over more than one cycle
+    for x, it, rr, st in runs[1:]:
+        assert st == st0 and it == it0, (it, it0)
+        assert np.array_equal(x, x0)
+        assert rr == rr0
+
+
 def test_single_panel_undamped_converges_in_one_iteration():
     P = case(n=(8, 7, 6), gamma=2, d=6, leaf=3, alpha=0.0)
     S = _solver(P, "c128")
