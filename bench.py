@@ -338,11 +338,11 @@ def cpu_baseline(name, iters, max_workers=None):
 
 # ------------------------------------------------------------------ records
 def measure_workload(name, steps, warmup, comparator=True, bf16=False, roofline=False, rhs_group=0,
-                     log=None, device_test=False):
+                     log=None, device_test=False, options=None):
     Ps, bs = workload(name)
     nrhs = max(b.shape[0] for b in bs)
     rec = dict(config=describe(Ps))
-    main_run = run_path(Ps, bs, "c64", steps, warmup, measure=roofline, rhs_group=rhs_group)
+    main_run = run_path(Ps, bs, "c64", steps, warmup, measure=roofline, rhs_group=rhs_group, options=options)
     kernels = main_run.pop("kernels", None)
     if log:
         log("c64 %s" % name, main_run)
@@ -406,6 +406,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-device-test", action="store_true",
                     help="skip the GMRES variant with the convergence test on the device")
+    ap.add_argument("--set", default="",
+                    help="context options of the headline's complex64 run, as key=value,... "
+                         "(e.g. mm_fwd_form=7; see hsw_set_option)")
     ap.add_argument("--rhs-group", type=int, default=0,
                     help="solve the right-hand sides in groups of this many columns")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -430,9 +433,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    opts = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.set.split(",") if kv)
     head = measure_workload(args.workload, args.steps, args.warmup, comparator=not args.no_comparator,
                             bf16=not args.no_bf16, roofline=not args.no_roofline,
-                            rhs_group=args.rhs_group, log=log, device_test=not args.no_device_test)
+                            rhs_group=args.rhs_group, log=log, device_test=not args.no_device_test,
+                            options=opts)
     main_run, comp = head["c64"], head.get("c128")
     subs = {}
     for name in [s for s in args.sub.split(",") if s and s != args.workload]:

@@ -130,6 +130,7 @@ struct Lane {
     // right-hand side in elimination order (likewise per class)
     void *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;  // [x_S; -x_U] per front, slots, h2
     void* d_mpart = nullptr;  // partial blocks of the split-contraction forms
+    int* d_mcnt = nullptr;    // their per-item counts (zero between launches)
     int mm_groups = 0;
     std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
     const int* run = nullptr;  // device flag the pass kernels test (GMRES cycles with the test on the device)
@@ -281,7 +282,7 @@ static void free_lane(Lane& L, bool own_stream) {
     for (auto& w : L.gws)
         if (w.first) (void)hipFree(w.first);
     L.gws.clear();
-    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart, (void**)&L.d_mcnt}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1064,10 +1065,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             drop_graphs(ctx);
         }
     } else if (k == "mm_fwd_form") {
-        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..5");
+        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..6");
         ctx->mm_fwd_form = (int)value;
     } else if (k == "mm_bwd_form") {
-        if (value < -1 || value > 4) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..4");
+        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..5");
         ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
@@ -1251,7 +1252,7 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     if (groups <= L.mm_groups) return HSW_OK;
     HIPCHK(hipStreamSynchronize(L.st));
     if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
-    for (void** p : {&L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
+    for (void** p : {&L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart, (void**)&L.d_mcnt}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1270,6 +1271,8 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     HIPCHK(hipMalloc(&L.d_mc2, bc2));
     HIPCHK(hipMalloc(&L.d_mh2, bh2));
     HIPCHK(hipMalloc(&L.d_mpart, sizeof(Cx<T>) * 1024 * (size_t)parts));
+    HIPCHK(hipMalloc(&L.d_mcnt, sizeof(int) * (size_t)parts));
+    HIPCHK(hipMemsetAsync(L.d_mcnt, 0, sizeof(int) * (size_t)parts, L.st));
     HIPCHK(hipMemsetAsync(L.d_mc2, 0, bc2, L.st));
     HIPCHK(hipMemsetAsync(L.d_mh2, 0, bh2, L.st));
     L.mm_groups = groups;
@@ -1366,6 +1369,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         A.c2 = (Cx<T>*)ln.d_mc2 + 16 * cls_c2;
         A.h2 = (Cx<T>*)ln.d_mh2 + 16 * cls_h2;
         A.part = (Cx<T>*)ln.d_mpart;
+        A.cnt = ln.d_mcnt;
         A.perm = ctx->d_perm + P.perm_off;
         A.zero_aux = ctx->cls_mixed_ga[P.cls];
         A.gs_u = 16 * std::max<int64_t>(ctx->max_wsize, 1);
@@ -1412,7 +1416,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 else
                     form = sizeof(T) == 4 && lv[d].bcount[MM_BWD_SHAPE] * groups < MM_WIDE_BELOW ? 3 : 1;
             }
-            const int bs = (form == 0 || form == 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
+            const int bs = (form == 0 || form >= 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
             A.items = ctx->d_sitems + lv[d].boff[bs];
             A.nsplit = mm_split(lv[d].bcount[bs], groups);
             run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec_bytes,
@@ -1576,7 +1580,7 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        constexpr int NF = 6, NB = 5;  // forward and backward forms
+        constexpr int NF = 7, NB = 6;  // forward and backward forms
         std::vector<std::array<float, NF>> tf(D + 1), tb(D + 1);
         for (auto& a : tf) a.fill(1e30f);
         for (auto& a : tb) a.fill(1e30f);
@@ -1677,6 +1681,7 @@ static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* 
         gl.d_mc2 = ln.d_mc2;
         gl.d_mh2 = ln.d_mh2;
         gl.d_mpart = ln.d_mpart;
+        gl.d_mcnt = ln.d_mcnt;
         gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -1920,6 +1925,7 @@ static hsw_status gmres_cycle_device(hsw_ctx* ctx, Lane& ln, int prob, Cx<double
         gl.d_mc2 = ln.d_mc2;
         gl.d_mh2 = ln.d_mh2;
         gl.d_mpart = ln.d_mpart;
+        gl.d_mcnt = ln.d_mcnt;
         gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         hsw_status cs_ = HSW_OK;

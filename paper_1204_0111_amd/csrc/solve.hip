@@ -18,6 +18,8 @@
 //            forward sweep) and pushed to the children's update-set values.
 // Parents and children exchange values through slots laid out in the
 // receiver's order, so no pass reads through an index it has to load first.
+#include <type_traits>
+
 #include "devtypes.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -582,16 +584,17 @@ __device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int 
 }
 
 // SK: split contraction.  Workgroup b takes item b / nsplit and the
-// (b mod nsplit)-th share of its chunks, and stores its partial block
-// instead of the epilogue (k_fwd_fin sums the shares).
-template <typename T, int RT, int NW, bool SK = false>
+// (b mod nsplit)-th share of its chunks and stores its partial block.  SK 1:
+// a finishing launch (k_fwd_fin) sums the shares; SK 2: the item's last
+// workgroup to finish sums them and applies the epilogue (split_last).
+template <typename T, int RT, int NW, int SK = 0>
 __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    static_assert(!SK || (RT == 4 && NW == 4), "split contraction: 64-row items, 4 waves");
-    const int S = SK ? A.nsplit : 1;
-    const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
-    const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    static_assert(SK == 0 || (RT == 4 && NW == 4), "split contraction: 64-row items, 4 waves");
+    const int S = SK != 0 ? A.nsplit : 1;
+    const int ib = SK != 0 ? (int)blockIdx.x / S : (int)blockIdx.x;
+    const int z = SK != 0 ? (int)blockIdx.x - ib * S : 0;
     if (A.run && !*A.run) return;
     const SolveItem it = A.items[ib];  // items of 16 RT rows
     if (it.blk + 16 * RT <= leaf_aux_rows(it, A.ga)) return;  // nothing to store
@@ -639,7 +642,9 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // B(k, rhs) = v_S(c + 4 q + lk, li)
     T gre[RT][4], gim[RT][4];
     T vre[3][4], vim[3][4];
-    auto load = [&](int c, T(&gr)[RT][4], T(&gi)[RT][4], T(&br)[3][4], T(&bi)[3][4]) {
+    // np: the parts of v_S loaded (a leaf has the right-hand side alone, and
+    // its loop issues no loads of the empty child slots)
+    auto load = [&](auto np, int c, T(&gr)[RT][4], T(&gi)[RT][4], T(&br)[3][4], T(&bi)[3][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t col = (uint32_t)(c + 4 * q + lk);
@@ -648,8 +653,12 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
                 BufCx<T>::load(rg, (col * n + it.blk + 16 * t + li) * ES, gr[t][q], gi[t][q]);
             const uint32_t vo = (col * 16 + li) * ES;
             BufCx<T>::load(rh, vo, br[0][q], bi[0][q]);
-            BufCx<T>::load(r0, vo, br[1][q], bi[1][q]);
-            BufCx<T>::load(r1, vo, br[2][q], bi[2][q]);
+            if constexpr (decltype(np)::value == 3) {
+                BufCx<T>::load(r0, vo, br[1][q], bi[1][q]);
+                BufCx<T>::load(r1, vo, br[2][q], bi[2][q]);
+            } else {
+                br[1][q] = bi[1][q] = br[2][q] = bi[2][q] = 0;
+            }
         }
     };
     // accumulators: with one row tile the real and imaginary parts each take
@@ -686,12 +695,19 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // one chunk at a time per wave: the loads of the waves sharing a SIMD
     // overlap each other's products (a few waves per SIMD at this register
     // count); a load past the contraction's end reads zeros.  (Two chunks in
-    // flight per wave, as in the backward pass, measured slower here.)
+    // flight per wave, their loads kept ahead of the products, measured
+    // slower at every depth.)
     const int per = (nch + S - 1) / S, c_lo = z * per, c_hi = min(nch, c_lo + per);
-    for (int ch = c_lo + wave; ch < c_hi; ch += NW) {
-        load(kb + ch * KC, gre, gim, vre, vim);
-        products(gre, gim, vre, vim);
-    }
+    auto chunks = [&](auto np) {
+        for (int ch = c_lo + wave; ch < c_hi; ch += NW) {
+            load(np, kb + ch * KC, gre, gim, vre, vim);
+            products(gre, gim, vre, vim);
+        }
+    };
+    if (it.leaf)
+        chunks(std::integral_constant<int, 1>{});
+    else
+        chunks(std::integral_constant<int, 3>{});
     if (SPLIT == 2) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -710,14 +726,15 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         }
         sum_wave_blocks<T, RT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
     }
-    if constexpr (SK) {
+    if constexpr (SK != 0) {
         Cx<T>* pp = A.part + ((int64_t)(ib * gridDim.y + grp) * S + z) * (256 * RT);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
         }
-        return;
+        if constexpr (SK == 1) return;
+        else if (!split_last(A, ib * gridDim.y + grp, S, tid, Yre, Yim)) return;
     }
     // thread tid < 256: right-hand side rhs0 + tid % 16 of rows blk + tid / 16 + 16 t
     // (a row's 16 right-hand sides are one contiguous block)
@@ -762,6 +779,35 @@ __device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[4]
             for (int t = 0; t < 4; ++t)
                 if (z0 + u < S) y[t] = y[t] + v[u][t];
     }
+}
+
+// The last of an item's S split workgroups to store its partial block (an
+// atomic count per item and group, reset by that workgroup) sums the S
+// blocks, in split order, into Y for the epilogue, and returns true; the
+// others return false.  The fences order each workgroup's partial stores
+// before its count and the last one's loads after it, across the XCDs'
+// caches; no workgroup waits for another.
+template <typename T>
+__device__ inline bool split_last(const PassArgs<T>& A, int slot, int S, int tid, T (&Yre)[64][17],
+                                  T (&Yim)[64][17]) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(A.cnt + slot, 1) == S - 1;
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    Cx<T> y[4];
+    split_sums(A.part + (int64_t)slot * S * 1024, S, tid, y);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int e = tid + 256 * t;
+        Yre[e >> 4][e & 15] = y[t].re;
+        Yim[e >> 4][e & 15] = y[t].im;
+    }
+    if (tid == 0) A.cnt[slot] = 0;
+    __syncthreads();
+    return true;
 }
 
 // Sums the nsplit partial blocks of each 64-row item (in split order, so the
@@ -855,21 +901,32 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         const int pm = buf_load_i32(rp, (uint32_t)(drow - s) * 4);  // zero on pivot rows
         Cx<T>* trash = reinterpret_cast<Cx<T>*>(PM + ROWS);  // 256 bytes past PM: aligned
         const int tot = nk16 * 16;
-        for (int e0 = tid; e0 < tot; e0 += 4 * 256) {
-            T hr[4], hi[4], ar[4], ai[4], br[4], bi[4];
+        constexpr int SU = 4;  // entries per thread and round
+        auto stage = [&](auto np) {  // np: parts of v_S (a leaf: the right-hand side alone)
+            for (int e0 = tid; e0 < tot; e0 += SU * 256) {
+                T hr[SU], hi[SU], ar[SU], ai[SU], br[SU], bi[SU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t off = (uint32_t)(kb * 16 + e0 + 256 * u) * ES;
-                BufCx<T>::load(rh, off, hr[u], hi[u]);
-                BufCx<T>::load(ra, off, ar[u], ai[u]);
-                BufCx<T>::load(rb, off, br[u], bi[u]);
-            }
+                for (int u = 0; u < SU; ++u) {
+                    const uint32_t off = (uint32_t)(kb * 16 + e0 + 256 * u) * ES;
+                    BufCx<T>::load(rh, off, hr[u], hi[u]);
+                    if constexpr (decltype(np)::value == 3) {
+                        BufCx<T>::load(ra, off, ar[u], ai[u]);
+                        BufCx<T>::load(rb, off, br[u], bi[u]);
+                    } else {
+                        ar[u] = ai[u] = br[u] = bi[u] = 0;
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + 256 * u;
-                *(e < tot ? V + e : trash) = cx<T>(hr[u] + ar[u] + br[u], hi[u] + ai[u] + bi[u]);
+                for (int u = 0; u < SU; ++u) {
+                    const int e = e0 + 256 * u;
+                    *(e < tot ? V + e : trash) = cx<T>(hr[u] + ar[u] + br[u], hi[u] + ai[u] + bi[u]);
+                }
             }
-        }
+        };
+        if (it.leaf)
+            stage(std::integral_constant<int, 1>{});
+        else
+            stage(std::integral_constant<int, 3>{});
         // pivot rows take no contribution (their slots hold the children's
         // v_S parts, already summed above)
 #pragma unroll
@@ -970,17 +1027,18 @@ __device__ inline void bwd_grid(const PassArgs<T>& A, const SolveItem& it, int j
 }
 
 // SK: split contraction.  Workgroup b takes item b / nsplit and the
-// (b mod nsplit)-th share of its row chunks (and of the front's hand-on),
-// and stores its partial block instead of the epilogue (k_bwd_fin sums the
-// shares).
-template <typename T, int CT, int NW, bool SK = false>
+// (b mod nsplit)-th share of its row chunks (and of the front's hand-on)
+// and stores its partial block.  SK 1: a finishing launch (k_bwd_fin) sums
+// the shares; SK 2: the item's last workgroup to finish sums them and
+// applies the epilogue (split_last).
+template <typename T, int CT, int NW, int SK = 0>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    static_assert(!SK || (CT == 4 && NW == 4), "split contraction: 64-column items, 4 waves");
-    const int S = SK ? A.nsplit : 1;
-    const int ib = SK ? (int)blockIdx.x / S : (int)blockIdx.x;
-    const int z = SK ? (int)blockIdx.x - ib * S : 0;
+    static_assert(SK == 0 || (CT == 4 && NW == 4), "split contraction: 64-column items, 4 waves");
+    const int S = SK != 0 ? A.nsplit : 1;
+    const int ib = SK != 0 ? (int)blockIdx.x / S : (int)blockIdx.x;
+    const int z = SK != 0 ? (int)blockIdx.x - ib * S : 0;
     if (A.run && !*A.run) return;
     const SolveItem it = A.items[ib];  // items of 16 CT columns
     if (leaf_aux_block(it, A.ga, it.blk, 16 * CT)) return;
@@ -1107,6 +1165,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         for (int ch = wave; ch < nch; ch += 2 * NW) {
             load(ch, gre, gim, sre, sim);
             load(ch + NW, gre2, gim2, sre2, sim2);
+            __builtin_amdgcn_sched_barrier(0);  // both chunks' loads ahead of the products
             products(gre, gim, sre, sim);
             products(gre2, gim2, sre2, sim2);
         }
@@ -1135,14 +1194,15 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         }
         sum_wave_blocks<T, CT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
     }
-    if constexpr (SK) {
+    if constexpr (SK != 0) {
         Cx<T>* pp = A.part + ((int64_t)(ib * gridDim.y + grp) * S + z) * (256 * CT);
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
         }
-        return;
+        if constexpr (SK == 1) return;
+        else if (!split_last(A, ib * gridDim.y + grp, S, tid, Yre, Yim)) return;
     }
     if (tid >= 256) return;
 #pragma unroll
@@ -1559,7 +1619,8 @@ void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st) {
 // 8 waves splitting the contraction; 1 / 4: 16 rows, 4 / 8 waves; 2:
 // row-split (64 rows, needs fwd_rs_lds_bytes(smax) of LDS); 5: 64 rows with
 // each item's contraction split over A.nsplit workgroups, then a finishing
-// launch (A.part holds the partial blocks).
+// launch (A.part holds the partial blocks); 6: as 5, the item's last
+// workgroup finishing (A.cnt holds the counts).
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStream_t st) {
     if (nwork <= 0) return;
@@ -1571,17 +1632,20 @@ void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStrea
     case 2: HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A); break;
     case 3: HSW_LAUNCH((k_fwd_mm<T, 4, 8>), grid, dim3(512), 0, st, A); break;
     case 4: HSW_LAUNCH((k_fwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
-    default: {
+    case 5: {
         const dim3 gs(nwork * A.nsplit, grid.y);
-        HSW_LAUNCH((k_fwd_mm<T, 4, 4, true>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_fwd_mm<T, 4, 4, 1>), gs, dim3(256), 0, st, A);
         HSW_LAUNCH(k_fwd_fin<T>, grid, dim3(256), 0, st, A);
+        break;
     }
+    default: HSW_LAUNCH((k_fwd_mm<T, 4, 4, 2>), dim3(nwork * A.nsplit, grid.y), dim3(256), 0, st, A); break;
     }
 }
 // Forms of the backward matrix-core pass: 0: 64 columns per workgroup, 4
 // waves; 1 / 2 / 3: 16 columns, 4 / 8 / 16 waves (complex128: 8 at most,
 // for registers); 4: 64 columns with each item's contraction split over
-// A.nsplit workgroups, then a finishing launch.
+// A.nsplit workgroups, then a finishing launch; 5: as 4, the item's last
+// workgroup finishing.
 template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
     if (nwork <= 0) return;
@@ -1592,11 +1656,13 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
     case 1: HSW_LAUNCH((k_bwd_mm<T, 1, 4>), grid, dim3(256), 0, st, A); break;
     case 2: HSW_LAUNCH((k_bwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
     case 3: HSW_LAUNCH((k_bwd_mm<T, 1, W16>), grid, dim3(64 * W16), 0, st, A); break;
-    default: {
+    case 4: {
         const dim3 gs(nwork * A.nsplit, grid.y);
-        HSW_LAUNCH((k_bwd_mm<T, 4, 4, true>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_bwd_mm<T, 4, 4, 1>), gs, dim3(256), 0, st, A);
         HSW_LAUNCH(k_bwd_fin<T>, grid, dim3(256), 0, st, A);
+        break;
     }
+    default: HSW_LAUNCH((k_bwd_mm<T, 4, 4, 2>), dim3(nwork * A.nsplit, grid.y), dim3(256), 0, st, A); break;
     }
 }
 

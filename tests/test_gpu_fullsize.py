@@ -118,17 +118,23 @@ def test_middle_panel_many_rhs_matrix_core_passes_match_oracle(name, nrhs, prec)
 
 @pytest.mark.parametrize("name", ["grf50", "layered100"])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_middle_panel_row_split_forward_form_matches_oracle(name, prec):
-    """The row-split forward form forced at every depth where it fits (the
-    others keep 64-row workgroups), 17 right-hand sides, against the oracle's
-    sparse LU per right-hand side."""
+@pytest.mark.parametrize("forms", [(2, -1), (5, 4), (6, 5)], ids=["row-split", "split-fin", "split-last"])
+def test_middle_panel_forced_matrix_core_forms_match_oracle(name, prec, forms):
+    """Forms of the matrix-core passes forced at every depth, 17 right-hand
+    sides, against the oracle's sparse LU per right-hand side: the row-split
+    forward form (where it fits; other depths keep 64-row workgroups), and
+    both pass's split-contraction forms, finished by a second launch or by
+    each item's last workgroup (whose shares run on several XCDs)."""
     P, v, ref = _panel_reference(name, 5)
     S = _solver(P, prec)
-    S.set_option("mm_fwd_form", 2)
+    S.set_option("mm_fwd_form", forms[0])
+    S.set_option("mm_bwd_form", forms[1])
     y = S.panel_solve(0, 5, torch.as_tensor(v).to("cuda")).cpu().numpy()
+    y2 = S.panel_solve(0, 5, torch.as_tensor(v).to("cuda")).cpu().numpy()
     S.close()
+    assert np.array_equal(y, y2)  # deterministic: shares summed in split order
     errs = [rel(y[r], ref[r]) for r in range(len(v))]
-    print("%s %s row-split: worst T_i relative error %.3e" % (name, prec, max(errs)))
+    print("%s %s forms %s: worst T_i relative error %.3e" % (name, prec, forms, max(errs)))
     assert max(errs) <= TOL[prec], errs
 
 
