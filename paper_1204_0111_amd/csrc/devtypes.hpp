@@ -149,7 +149,6 @@ struct PassArgs {
     // nsplit workgroups): partial 64 x 16 blocks, item-major, then group,
     // then split; a finishing launch sums them in split order
     Cx<T>* part;
-    int* cnt;                  // per item and group: split workgroups done (zero between launches)
     int nsplit;
     // GMRES with the convergence test on the device: while *run is 0 (every
     // right-hand side converged) the pass kernels return at once; NULL: always run

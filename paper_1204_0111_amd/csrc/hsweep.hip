@@ -130,7 +130,6 @@ struct Lane {
     // right-hand side in elimination order (likewise per class)
     void *d_mxu = nullptr, *d_mc2 = nullptr, *d_mh2 = nullptr;  // [x_S; -x_U] per front, slots, h2
     void* d_mpart = nullptr;  // partial blocks of the split-contraction forms
-    int* d_mcnt = nullptr;    // their per-item counts (zero between launches)
     int mm_groups = 0;
     std::vector<std::pair<void*, size_t>> gws;  // GMRES workspace: (pointer, bytes) per buffer
     const int* run = nullptr;  // device flag the pass kernels test (GMRES cycles with the test on the device)
@@ -205,6 +204,7 @@ struct hsw_ctx {
     int update_order = -1;   // Schur updates: -1 default (hybrid), 0 right-, 1 left-looking, 2 hybrid
     bool block_gmres = false;  // one block Krylov space per group of <= 16 right-hand sides
     bool gmres_device_test = false;  // GMRES: convergence tested on the device, one read per cycle
+    bool tune_report = false;        // print the autotuner's timings (environment HSW_TUNE_REPORT=1)
     bool bf16_mfma = true;     // HSW_C64_BF16GEMM: Schur updates on the BF16 matrix cores
     // matrix-core pass forms for every depth (-1: the tuned choice; the
     // forms of launch_fwd_mm and launch_bwd_mm)
@@ -282,7 +282,7 @@ static void free_lane(Lane& L, bool own_stream) {
     for (auto& w : L.gws)
         if (w.first) (void)hipFree(w.first);
     L.gws.clear();
-    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart, (void**)&L.d_mcnt}) {
+    for (void** p : {&L.d_xmid, &L.d_xu, &L.d_c2, &L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -812,6 +812,7 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ctx->lanes[0].st = ctx->st;
     if (hipGetDevice(&ctx->device) != hipSuccess) ctx->device = 0;
     if (const char* at = std::getenv("HSW_AUTOTUNE")) ctx->autotune = std::string(at) != "0";
+    if (const char* tr = std::getenv("HSW_TUNE_REPORT")) ctx->tune_report = std::string(tr) != "0";
     ctx->prec = prec;
     ctx->esz = prec == HSW_C128 ? 16 : 8;
     ctx->probs.assign(p, p + nprob);
@@ -1065,10 +1066,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             drop_graphs(ctx);
         }
     } else if (k == "mm_fwd_form") {
-        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..6");
+        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..5");
         ctx->mm_fwd_form = (int)value;
     } else if (k == "mm_bwd_form") {
-        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..5");
+        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..6");
         ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
@@ -1252,7 +1253,7 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     if (groups <= L.mm_groups) return HSW_OK;
     HIPCHK(hipStreamSynchronize(L.st));
     if (&L == &ctx->lanes[0]) drop_graphs(ctx);  // they hold the old workspace addresses
-    for (void** p : {&L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart, (void**)&L.d_mcnt}) {
+    for (void** p : {&L.d_mxu, &L.d_mc2, &L.d_mh2, &L.d_mpart}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1271,8 +1272,6 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     HIPCHK(hipMalloc(&L.d_mc2, bc2));
     HIPCHK(hipMalloc(&L.d_mh2, bh2));
     HIPCHK(hipMalloc(&L.d_mpart, sizeof(Cx<T>) * 1024 * (size_t)parts));
-    HIPCHK(hipMalloc(&L.d_mcnt, sizeof(int) * (size_t)parts));
-    HIPCHK(hipMemsetAsync(L.d_mcnt, 0, sizeof(int) * (size_t)parts, L.st));
     HIPCHK(hipMemsetAsync(L.d_mc2, 0, bc2, L.st));
     HIPCHK(hipMemsetAsync(L.d_mh2, 0, bh2, L.st));
     L.mm_groups = groups;
@@ -1369,7 +1368,6 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         A.c2 = (Cx<T>*)ln.d_mc2 + 16 * cls_c2;
         A.h2 = (Cx<T>*)ln.d_mh2 + 16 * cls_h2;
         A.part = (Cx<T>*)ln.d_mpart;
-        A.cnt = ln.d_mcnt;
         A.perm = ctx->d_perm + P.perm_off;
         A.zero_aux = ctx->cls_mixed_ga[P.cls];
         A.gs_u = 16 * std::max<int64_t>(ctx->max_wsize, 1);
@@ -1416,7 +1414,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 else
                     form = sizeof(T) == 4 && lv[d].bcount[MM_BWD_SHAPE] * groups < MM_WIDE_BELOW ? 3 : 1;
             }
-            const int bs = (form == 0 || form >= 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
+            const int bs = (form == 0 || form == 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
             A.items = ctx->d_sitems + lv[d].boff[bs];
             A.nsplit = mm_split(lv[d].bcount[bs], groups);
             run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec_bytes,
@@ -1580,25 +1578,27 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        constexpr int NF = 7, NB = 6;  // forward and backward forms
-        std::vector<std::array<float, NF>> tf(D + 1), tb(D + 1);
+        constexpr int NF = 6, NB = 7;  // forward and backward forms
+        constexpr int NK = NF > NB ? NF : NB;
+        std::vector<std::array<float, NF>> tf(D + 1);
+        std::vector<std::array<float, NB>> tb(D + 1);
         for (auto& a : tf) a.fill(1e30f);
         for (auto& a : tb) a.fill(1e30f);
         int run = 0;
         for (int rep = 0; rep < REPS; ++rep)
-            for (int k = 0; k < NF; ++k, ++run) {
+            for (int k = 0; k < NK; ++k, ++run) {
                 const int gp = panels[run % panels.size()];
                 const PanelDev& P = ctx->pan_h[gp];
-                // forward form k and backward form min(k, NB - 1) at every depth
-                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(), k,
-                                std::min(k, NB - 1));
+                // forward form min(k, NF - 1) and backward form min(k, NB - 1) at every depth
+                panel_tsolve<T>(ctx, ctx->lanes[0], gp, 0, v, plen, P.lo, 0, 0, v, NR, -1, -1, ev.data(),
+                                std::min(k, NF - 1), std::min(k, NB - 1));
                 TCHK(hipGetLastError());
                 TCHK(hipEventSynchronize(ev[2 * (2 * (D + 1)) - 1]));
                 for (int l = 0; l < 2 * (D + 1); ++l) {
                     float ms = 0;
                     TCHK(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
                     if (l <= D) {
-                        float& t = tf[D - l][k];
+                        float& t = tf[D - l][std::min(k, NF - 1)];
                         t = std::min(t, ms);
                     } else {
                         float& t = tb[l - (D + 1)][std::min(k, NB - 1)];
@@ -1615,6 +1615,13 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
             sl.mm_b = 0;
             for (int k = 1; k < NB; ++k)
                 if (tb[d][k] < tb[d][sl.mm_b]) sl.mm_b = k;
+            if (ctx->tune_report) {
+                fprintf(stderr, "tune class %zu depth %d fwd", ci, d);
+                for (int k = 0; k < NF; ++k) fprintf(stderr, " %.1f", 1e3 * tf[d][k]);
+                fprintf(stderr, " -> %d  bwd", sl.mm_f);
+                for (int k = 0; k < NB; ++k) fprintf(stderr, " %.1f", 1e3 * tb[d][k]);
+                fprintf(stderr, " -> %d (us)\n", sl.mm_b);
+            }
         }
     }
 #undef TCHK
@@ -1681,7 +1688,6 @@ static hsw_status sweep_any(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>* 
         gl.d_mc2 = ln.d_mc2;
         gl.d_mh2 = ln.d_mh2;
         gl.d_mpart = ln.d_mpart;
-        gl.d_mcnt = ln.d_mcnt;
         gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -1925,7 +1931,6 @@ static hsw_status gmres_cycle_device(hsw_ctx* ctx, Lane& ln, int prob, Cx<double
         gl.d_mc2 = ln.d_mc2;
         gl.d_mh2 = ln.d_mh2;
         gl.d_mpart = ln.d_mpart;
-        gl.d_mcnt = ln.d_mcnt;
         gl.mm_groups = ln.mm_groups;
         hipError_t e = hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal);
         hsw_status cs_ = HSW_OK;

@@ -584,9 +584,8 @@ __device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int 
 }
 
 // SK: split contraction.  Workgroup b takes item b / nsplit and the
-// (b mod nsplit)-th share of its chunks and stores its partial block.  SK 1:
-// a finishing launch (k_fwd_fin) sums the shares; SK 2: the item's last
-// workgroup to finish sums them and applies the epilogue (split_last).
+// (b mod nsplit)-th share of its chunks and stores its partial block; a
+// finishing launch (k_fwd_fin) sums the shares.
 template <typename T, int RT, int NW, int SK = 0>
 __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
@@ -733,8 +732,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
         }
-        if constexpr (SK == 1) return;
-        else if (!split_last(A, ib * gridDim.y + grp, S, tid, Yre, Yim)) return;
+        return;
     }
     // thread tid < 256: right-hand side rhs0 + tid % 16 of rows blk + tid / 16 + 16 t
     // (a row's 16 right-hand sides are one contiguous block)
@@ -779,35 +777,6 @@ __device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[4]
             for (int t = 0; t < 4; ++t)
                 if (z0 + u < S) y[t] = y[t] + v[u][t];
     }
-}
-
-// The last of an item's S split workgroups to store its partial block (an
-// atomic count per item and group, reset by that workgroup) sums the S
-// blocks, in split order, into Y for the epilogue, and returns true; the
-// others return false.  The fences order each workgroup's partial stores
-// before its count and the last one's loads after it, across the XCDs'
-// caches; no workgroup waits for another.
-template <typename T>
-__device__ inline bool split_last(const PassArgs<T>& A, int slot, int S, int tid, T (&Yre)[64][17],
-                                  T (&Yim)[64][17]) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(A.cnt + slot, 1) == S - 1;
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    Cx<T> y[4];
-    split_sums(A.part + (int64_t)slot * S * 1024, S, tid, y);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int e = tid + 256 * t;
-        Yre[e >> 4][e & 15] = y[t].re;
-        Yim[e >> 4][e & 15] = y[t].im;
-    }
-    if (tid == 0) A.cnt[slot] = 0;
-    __syncthreads();
-    return true;
 }
 
 // Sums the nsplit partial blocks of each 64-row item (in split order, so the
@@ -1028,14 +997,16 @@ __device__ inline void bwd_grid(const PassArgs<T>& A, const SolveItem& it, int j
 
 // SK: split contraction.  Workgroup b takes item b / nsplit and the
 // (b mod nsplit)-th share of its row chunks (and of the front's hand-on)
-// and stores its partial block.  SK 1: a finishing launch (k_bwd_fin) sums
-// the shares; SK 2: the item's last workgroup to finish sums them and
-// applies the epilogue (split_last).
-template <typename T, int CT, int NW, int SK = 0>
+// and stores its partial block; a finishing launch (k_bwd_fin) sums the
+// shares.
+// IFB: chunks in flight per wave with one column tile (their loads all
+// issued before their products).
+template <typename T, int CT, int NW, int SK = 0, int IFB = 2>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
     static_assert(SK == 0 || (CT == 4 && NW == 4), "split contraction: 64-column items, 4 waves");
+    static_assert(IFB == 2 || (IFB == 4 && CT == 1), "four chunks in flight: one column tile");
     const int S = SK != 0 ? A.nsplit : 1;
     const int ib = SK != 0 ? (int)blockIdx.x / S : (int)blockIdx.x;
     const int z = SK != 0 ? (int)blockIdx.x - ib * S : 0;
@@ -1160,7 +1131,21 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     };
     // with one column tile each wave issues two chunks' loads before their
     // products (loads past the end read zeros), as in k_fwd_mm
-    if constexpr (CT == 1) {
+    if constexpr (CT == 1 && IFB == 4) {
+        T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4], gre3[CT][4], gim3[CT][4], sre3[4], sim3[4];
+        T gre4[CT][4], gim4[CT][4], sre4[4], sim4[4];
+        for (int ch = wave; ch < nch; ch += 4 * NW) {
+            load(ch, gre, gim, sre, sim);
+            load(ch + NW, gre2, gim2, sre2, sim2);
+            load(ch + 2 * NW, gre3, gim3, sre3, sim3);
+            load(ch + 3 * NW, gre4, gim4, sre4, sim4);
+            __builtin_amdgcn_sched_barrier(0);  // all four chunks' loads ahead of the products
+            products(gre, gim, sre, sim);
+            products(gre2, gim2, sre2, sim2);
+            products(gre3, gim3, sre3, sim3);
+            products(gre4, gim4, sre4, sim4);
+        }
+    } else if constexpr (CT == 1) {
         T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4];
         for (int ch = wave; ch < nch; ch += 2 * NW) {
             load(ch, gre, gim, sre, sim);
@@ -1201,8 +1186,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
         }
-        if constexpr (SK == 1) return;
-        else if (!split_last(A, ib * gridDim.y + grp, S, tid, Yre, Yim)) return;
+        return;
     }
     if (tid >= 256) return;
 #pragma unroll
@@ -1619,8 +1603,7 @@ void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st) {
 // 8 waves splitting the contraction; 1 / 4: 16 rows, 4 / 8 waves; 2:
 // row-split (64 rows, needs fwd_rs_lds_bytes(smax) of LDS); 5: 64 rows with
 // each item's contraction split over A.nsplit workgroups, then a finishing
-// launch (A.part holds the partial blocks); 6: as 5, the item's last
-// workgroup finishing (A.cnt holds the counts).
+// launch (A.part holds the partial blocks).
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStream_t st) {
     if (nwork <= 0) return;
@@ -1632,20 +1615,18 @@ void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStrea
     case 2: HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A); break;
     case 3: HSW_LAUNCH((k_fwd_mm<T, 4, 8>), grid, dim3(512), 0, st, A); break;
     case 4: HSW_LAUNCH((k_fwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
-    case 5: {
+    default: {
         const dim3 gs(nwork * A.nsplit, grid.y);
         HSW_LAUNCH((k_fwd_mm<T, 4, 4, 1>), gs, dim3(256), 0, st, A);
         HSW_LAUNCH(k_fwd_fin<T>, grid, dim3(256), 0, st, A);
-        break;
     }
-    default: HSW_LAUNCH((k_fwd_mm<T, 4, 4, 2>), dim3(nwork * A.nsplit, grid.y), dim3(256), 0, st, A); break;
     }
 }
 // Forms of the backward matrix-core pass: 0: 64 columns per workgroup, 4
 // waves; 1 / 2 / 3: 16 columns, 4 / 8 / 16 waves (complex128: 8 at most,
 // for registers); 4: 64 columns with each item's contraction split over
-// A.nsplit workgroups, then a finishing launch; 5: as 4, the item's last
-// workgroup finishing.
+// A.nsplit workgroups, then a finishing launch; 5 / 6: as 1 / 2 with four
+// chunks in flight per wave (two in the others).
 template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
     if (nwork <= 0) return;
@@ -1662,7 +1643,8 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
         HSW_LAUNCH(k_bwd_fin<T>, grid, dim3(256), 0, st, A);
         break;
     }
-    default: HSW_LAUNCH((k_bwd_mm<T, 4, 4, 2>), dim3(nwork * A.nsplit, grid.y), dim3(256), 0, st, A); break;
+    case 5: HSW_LAUNCH((k_bwd_mm<T, 1, 4, 0, 4>), grid, dim3(256), 0, st, A); break;
+    default: HSW_LAUNCH((k_bwd_mm<T, 1, 8, 0, 4>), grid, dim3(512), 0, st, A); break;
     }
 }
 

@@ -118,13 +118,13 @@ def test_middle_panel_many_rhs_matrix_core_passes_match_oracle(name, nrhs, prec)
 
 @pytest.mark.parametrize("name", ["grf50", "layered100"])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-@pytest.mark.parametrize("forms", [(2, -1), (5, 4), (6, 5)], ids=["row-split", "split-fin", "split-last"])
+@pytest.mark.parametrize("forms", [(2, -1), (5, 4), (1, 6)], ids=["row-split", "split", "bwd-4-in-flight"])
 def test_middle_panel_forced_matrix_core_forms_match_oracle(name, prec, forms):
     """Forms of the matrix-core passes forced at every depth, 17 right-hand
     sides, against the oracle's sparse LU per right-hand side: the row-split
-    forward form (where it fits; other depths keep 64-row workgroups), and
-    both pass's split-contraction forms, finished by a second launch or by
-    each item's last workgroup (whose shares run on several XCDs)."""
+    forward form (where it fits; other depths keep 64-row workgroups), both
+    passes' split-contraction forms (shares summed by a finishing launch),
+    and the backward form with four chunks in flight per wave."""
     P, v, ref = _panel_reference(name, 5)
     S = _solver(P, prec)
     S.set_option("mm_fwd_form", forms[0])
