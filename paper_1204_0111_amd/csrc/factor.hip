@@ -190,13 +190,22 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
             m = idx >> 6;
         }
     };
+    // k of a thread's R entries: (tid >> 6) + 4 q, the same across a wave
+    // (so the bounds tests are uniform branches and a loader's per-k values,
+    // such as the pivot d_k of the update's C operand, are scalar loads)
+    const int wq = __builtin_amdgcn_readfirstlane(tid >> 6);
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int idx = tid + 256 * q, a = idx & 63, kk = k0 + (idx >> 6);
+            const int idx = tid + 256 * q, a = tid & 63, kk = k0 + wq + 4 * q;
             r[q] = kk < K ? ldR(kk, a) : cx<T>(0, 0);
             int ca, cm;
-            cmap_(idx, ca, cm);
+            if (CT) {
+                cmap_(idx, ca, cm);
+            } else {
+                ca = a;
+                cm = wq + 4 * q;
+            }
             c[q] = k0 + cm < K ? ldC(k0 + cm, ca) : cx<T>(0, 0);
         }
     };
@@ -833,13 +842,21 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
+    // Operand loads through a descriptor cut at the end of the front's n x s
+    // block: a row past n (or a column past cend) reads a finite value of the
+    // block (or zero past its end) that only reaches output entries never
+    // stored, so the loads need no per-lane test.
+    const BufRsrc rl = buf_rsrc(L, (uint32_t)n * f.s * (uint32_t)sizeof(Cx<T>));
     auto ldR = [&](int m, int a) {
-        const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
-        return r0 + a < n ? col[r0 + a] : cx<T>(0, 0);
+        Cx<T> v;
+        BufCx<T>::load(rl, ((uint32_t)(kbeg + m) * n + r0 + a) * (uint32_t)sizeof(Cx<T>), v.re, v.im);
+        return v;
     };
-    auto ldC = [&](int m, int a) {
+    auto ldC = [&](int m, int a) {  // L[j,m] d_m (the pivot is the same across a wave)
         const Cx<T>* col = L + (int64_t)(kbeg + m) * n;
-        return c0 + a < cend ? col[c0 + a] * col[kbeg + m] : cx<T>(0, 0);  // L[j,m] d_m
+        Cx<T> v;
+        BufCx<T>::load(rl, ((uint32_t)(kbeg + m) * n + c0 + a) * (uint32_t)sizeof(Cx<T>), v.re, v.im);
+        return v * col[kbeg + m];
     };
     if constexpr (BF) {
         // complex BF16 inputs on the BF16 matrix cores
