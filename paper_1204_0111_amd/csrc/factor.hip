@@ -731,9 +731,16 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
             are[bi][bj] = V4{0, 0, 0, 0};
             aim[bi][bj] = V4{0, 0, 0, 0};
         }
+    // P(r, m) through a descriptor cut at the front's n x s block: rows past
+    // rend read finite values that reach only rows never stored
+    const BufRsrc rl = buf_rsrc(L, (uint32_t)n * f.s * (uint32_t)sizeof(Cx<T>));
     cgemm64_pipe<T, KC, true>(  // L_kk^{-1}(a, m) is contiguous in m: transposed C loads
         are, aim, b,
-        [&](int m, int a) { return rbeg + a < rend ? L[(int64_t)(k + m) * n + rbeg + a] : cx<T>(0, 0); },
+        [&](int m, int a) {
+            Cx<T> v;
+            BufCx<T>::load(rl, ((uint32_t)(k + m) * n + rbeg + a) * (uint32_t)sizeof(Cx<T>), v.re, v.im);
+            return v;
+        },
         [&](int m, int a) {
             // L_kk^{-1}(a, m): 1 on the diagonal, stored at L(k + m, k + a) when m < a
             if (a >= b || m > a) return cx<T>(0, 0);
