@@ -117,6 +117,7 @@ struct PassArgs {
     const Cx<T>* dinv;         // the panel's reciprocal pivots
     const int* cmap;           // extend-add maps (concatenated)
     const int* pmap;           // parent positions (concatenated)
+    const int* hmap;           // matrix-core passes: parent pivot in h2 a first child adds into, or -1
     const Cx<double>* et;      // stretch tables
     const Cx<double>* src;     // forward: padded-grid input (column r at r * ld)
     Cx<double>* dst;           // backward: padded-grid output
@@ -142,8 +143,6 @@ struct PassArgs {
     // planes), written by the scatter at the start of a solve.
     Cx<T>* h2;
     const int* perm;           // elimination position -> box index of the panel class
-    int zero_aux;              // scatter: also write zeros on the auxiliary planes (a class
-                               // shared by panels with different auxiliary depths)
     int64_t gs_u, gs_c2, gs_h2;
     // split contraction (forms that divide each item's contraction over
     // nsplit workgroups): partial 64 x 16 blocks, item-major, then group,

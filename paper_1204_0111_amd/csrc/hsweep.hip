@@ -172,7 +172,6 @@ struct hsw_ctx {
     // right-hand-side region uses cls_perm_off
     std::vector<int64_t> cls_c2_base;
     int64_t total_c2 = 0, total_naux = 0;
-    std::vector<char> cls_mixed_ga;  // the class serves panels with different auxiliary depths
     int64_t et_size = 0;
     std::vector<int64_t> et_prob_off, et_panel_off;
 
@@ -183,6 +182,7 @@ struct hsw_ctx {
     int *d_perm = nullptr, *d_ulist = nullptr, *d_cmap = nullptr;
     int2* d_fwork = nullptr;
     int* d_pmap = nullptr;
+    int* d_hmap = nullptr;
     SolveItem* d_sitems = nullptr;
     Cx<double>* d_et = nullptr;
     double* d_c = nullptr;
@@ -299,7 +299,7 @@ static void free_all(hsw_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     if (ctx->gst) (void)hipStreamDestroy(ctx->gst);
     void* ptrs[] = {ctx->d_inst, ctx->d_pan, ctx->d_prob, ctx->d_perm, ctx->d_ulist,
-                    ctx->d_cmap, ctx->d_pmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
+                    ctx->d_cmap, ctx->d_pmap, ctx->d_hmap, ctx->d_fwork, ctx->d_sitems, ctx->d_et, ctx->d_c,
                     ctx->d_L, ctx->d_G != ctx->d_L ? ctx->d_G : nullptr, ctx->d_dinv, ctx->d_ws[0],
                     ctx->d_ws[1], ctx->d_err, ctx->d_T};
     for (void* p : ptrs)
@@ -419,14 +419,6 @@ static hsw_status plan_all(hsw_ctx* ctx, const hsw_problem* p, int nprob) {
         ctx->total_c2 += c.c2size;
         ctx->total_naux += c.naux;
         ctx->maxdepth = std::max(ctx->maxdepth, c.maxdepth);
-    }
-    ctx->cls_mixed_ga.assign(ctx->classes.size(), 0);
-    {
-        std::vector<int> ga_seen(ctx->classes.size(), -1);
-        for (const PanelDev& P : ctx->pan_h) {
-            if (ga_seen[P.cls] >= 0 && ga_seen[P.cls] != P.ga) ctx->cls_mixed_ga[P.cls] = 1;
-            ga_seen[P.cls] = P.ga;
-        }
     }
     // front instances
     int64_t loff = 0, doff = 0;
@@ -914,18 +906,20 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
     ACHK(dalloc(&ctx->d_inst, sizeof(FrontInst) * ctx->inst_h.size()));
     ACHK(dalloc(&ctx->d_pan, sizeof(PanelDev) * ctx->pan_h.size()));
     ACHK(dalloc(&ctx->d_prob, sizeof(ProbDev) * ctx->prob_h.size()));
-    std::vector<int> perm, ul, cm, pm;
+    std::vector<int> perm, ul, cm, pm, hm;
     for (auto& c : ctx->classes) {
         perm.insert(perm.end(), c.perm.begin(), c.perm.end());
         ul.insert(ul.end(), c.ulist.begin(), c.ulist.end());
         cm.insert(cm.end(), c.cmap.begin(), c.cmap.end());
         pm.insert(pm.end(), c.pmap.begin(), c.pmap.end());
+        hm.insert(hm.end(), c.hmap.begin(), c.hmap.end());
     }
     ACHK(dalloc(&ctx->d_perm, 4 * perm.size()));
     ACHK(dalloc(&ctx->d_ulist, 4 * std::max<size_t>(ul.size(), 1)));
     ACHK(dalloc(&ctx->d_cmap, 4 * std::max<size_t>(cm.size(), 1)));
     ACHK(dalloc(&ctx->d_fwork, 8 * std::max<size_t>(fwork.size(), 1)));
     ACHK(dalloc(&ctx->d_pmap, 4 * std::max<size_t>(pm.size(), 1)));
+    ACHK(dalloc(&ctx->d_hmap, 4 * std::max<size_t>(hm.size(), 1)));
     ACHK(dalloc(&ctx->d_sitems, sizeof(SolveItem) * std::max<size_t>(sitems.size(), 1)));
     ACHK(dalloc(&ctx->d_et, 16 * (size_t)eo));
     ACHK(dalloc(&ctx->d_L, (size_t)ctx->esz * ctx->L_size));
@@ -955,6 +949,8 @@ extern "C" hsw_status hsw_create(const hsw_problem* p, int32_t nprob, hsw_precis
         ACHK(hipMemcpyAsync(ctx->d_fwork, fwork.data(), 8 * fwork.size(), hipMemcpyHostToDevice, st));
     if (!pm.empty())
         ACHK(hipMemcpyAsync(ctx->d_pmap, pm.data(), 4 * pm.size(), hipMemcpyHostToDevice, st));
+    if (!hm.empty())
+        ACHK(hipMemcpyAsync(ctx->d_hmap, hm.data(), 4 * hm.size(), hipMemcpyHostToDevice, st));
     if (!sitems.empty())
         ACHK(hipMemcpyAsync(ctx->d_sitems, sitems.data(), sizeof(SolveItem) * sitems.size(),
                             hipMemcpyHostToDevice, st));
@@ -1314,6 +1310,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     A.dinv = (const Cx<T>*)ctx->d_dinv + f0.doff;
     A.cmap = ctx->d_cmap;
     A.pmap = ctx->d_pmap;
+    A.hmap = ctx->d_hmap;
     A.et = ctx->d_et;
     A.src = src;
     A.dst = dst;
@@ -1369,7 +1366,6 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         A.h2 = (Cx<T>*)ln.d_mh2 + 16 * cls_h2;
         A.part = (Cx<T>*)ln.d_mpart;
         A.perm = ctx->d_perm + P.perm_off;
-        A.zero_aux = ctx->cls_mixed_ga[P.cls];
         A.gs_u = 16 * std::max<int64_t>(ctx->max_wsize, 1);
         A.gs_c2 = 16 * std::max<int64_t>(ctx->total_c2, 1);
         A.gs_h2 = 16 * std::max<int64_t>(ctx->total_naux, 1);

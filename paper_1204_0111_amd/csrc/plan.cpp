@@ -193,6 +193,7 @@ std::string build_class(const LatTree& lt, int nz, PanelClass& pc) {
                 local = pc.s[p] + (int)(it - Up);
             }
             pc.pmap.push_back(local);
+            pc.hmap.push_back(pc.child0[p] == k && local < pc.s[p] ? pc.start[p] + local : -1);
         }
     }
     // storage offsets and work counts

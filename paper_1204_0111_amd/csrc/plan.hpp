@@ -101,6 +101,10 @@ struct PanelClass {
     std::vector<int> uoff, ulist;  // update sets, concatenated (elimination positions)
     std::vector<int> moff, cmap;   // per front 2 (s+u) entries: position in child 0 / 1 update set or -1
     std::vector<int> pmoff, pmap;  // per front u entries: position of each update entry in the parent front
+    // per front u entries, parallel to pmap: for the parent's first child, the
+    // elimination position of the parent pivot an update entry adds into
+    // (its contribution joins the parent's right-hand side there), else -1
+    std::vector<int> hmap;
     std::vector<int> c2off;        // per front: offset of its 2 (s+u) child-contribution slots
     int64_t c2size = 0;            // sum 2 (s+u)
     std::vector<int64_t> loff;     // per front: offset of its (s+u) x s block, relative to the panel

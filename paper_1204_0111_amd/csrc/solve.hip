@@ -455,23 +455,21 @@ __device__ inline void wave_lds_sync() {
 // workgroup and one group of 16 right-hand sides per blockIdx.y.  Mode 0
 // writes the panel's own planes (q >= ga); mode 1 writes J_{i+1,i}^T of the
 // next plane on the last plane and zeros on the other panel planes.  The
-// auxiliary planes (q < ga) stay zero: they are written (as zeros) only when
-// the class also serves a panel with fewer auxiliary planes (zero_aux).
+// auxiliary planes (q < ga) are written as zeros: the forward pass adds the
+// first children's contributions into this array, so every entry is set
+// anew at each solve.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
     if (A.run && !*A.run) return;
     __shared__ T Sre[64][17], Sim[64][17];
-    __shared__ int wr[64];
     const int e0 = blockIdx.x * 64, grp = blockIdx.y;
     const int tid = threadIdx.x, el = tid & 63;
     const int e = e0 + el;
     int64_t goff = -1;
     Cx<double> cf = cx<double>(1, 0);
-    bool write = false;
     if (e < A.naux) {
         const int b = A.perm[e];
         const int q = b / A.NxNy, lat = b - q * A.NxNy;
-        write = q >= A.ga || A.zero_aux;
         if (A.mode == 0) {
             if (q >= A.ga) goff = (int64_t)(A.lo + q - A.ga - A.plane0) * A.NxNy + lat;
         } else if (q == A.nz - 1) {
@@ -492,7 +490,6 @@ __global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
         Sre[el][r] = v.re;
         Sim[el][r] = v.im;
     }
-    if (tid < 64) wr[tid] = write;
     __syncthreads();
     // write whole [entry][16] blocks, sixteen consecutive threads per entry
     Cx<T>* h2 = A.h2 + grp * A.gs_h2;
@@ -500,7 +497,7 @@ __global__ __launch_bounds__(256) void k_rhs_scatter(PassArgs<T> A) {
     for (int j = 0; j < 4; ++j) {
         const int idx = tid + 256 * j;
         const int l = idx >> 4, r = idx & 15;
-        if (e0 + l < A.naux && wr[l]) h2[(int64_t)(e0 + l) * 16 + r] = cx<T>(Sre[l][r], Sim[l][r]);
+        if (e0 + l < A.naux) h2[(int64_t)(e0 + l) * 16 + r] = cx<T>(Sre[l][r], Sim[l][r]);
     }
 }
 
@@ -562,13 +559,26 @@ __device__ inline void sum_wave_blocks(const V4 (&acr)[R], const V4 (&aci)[R], T
     }
 }
 
-// RT row tiles of 16 per workgroup: each of the NW waves updates all of them
-// over every NW-th chunk of the contraction.  Launches with few workgroups
-// (the upper depths, with long contractions) take the wide form, NW = 8, to
-// shorten each wave's chain of chunks.
+// An update row's contribution d to the parent (right-hand side r of the
+// group): a first child adds it to the parent's right-hand side in h2 where
+// it lands on a parent pivot (hm >= 0: the one writer of that entry in the
+// launch, so the sum is that of a plain load and store), else it goes to the
+// child's half of the parent's slots at position pm.
+template <typename T>
+__device__ inline void push_update(const PassArgs<T>& A, const SolveItem& it, int grp, int hm, int pm, int r,
+                                   Cx<T> d) {
+    if (hm >= 0) {
+        Cx<T>* h = A.h2 + grp * A.gs_h2 + (int64_t)hm * 16 + r;
+        unsafeAtomicAdd(&h->re, d.re);
+        unsafeAtomicAdd(&h->im, d.im);
+    } else {
+        A.c2[grp * A.gs_c2 + (int64_t)(it.push + pm) * 16 + r] = d;
+    }
+}
+
 // The forward epilogue of one output (row, right-hand side r of the group):
 // x_S := D^{-1} y on a pivot row, the update part (the children's
-// contributions minus y) to the front's slot in its parent otherwise.
+// contributions minus y) to the parent otherwise.
 template <typename T>
 __device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int grp, int row, int r, Cx<T> y) {
     const int n = it.n, s = it.s;
@@ -579,10 +589,14 @@ __device__ inline void fwd_store(const PassArgs<T>& A, const SolveItem& it, int 
     } else {
         const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
         const Cx<T> pre = it.leaf ? cx<T>(0, 0) : c2f[(int64_t)row * 16 + r] + c2f[(int64_t)(n + row) * 16 + r];
-        A.c2[grp * A.gs_c2 + (int64_t)(it.push + A.pmap[it.pmap + row - s]) * 16 + r] = pre - y;
+        push_update(A, it, grp, A.hmap[it.pmap + row - s], A.pmap[it.pmap + row - s], r, pre - y);
     }
 }
 
+// RT row tiles of 16 per workgroup: each of the NW waves updates all of them
+// over every NW-th chunk of the contraction.  Launches with few workgroups
+// (the upper depths, with long contractions) take the wide form, NW = 8, to
+// shorten each wave's chain of chunks.
 // SK: split contraction.  Workgroup b takes item b / nsplit and the
 // (b mod nsplit)-th share of its chunks and stores its partial block; a
 // finishing launch (k_fwd_fin) sums the shares.
@@ -614,12 +628,12 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // them read zeros, so every chunk issues the same loads (the next
     // chunk's stay in flight during this one's products) and needs no bounds
     // test; rows past n give product rows that are never stored.
-    // A leaf has no children: its slots hold zeros and are not read (the
-    // descriptors of zero length return zeros without touching memory).
+    // v_S is h2 (the right-hand side, to which the first child has added its
+    // contributions on these pivots) plus the second child's half; a leaf has
+    // h2 alone.
     const uint32_t c2len = it.leaf ? 0u : (uint32_t)kend * 16 * ES;
     const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)kend * n * ES);
     const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
-    const BufRsrc r0 = buf_rsrc(c2f, c2len);
     const BufRsrc r1 = buf_rsrc(c2f + (int64_t)n * 16, c2len);
     // With one row tile, the epilogue's operands (1/D of a pivot row, or the
     // children's contributions and the parent position of an update row)
@@ -627,23 +641,25 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // arrive during the products instead of after them.
     const int erow = it.blk + (tid >> 4), er = tid & 15;
     Cx<T> e_d = cx<T>(0, 0), e_a = cx<T>(0, 0), e_b = cx<T>(0, 0);
-    int e_pm = 0;
+    int e_pm = 0, e_hm = -1;
     if constexpr (RT == 1) {
         const BufRsrc rd = buf_rsrc(A.dinv + it.start, (uint32_t)s * ES);
         const BufRsrc rp = buf_rsrc(A.pmap + it.pmap, (uint32_t)(n - s) * 4);
+        const BufRsrc rm = buf_rsrc(A.hmap + it.pmap, (uint32_t)(n - s) * 4);
         const BufRsrc rc = buf_rsrc(c2f, it.leaf ? 0u : (uint32_t)(2 * n) * 16 * ES);
         BufCx<T>::load(rd, (uint32_t)erow * ES, e_d.re, e_d.im);
         e_pm = buf_load_i32(rp, (uint32_t)(erow - s) * 4);
+        e_hm = buf_load_i32(rm, (uint32_t)(erow - s) * 4);
         BufCx<T>::load(rc, (uint32_t)(erow * 16 + er) * ES, e_a.re, e_a.im);
         BufCx<T>::load(rc, (uint32_t)((n + erow) * 16 + er) * ES, e_b.re, e_b.im);
     }
     // lane operands: A(row, k) = G(blk + 16 t + li, c + 4 q + lk) and
     // B(k, rhs) = v_S(c + 4 q + lk, li)
     T gre[RT][4], gim[RT][4];
-    T vre[3][4], vim[3][4];
+    T vre[2][4], vim[2][4];
     // np: the parts of v_S loaded (a leaf has the right-hand side alone, and
     // its loop issues no loads of the empty child slots)
-    auto load = [&](auto np, int c, T(&gr)[RT][4], T(&gi)[RT][4], T(&br)[3][4], T(&bi)[3][4]) {
+    auto load = [&](auto np, int c, T(&gr)[RT][4], T(&gi)[RT][4], T(&br)[2][4], T(&bi)[2][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t col = (uint32_t)(c + 4 * q + lk);
@@ -652,12 +668,10 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
                 BufCx<T>::load(rg, (col * n + it.blk + 16 * t + li) * ES, gr[t][q], gi[t][q]);
             const uint32_t vo = (col * 16 + li) * ES;
             BufCx<T>::load(rh, vo, br[0][q], bi[0][q]);
-            if constexpr (decltype(np)::value == 3) {
-                BufCx<T>::load(r0, vo, br[1][q], bi[1][q]);
-                BufCx<T>::load(r1, vo, br[2][q], bi[2][q]);
-            } else {
-                br[1][q] = bi[1][q] = br[2][q] = bi[2][q] = 0;
-            }
+            if constexpr (decltype(np)::value == 2)
+                BufCx<T>::load(r1, vo, br[1][q], bi[1][q]);
+            else
+                br[1][q] = bi[1][q] = 0;
         }
     };
     // accumulators: with one row tile the real and imaginary parts each take
@@ -675,10 +689,10 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     // chunks from the one holding the first live pivot (entries before it are zeros)
     const int kb = (leaf_first_live(A, it) / KC) * KC;
     const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
-    auto products = [&](const T(&gr)[RT][4], const T(&gi)[RT][4], const T(&vr)[3][4], const T(&vi)[3][4]) {
+    auto products = [&](const T(&gr)[RT][4], const T(&gi)[RT][4], const T(&vr)[2][4], const T(&vi)[2][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T br = vr[0][q] + vr[1][q] + vr[2][q], bi = vi[0][q] + vi[1][q] + vi[2][q];
+            const T br = vr[0][q] + vr[1][q], bi = vi[0][q] + vi[1][q];
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 are[t][0] = mfma4(gr[t][q], br, are[t][0]);
@@ -706,7 +720,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     if (it.leaf)
         chunks(std::integral_constant<int, 1>{});
     else
-        chunks(std::integral_constant<int, 3>{});
+        chunks(std::integral_constant<int, 2>{});
     if (SPLIT == 2) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -749,7 +763,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
             if (row < s) {
                 if (row >= leaf_aux_rows(it, A.ga)) xs[(int64_t)row * 16 + r] = y * e_d;
             } else {
-                c2g[(int64_t)(it.push + e_pm) * 16 + r] = (e_a + e_b) - y;
+                push_update(A, it, grp, e_hm, e_pm, r, (e_a + e_b) - y);
             }
         } else {
             fwd_store(A, it, grp, row, r, y);
@@ -796,9 +810,10 @@ __global__ __launch_bounds__(256) void k_fwd_fin(PassArgs<T> A) {
 // Row-split form of the forward matrix-core pass for fronts whose v_S fits
 // in LDS: the workgroup's 64 rows go one 16-row tile to each of its four
 // waves, so no partial sums are combined.  The workgroup stages its slice of
-// v_S (right-hand side plus the children's halves, summed) once in LDS,
-// together with what the epilogue needs (1/D of its pivot rows, the
-// children's contributions and parent positions of its update rows); each
+// v_S (right-hand side, which holds the first child's part, plus the second
+// child's half, summed) once in LDS, together with what the epilogue needs
+// (1/D of its pivot rows, the children's contributions and parent positions
+// of its update rows); each
 // wave then streams its rows of G with FP chunks of loads in flight, taking
 // the B operand from LDS.  The first FP chunks are issued before the staging
 // loads.  LDS: fwd_rs_lds_bytes.
@@ -823,7 +838,8 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
     Cx<T>* V = reinterpret_cast<Cx<T>*>(smem_raw);   // [nk16][16]
     Cx<T>* E = V + (int64_t)nk16 * 16;               // [ROWS][16]
     Cx<T>* Dv = E + ROWS * 16;                       // [ROWS]
-    int* PM = reinterpret_cast<int*>(Dv + ROWS);     // [ROWS], then one spare entry
+    int* PM = reinterpret_cast<int*>(Dv + ROWS);     // [ROWS]
+    int* HM = PM + ROWS;                             // [ROWS], then one spare entry
     const Cx<T>* c2f = A.c2 + grp * A.gs_c2 + (int64_t)it.c2 * 16;
     const Cx<T>* h2f = A.h2 + grp * A.gs_h2 + (int64_t)it.start * 16;
     // this wave's rows r0 .. r0 + 15 need the columns below kw (the triangle
@@ -853,10 +869,11 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         const uint32_t c2len = it.leaf ? 0u : (uint32_t)kend * 16 * ES;
         const uint32_t c2all = it.leaf ? 0u : (uint32_t)n * 16 * ES;
         const BufRsrc rh = buf_rsrc(h2f, (uint32_t)kend * 16 * ES);
-        const BufRsrc ra = buf_rsrc(c2f, c2len), rb = buf_rsrc(c2f + (int64_t)n * 16, c2len);
+        const BufRsrc rb = buf_rsrc(c2f + (int64_t)n * 16, c2len);
         const BufRsrc ea = buf_rsrc(c2f, c2all), eb = buf_rsrc(c2f + (int64_t)n * 16, c2all);
         const BufRsrc rd = buf_rsrc(A.dinv + it.start, (uint32_t)s * ES);
         const BufRsrc rp = buf_rsrc(A.pmap + it.pmap, (uint32_t)(n - s) * 4);
+        const BufRsrc rm = buf_rsrc(A.hmap + it.pmap, (uint32_t)(n - s) * 4);
         T er[4], ei[4], fr[4], fi[4], dr, di;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -868,34 +885,33 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         const int drow = it.blk + (tid & 63);
         BufCx<T>::load(rd, (uint32_t)drow * ES, dr, di);  // zero from s on
         const int pm = buf_load_i32(rp, (uint32_t)(drow - s) * 4);  // zero on pivot rows
-        Cx<T>* trash = reinterpret_cast<Cx<T>*>(PM + ROWS);  // 256 bytes past PM: aligned
+        const int hm = buf_load_i32(rm, (uint32_t)(drow - s) * 4);
+        Cx<T>* trash = reinterpret_cast<Cx<T>*>(HM + ROWS);  // 512 bytes past PM: aligned
         const int tot = nk16 * 16;
         constexpr int SU = 4;  // entries per thread and round
         auto stage = [&](auto np) {  // np: parts of v_S (a leaf: the right-hand side alone)
             for (int e0 = tid; e0 < tot; e0 += SU * 256) {
-                T hr[SU], hi[SU], ar[SU], ai[SU], br[SU], bi[SU];
+                T hr[SU], hi[SU], br[SU], bi[SU];
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
                     const uint32_t off = (uint32_t)(kb * 16 + e0 + 256 * u) * ES;
                     BufCx<T>::load(rh, off, hr[u], hi[u]);
-                    if constexpr (decltype(np)::value == 3) {
-                        BufCx<T>::load(ra, off, ar[u], ai[u]);
+                    if constexpr (decltype(np)::value == 2)
                         BufCx<T>::load(rb, off, br[u], bi[u]);
-                    } else {
-                        ar[u] = ai[u] = br[u] = bi[u] = 0;
-                    }
+                    else
+                        br[u] = bi[u] = 0;
                 }
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
                     const int e = e0 + 256 * u;
-                    *(e < tot ? V + e : trash) = cx<T>(hr[u] + ar[u] + br[u], hi[u] + ai[u] + bi[u]);
+                    *(e < tot ? V + e : trash) = cx<T>(hr[u] + br[u], hi[u] + bi[u]);
                 }
             }
         };
         if (it.leaf)
             stage(std::integral_constant<int, 1>{});
         else
-            stage(std::integral_constant<int, 3>{});
+            stage(std::integral_constant<int, 2>{});
         // pivot rows take no contribution (their slots hold the children's
         // v_S parts, already summed above)
 #pragma unroll
@@ -906,6 +922,7 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         if (tid < ROWS) {
             Dv[tid] = cx<T>(dr, di);
             PM[tid] = pm;
+            HM[tid] = hm;
         }
     }
     __syncthreads();
@@ -933,7 +950,6 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
     b0 += b1;
     if (rhs0 + li >= A.nrhs) return;
     Cx<T>* xs = A.xu + grp * A.gs_u + (int64_t)(it.xu - s) * 16;  // the front's [x_S; -x_U]
-    Cx<T>* c2g = A.c2 + grp * A.gs_c2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int lrow = 16 * wave + mfma_out_row<T>(lk, r), row = it.blk + lrow;
@@ -942,17 +958,17 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         if (row < s) {
             if (row >= leaf_aux_rows(it, A.ga)) xs[(int64_t)row * 16 + li] = y * Dv[lrow];
         } else {
-            c2g[(int64_t)(it.push + PM[lrow]) * 16 + li] = E[lrow * 16 + li] - y;
+            push_update(A, it, grp, HM[lrow], PM[lrow], li, E[lrow * 16 + li] - y);
         }
     }
 }
 
 // LDS of k_fwd_rs for fronts of up to smax pivots (staged v_S, the
-// epilogue's contributions, 1/D and parent positions).
+// epilogue's contributions, 1/D and the two parent position maps).
 template <typename T>
 size_t fwd_rs_lds_bytes(int smax) {
     const size_t nk16 = (size_t)(smax + 15) / 16 * 16;
-    return (nk16 * 16 + 64 * 16 + 64 + 1) * sizeof(Cx<T>) + 64 * sizeof(int);
+    return (nk16 * 16 + 64 * 16 + 64 + 1) * sizeof(Cx<T>) + 2 * 64 * sizeof(int);
 }
 
 // CT column tiles of 16 per workgroup; NW waves split the rows of the
