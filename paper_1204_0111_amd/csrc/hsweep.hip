@@ -76,14 +76,14 @@ struct SolveLevel {
     // matrix-core passes: items of 64 rows / columns (0) or of 16 (1) per
     // pass, picked by the autotuner; -1: the fixed rule
     int mm_f = -1, mm_b = -1;
-    // algorithmic traffic: bytes per right-hand side of the vectors each pass
-    // reads and writes, and the G entries a pass needs (also its complex
-    // multiply-adds per right-hand side): those of the fronts with children,
-    // plus, for the leaves, only the columns from the first pivot on plane p
-    // (p = 0..nz): the passes skip the columns of a leaf that multiply exact zeros
-    double fwd_vec_bytes = 0, bwd_vec_bytes = 0;
+    // algorithmic traffic, for a panel whose own planes start at plane p
+    // (p = 0..nz): the G entries a pass needs (also its complex multiply-adds
+    // per right-hand side) -- those of the fronts with children, plus, for the
+    // leaves, only the columns from the first pivot on plane p, since the
+    // passes skip the columns of a leaf that multiply exact zeros -- and the
+    // bytes per right-hand side of the vectors each pass must read and write
     double g_inner = 0;
-    std::vector<double> g_leaf;
+    std::vector<double> g_leaf, fwd_vec, bwd_vec;
     double g_need(int p) const { return g_inner + g_leaf[p]; }
 };
 
@@ -755,9 +755,13 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 xcd_group_by(sitems, sl.boff[k], sitems.size(), [](const SolveItem& q) { return q.loff; });
             }
             sl.g_leaf.assign(c.nz + 1, 0.0);
+            sl.fwd_vec.assign(c.nz + 1, 0.0);
+            sl.bwd_vec.assign(c.nz + 1, 0.0);
+            const double es = ctx->esz;
             for (int f : c.at_depth[d]) {
-                if (c.child0[f] < 0 && c.child1[f] < 0) {
-                    const int cells = c.cellw[f] >> 16;
+                const bool leaf = c.child0[f] < 0 && c.child1[f] < 0;
+                const int cells = c.cellw[f] >> 16;  // pivots per plane (pivots are plane-major)
+                if (leaf) {
                     for (int p = 0; p <= c.nz; ++p) {
                         const double r = std::max(0, c.s[f] - p * cells);
                         sl.g_leaf[p] += r * (r + 1) / 2 + (double)c.u[f] * r;
@@ -767,17 +771,24 @@ static void schedule_all(hsw_ctx* ctx, std::vector<int2>& fwork, std::vector<Sol
                 }
                 sl.smax = std::max(sl.smax, c.s[f]);
                 sl.nmax = std::max(sl.nmax, c.s[f] + c.u[f]);
-                const double sd = c.s[f], ud = c.u[f];
                 double uc = 0;
                 for (int ch : {c.child0[f], c.child1[f]})
                     if (ch >= 0) uc += c.u[ch];
-                const double es = ctx->esz;
-                // forward: right-hand side (complex128, deepest use), children's
-                // contributions, 1/D, x_mid and the update part written
-                sl.fwd_vec_bytes += 16 * sd + es * (uc + 3 * sd + ud);
-                // backward: x_mid and x_U read, x_S to the grid (complex128) and
-                // to the children's update-set values
-                sl.bwd_vec_bytes += es * (sd + ud + uc) + 16 * sd;
+                for (int p = 0; p <= c.nz; ++p) {
+                    // pivots on the panel's own planes (p auxiliary planes
+                    // below them), and the pivots the forward pass carries: a
+                    // leaf's auxiliary pivots have zero right-hand sides and
+                    // no children, so they stay zero
+                    const double grid = std::max(0, c.s[f] - p * cells);
+                    const double live = leaf ? grid : c.s[f];
+                    // forward: v_S read (right-hand side with the children's
+                    // parts added), the children's contributions, x_S and the
+                    // update part written
+                    sl.fwd_vec[p] += es * (2 * live + uc + c.u[f]);
+                    // backward: [x_S; -x_U] read, the children's update-set
+                    // values written, x_S to the grid (complex128)
+                    sl.bwd_vec[p] += es * (live + c.u[f] + uc) + 16 * grid;
+                }
             }
             const int dflt = sl.nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
             for (int key = 0; key < N_RHS_KEYS; ++key) sl.fsel[key] = sl.bsel[key] = dflt;
@@ -1391,10 +1402,10 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 form = rt4 ? 0 : 1;
                 if (lv[d].fcount[rt4 ? 0 : 1] * groups < MM_WIDE_BELOW) form += 3;
             }
-            const int fs = (form == 1 || form == 4) ? 1 : 0;
+            const int fs = (form == 1 || form == 4) ? 1 : 0;  // items of 16 rows
             A.items = ctx->d_sitems + lv[d].foff[fs];
             A.nsplit = mm_split(lv[d].fcount[fs], groups);
-            run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec_bytes,
+            run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec[pf],
                 8.0 * nrhs * lv[d].g_need(pf),
                 [&] { launch_fwd_mm<T>(A, lv[d].fcount[fs], form, lv[d].smax, st); });
         }
@@ -1413,7 +1424,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
             const int bs = (form == 0 || form == 4) ? MM_BWD_SHAPE64 : MM_BWD_SHAPE;
             A.items = ctx->d_sitems + lv[d].boff[bs];
             A.nsplit = mm_split(lv[d].bcount[bs], groups);
-            run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec_bytes,
+            run("bwd", lv[d].bcount[bs], es * lv[d].g_need(pb) * groups + nrhs * lv[d].bwd_vec[pb],
                 8.0 * nrhs * lv[d].g_need(pb), [&] { launch_bwd_mm<T>(A, lv[d].bcount[bs], form, st); });
         }
         return;
@@ -1424,12 +1435,12 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         if (k == TRI_F && !tri_ok) k = lv[d].nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
         if (k == TRI_F) {
             AT.items = ctx->d_sitems + lv[d].toff;
-            run("fwd", lv[d].tcount, es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec_bytes,
+            run("fwd", lv[d].tcount, es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec[pf],
                 8.0 * nrhs * lv[d].g_need(pf), [&] { launch_tri<T>(AT, lv[d].tcount, lv[d].nmax, true, st); });
             continue;
         }
         A.items = ctx->d_sitems + lv[d].foff[k];
-        run("fwd", lv[d].fcount[k], es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec_bytes,
+        run("fwd", lv[d].fcount[k], es * lv[d].g_need(pf) + nrhs * lv[d].fwd_vec[pf],
             8.0 * nrhs * lv[d].g_need(pf),
             [&] { launch_fwd<T>(A, lv[d].fcount[k], k, lv[d].smax, lv[d].nmax, st); });
     }
@@ -1439,12 +1450,12 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
         if (k == TRI_B && !tri_ok) k = lv[d].nmax >= SOLVE_SMALL_BLOCK_N ? 1 : 0;
         if (k == TRI_B) {
             AT.items = ctx->d_sitems + lv[d].toff;
-            run("bwd", lv[d].tcount, es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec_bytes,
+            run("bwd", lv[d].tcount, es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec[pb],
                 8.0 * nrhs * lv[d].g_need(pb), [&] { launch_tri<T>(AT, lv[d].tcount, lv[d].nmax, false, st); });
             continue;
         }
         A.items = ctx->d_sitems + lv[d].boff[k];
-        run("bwd", lv[d].bcount[k], es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec_bytes,
+        run("bwd", lv[d].bcount[k], es * lv[d].g_need(pb) + nrhs * lv[d].bwd_vec[pb],
             8.0 * nrhs * lv[d].g_need(pb),
             [&] { launch_bwd<T>(A, lv[d].bcount[k], k, lv[d].nmax, st); });
     }
@@ -1612,11 +1623,16 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
             for (int k = 1; k < NB; ++k)
                 if (tb[d][k] < tb[d][sl.mm_b]) sl.mm_b = k;
             if (ctx->tune_report) {
-                fprintf(stderr, "tune class %zu depth %d fwd", ci, d);
+                // algorithmic bytes of each pass at this depth (as the pass timers count them)
+                const int ga = ctx->pan_h[panels[panels.size() / 2]].ga;  // a middle panel's
+                const double fb = ctx->esz * sl.g_need(ga) + NR * sl.fwd_vec[ga];
+                const double bb = ctx->esz * sl.g_need(ga) + NR * sl.bwd_vec[ga];
+                fprintf(stderr, "tune class %zu depth %d fronts %zu fwd", ci, d, c.at_depth[d].size());
                 for (int k = 0; k < NF; ++k) fprintf(stderr, " %.1f", 1e3 * tf[d][k]);
-                fprintf(stderr, " -> %d  bwd", sl.mm_f);
+                fprintf(stderr, " -> %d (%.1f MB, %.2f TB/s)  bwd", sl.mm_f, fb / 1e6,
+                        fb / (1e9 * tf[d][sl.mm_f]));
                 for (int k = 0; k < NB; ++k) fprintf(stderr, " %.1f", 1e3 * tb[d][k]);
-                fprintf(stderr, " -> %d (us)\n", sl.mm_b);
+                fprintf(stderr, " -> %d (%.1f MB, %.2f TB/s) (us)\n", sl.mm_b, bb / 1e6, bb / (1e9 * tb[d][sl.mm_b]));
             }
         }
     }

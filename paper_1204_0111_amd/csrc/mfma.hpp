@@ -1,7 +1,8 @@
 // Matrix-core primitives shared by the front and solve kernels.
 //
 // A complex tile product is four real products per 16 x 16 x 4 step (there
-// is no complex MFMA instruction): FP32 MFMA for complex64 and FP64 MFMA for
+// is no complex MFMA instruction), or three in the solve passes, which add
+// the operands' parts first: FP32 MFMA for complex64 and FP64 MFMA for
 // complex128, accumulating in the same precision.  Operand layout of the
 // 16 x 16 x 4 instructions: lane l supplies A(l % 16, k) and B(k, l % 16) for
 // k = l / 16; register r of lane l receives D(mfma_out_row(l / 16, r), l % 16).

@@ -559,6 +559,17 @@ __device__ inline void sum_wave_blocks(const V4 (&acr)[R], const V4 (&aci)[R], T
     }
 }
 
+// Complex products on the real matrix cores with three real products
+// instead of four (the three-multiplication form of the complex product): for
+// G = a + ib and v = c + id,
+//   k1 += (a + b) c,  k2 += a (d - c),  k3 += b (c + d),
+// and then Re(G v) = k1 - k3, Im(G v) = k1 + k2.
+template <typename V4>
+__device__ inline void cmul3_finish(const V4& k1, const V4& k2, const V4& k3, V4& re, V4& im) {
+    re = k1 - k3;
+    im = k1 + k2;
+}
+
 // An update row's contribution d to the parent (right-hand side r of the
 // group): a first child adds it to the parent's right-hand side in h2 where
 // it lands on a parent pivot (hm >= 0: the one writer of that entry in the
@@ -674,18 +685,11 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
                 br[1][q] = bi[1][q] = 0;
         }
     };
-    // accumulators: with one row tile the real and imaginary parts each take
-    // two (products of the real and of the imaginary part of G), so that four
-    // independent chains share the matrix core instead of two
-    constexpr int SPLIT = RT == 1 ? 2 : 1;
-    V4 are[RT][SPLIT], aim[RT][SPLIT];
+    // complex products with three real ones (cmul3): three independent
+    // accumulator chains per row tile
+    V4 k1[RT], k2[RT], k3[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int h = 0; h < SPLIT; ++h) {
-            are[t][h] = V4{0, 0, 0, 0};
-            aim[t][h] = V4{0, 0, 0, 0};
-        }
+    for (int t = 0; t < RT; ++t) k1[t] = k2[t] = k3[t] = V4{0, 0, 0, 0};
     // chunks from the one holding the first live pivot (entries before it are zeros)
     const int kb = (leaf_first_live(A, it) / KC) * KC;
     const int nch = kend > kb ? (kend - kb + KC - 1) / KC : 0;
@@ -693,15 +697,12 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T br = vr[0][q] + vr[1][q], bi = vi[0][q] + vi[1][q];
+            const T bs = br + bi, bd = bi - br;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                are[t][0] = mfma4(gr[t][q], br, are[t][0]);
-                aim[t][0] = mfma4(gr[t][q], bi, aim[t][0]);
-            }
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                are[t][SPLIT - 1] = mfma4(-gi[t][q], bi, are[t][SPLIT - 1]);
-                aim[t][SPLIT - 1] = mfma4(gi[t][q], br, aim[t][SPLIT - 1]);
+                k1[t] = mfma4(gr[t][q] + gi[t][q], br, k1[t]);
+                k2[t] = mfma4(gr[t][q], bd, k2[t]);
+                k3[t] = mfma4(gi[t][q], bs, k3[t]);
             }
         }
     };
@@ -721,22 +722,12 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         chunks(std::integral_constant<int, 1>{});
     else
         chunks(std::integral_constant<int, 2>{});
-    if (SPLIT == 2) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            are[t][0] += are[t][SPLIT - 1];
-            aim[t][0] += aim[t][SPLIT - 1];
-        }
-    }
     // sum the waves' partial blocks
     {
         __shared__ T Pre[WaveSum<T, RT, NW>::PLEN], Pim[WaveSum<T, RT, NW>::PLEN];
         V4 acr[RT], aci[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            acr[t] = are[t][0];
-            aci[t] = aim[t][0];
-        }
+        for (int t = 0; t < RT; ++t) cmul3_finish(k1[t], k2[t], k3[t], acr[t], aci[t]);
         sum_wave_blocks<T, RT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
     }
     if constexpr (SK != 0) {
@@ -926,15 +917,14 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
         }
     }
     __syncthreads();
-    V4 a0 = V4{0, 0, 0, 0}, a1 = V4{0, 0, 0, 0}, b0 = V4{0, 0, 0, 0}, b1 = V4{0, 0, 0, 0};
+    V4 k1 = V4{0, 0, 0, 0}, k2 = V4{0, 0, 0, 0}, k3 = V4{0, 0, 0, 0};  // cmul3
     auto products = [&](int ch, const T(&gr)[4], const T(&gi)[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const Cx<T> v = V[(ch * KC + 4 * q + lk) * 16 + li];
-            a0 = mfma4(gr[q], v.re, a0);
-            b0 = mfma4(gr[q], v.im, b0);
-            a1 = mfma4(-gi[q], v.im, a1);
-            b1 = mfma4(gi[q], v.re, b1);
+            k1 = mfma4(gr[q] + gi[q], v.re, k1);
+            k2 = mfma4(gr[q], v.im - v.re, k2);
+            k3 = mfma4(gi[q], v.re + v.im, k3);
         }
     };
     // chunk ch + j sits in buffer j; each buffer is refilled with the chunk
@@ -946,8 +936,8 @@ __global__ __launch_bounds__(256) void k_fwd_rs(PassArgs<T> A) {
             load(ch + j + FP, gre[j], gim[j]);
         }
     }
-    a0 += a1;
-    b0 += b1;
+    V4 a0, b0;
+    cmul3_finish(k1, k2, k3, a0, b0);
     if (rhs0 + li >= A.nrhs) return;
     Cx<T>* xs = A.xu + grp * A.gs_u + (int64_t)(it.xu - s) * 16;  // the front's [x_S; -x_U]
 #pragma unroll
@@ -1103,16 +1093,9 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     const BufRsrc rg = buf_rsrc(A.G + it.loff, (uint32_t)s * n * ES);
     const BufRsrc rs = buf_rsrc(xsu, (uint32_t)n * 16 * ES);
     T gre[CT][4], gim[CT][4], sre[4], sim[4];
-    // with one column tile, four accumulator chains instead of two (as in k_fwd_mm)
-    constexpr int SPLIT = CT == 1 ? 2 : 1;
-    V4 are[CT][SPLIT], aim[CT][SPLIT];
+    V4 k1[CT], k2[CT], k3[CT];  // cmul3, as in k_fwd_mm
 #pragma unroll
-    for (int t = 0; t < CT; ++t)
-#pragma unroll
-        for (int h = 0; h < SPLIT; ++h) {
-            are[t][h] = V4{0, 0, 0, 0};
-            aim[t][h] = V4{0, 0, 0, 0};
-        }
+    for (int t = 0; t < CT; ++t) k1[t] = k2[t] = k3[t] = V4{0, 0, 0, 0};
     // rows above the block's first column are zeros of G_TL; a leaf's
     // auxiliary rows are skipped (leaf_aux_rows)
     const int ib0 = max(c0, leaf_aux_rows(it, A.ga));
@@ -1133,15 +1116,12 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const T br = sr[m], bi = si[m];
+            const T bs = br + bi, bd = bi - br;
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-                are[t][0] = mfma4(gr[t][m], br, are[t][0]);
-                aim[t][0] = mfma4(gr[t][m], bi, aim[t][0]);
-            }
-#pragma unroll
-            for (int t = 0; t < CT; ++t) {
-                are[t][SPLIT - 1] = mfma4(-gi[t][m], bi, are[t][SPLIT - 1]);
-                aim[t][SPLIT - 1] = mfma4(gi[t][m], br, aim[t][SPLIT - 1]);
+                k1[t] = mfma4(gr[t][m] + gi[t][m], br, k1[t]);
+                k2[t] = mfma4(gr[t][m], bd, k2[t]);
+                k3[t] = mfma4(gi[t][m], bs, k3[t]);
             }
         }
     };
@@ -1177,22 +1157,12 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             products(gre, gim, sre, sim);
         }
     }
-    if (SPLIT == 2) {
-#pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            are[t][0] += are[t][SPLIT - 1];
-            aim[t][0] += aim[t][SPLIT - 1];
-        }
-    }
     // sum the waves' partial blocks
     {
         __shared__ T Pre[WaveSum<T, CT, NW>::PLEN], Pim[WaveSum<T, CT, NW>::PLEN];
         V4 acr[CT], aci[CT];
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            acr[t] = are[t][0];
-            aci[t] = aim[t][0];
-        }
+        for (int t = 0; t < CT; ++t) cmul3_finish(k1[t], k2[t], k3[t], acr[t], aci[t]);
         sum_wave_blocks<T, CT, NW>(acr, aci, Yre, Yim, Pre, Pim, wave, li, lk, tid);
     }
     if constexpr (SK != 0) {
