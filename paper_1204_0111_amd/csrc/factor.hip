@@ -163,15 +163,61 @@ __device__ inline void tile_cgemm(typename MfmaAcc<T>::type (&are)[2][2],
     }
 }
 
+// The same tile product with each complex product as three real ones (the
+// three-multiplication form): with C = a + ib and R = c + id, k1 += (a + b) c,
+// k2 += a (d - c) and k3 += b (c + d); the product's real part is k1 - k3, its
+// imaginary part k1 + k2 (cgemm64_pipe folds them in).  A quarter fewer
+// matrix-core products for one more accumulator block per 16 x 16 block.
+template <typename T, int KC>
+__device__ inline void tile_cgemm3(typename MfmaAcc<T>::type (&k1)[2][2],
+                                   typename MfmaAcc<T>::type (&k2)[2][2],
+                                   typename MfmaAcc<T>::type (&k3)[2][2], const T (*Rre)[LDP],
+                                   const T (*Rim)[LDP], const T (*Cre)[LDP], const T (*Cim)[LDP],
+                                   int kmax) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const int li = l & 15, lk = l >> 4;
+#pragma unroll 2
+    for (int kk = 0; kk < KC; kk += 4) {
+        if (kk >= kmax) break;
+        T cr[2], ci[2], rr[2], ri[2], cs[2], rd[2], rs[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            cr[q] = Cre[kk + lk][wc + 16 * q + li];
+            ci[q] = Cim[kk + lk][wc + 16 * q + li];
+            rr[q] = Rre[kk + lk][wr + 16 * q + li];
+            ri[q] = Rim[kk + lk][wr + 16 * q + li];
+            cs[q] = cr[q] + ci[q];
+            rd[q] = ri[q] - rr[q];
+            rs[q] = rr[q] + ri[q];
+        }
+        // three rounds of four independent products
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) k1[bi][bj] = mfma4(cs[bj], rr[bi], k1[bi][bj]);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) k2[bi][bj] = mfma4(cr[bj], rd[bi], k2[bi][bj]);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) k3[bi][bj] = mfma4(ci[bj], rs[bi], k3[bi][bj]);
+    }
+}
+
 // acc += R C^T over k < K for a 64 x 64 tile, R and C read from memory by
 // ldR(k, row) and ldC(k, col) in chunks of KC columns.  Software pipelined:
 // the loads of chunk c + 1 are in flight while chunk c runs on the matrix
 // cores from one of two LDS buffers, so one barrier per chunk suffices.
 // CT picks the thread mapping of the C loads: false, consecutive threads read
 // consecutive cols (contiguous when C is stored [k][col]); true, consecutive
-// k (contiguous when C is stored [col][k]).  Ends with a barrier (except for
-// K <= 0, which returns at once); the caller's LDS buffers are free afterwards.
-template <typename T, int KC, bool CT = false, typename LR, typename LC>
+// k (contiguous when C is stored [col][k]).  M3 takes the three-product tile
+// (tile_cgemm3), for the callers whose occupancy its extra accumulators do
+// not lower.  Ends with a barrier (except for K <= 0, which returns at once);
+// the caller's LDS buffers are free afterwards.
+template <typename T, int KC, bool CT = false, bool M3 = false, typename LR, typename LC>
 __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
                                     typename MfmaAcc<T>::type (&aim)[2][2], int K, LR ldR, LC ldC,
                                     T (*Rre)[KC][LDP], T (*Rim)[KC][LDP], T (*Cre)[KC][LDP],
@@ -224,12 +270,40 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
     fetch(0);
     put(0);
     __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nch) fetch((ch + 1) * KC);
-        tile_cgemm<T, KC>(are, aim, Rre[buf], Rim[buf], Cre[buf], Cim[buf], K - ch * KC);
-        if (ch + 1 < nch) put(buf ^ 1);
-        __syncthreads();
+    if constexpr (M3) {
+        // the three-product accumulators start from the incoming sums:
+        // re = k1 - k3 and im = k1 + k2 with k1 = 0, k2 = im, k3 = -re
+        typename MfmaAcc<T>::type k1[2][2], k2[2][2], k3[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                k1[bi][bj] = typename MfmaAcc<T>::type{0, 0, 0, 0};
+                k2[bi][bj] = aim[bi][bj];
+                k3[bi][bj] = -are[bi][bj];
+            }
+        for (int ch = 0; ch < nch; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nch) fetch((ch + 1) * KC);
+            tile_cgemm3<T, KC>(k1, k2, k3, Rre[buf], Rim[buf], Cre[buf], Cim[buf], K - ch * KC);
+            if (ch + 1 < nch) put(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                are[bi][bj] = k1[bi][bj] - k3[bi][bj];
+                aim[bi][bj] = k1[bi][bj] + k2[bi][bj];
+            }
+    } else {
+        for (int ch = 0; ch < nch; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nch) fetch((ch + 1) * KC);
+            tile_cgemm<T, KC>(are, aim, Rre[buf], Rim[buf], Cre[buf], Cim[buf], K - ch * KC);
+            if (ch + 1 < nch) put(buf ^ 1);
+            __syncthreads();
+        }
     }
 }
 
@@ -734,7 +808,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(const int2* __restrict__ wor
     // P(r, m) through a descriptor cut at the front's n x s block: rows past
     // rend read finite values that reach only rows never stored
     const BufRsrc rl = buf_rsrc(L, (uint32_t)n * f.s * (uint32_t)sizeof(Cx<T>));
-    cgemm64_pipe<T, KC, true>(  // L_kk^{-1}(a, m) is contiguous in m: transposed C loads
+    cgemm64_pipe<T, KC, true, true>(  // L_kk^{-1}(a, m) is contiguous in m: transposed C loads
         are, aim, b,
         [&](int m, int a) {
             Cx<T> v;
@@ -955,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
         // L_F^{-1} are zero right of the diagonal, so a block of such rows stops
         // at its own last row.
         const int kend = r0 + 64 <= s ? r0 + 64 : s;
-        cgemm64_pipe<T, KC, true>(
+        cgemm64_pipe<T, KC, true, true>(
             are, aim, kend - c1,
             [&](int m, int a) { return r0 + a < n ? *xat(r0 + a, c1 + m) : cx<T>(0, 0); },
             [&](int m, int a) { return a < bw ? L[(int64_t)(c0 + a) * n + c1 + m] : cx<T>(0, 0); },
@@ -982,7 +1056,7 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 }
         __syncthreads();
         // X_blk = acc L_blk^{-1}: X(r, j) = sum_{m >= j} acc(r, m) Linv(m, j)
-        cgemm64_pipe<T, KC>(
+        cgemm64_pipe<T, KC, false, true>(
             are, aim, bw, [&](int m, int a) { return cx<T>(Are[m][a], Aim[m][a]); },
             [&](int m, int a) {
                 // Linv(m, a) for m > a is stored at L(c0 + a, c0 + m) (upper triangle)
