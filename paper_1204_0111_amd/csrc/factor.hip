@@ -867,8 +867,11 @@ __device__ inline double round_bf16(double x) { return x; }
 // bf16: 0 complex products in the working precision; 1 complex BF16 inputs
 // on the BF16 matrix cores (BF, complex64 only); 2 the same bf16-rounded
 // inputs on the FP32 matrix cores.
+// Complex64 without BF16 inputs takes the three-product tile and is held to
+// 128 registers (4 waves per SIMD, which its LDS allows); complex128 keeps
+// four products (its extra accumulator blocks would cost occupancy).
 template <typename T, bool BF>
-__global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && !BF) ? 4 : 1) void k_update(const int2* __restrict__ work,
                                                 const FrontInst* __restrict__ inst,
                                                 Cx<T>* __restrict__ Lb, Cx<T>* __restrict__ Wcur,
                                                 int k, int mode, int bf16) {
@@ -953,7 +956,7 @@ __global__ __launch_bounds__(256) void k_update(const int2* __restrict__ work,
                 are, aim, K, [&](int m, int a) { return rnd(ldR(m, a)); },
                 [&](int m, int a) { return rnd(ldC(m, a)); }, Rre, Rim, Cre, Cim);
         } else {
-            cgemm64_pipe<T, KC>(are, aim, K, ldR, ldC, Rre, Rim, Cre, Cim);
+            cgemm64_pipe<T, KC, false, sizeof(T) == 4>(are, aim, K, ldR, ldC, Rre, Rim, Cre, Cim);
         }
     }
 #pragma unroll
