@@ -33,16 +33,24 @@ __device__ inline Cx<T>* front_at(Cx<T>* L, Cx<T>* W, int n, int s, int u, int i
     return j < s ? L + (int64_t)j * n + i : W + (int64_t)(j - s) * u + (i - s);
 }
 
-// Entry H(bi, bj) of a panel's auxiliary operator between box nodes bi, bj
-// (box index a1 + a2 Nx + q Nx Ny); zero when they are not stencil neighbours.
-__device__ inline Cx<double> aux_entry(const ProbDev& Q, const PanelDev& P, const Cx<double>* et,
-                                       int bi, int bj, Cx<double> kappa2, double inv_h2) {
+// A box node's coordinates (a1, a2, q) of box index a1 + a2 Nx + q Nx Ny,
+// packed 16 bits each (panel boxes are far below 65536 nodes per axis).
+__device__ inline uint64_t box_coords(const PanelDev& P, int b) {
     const int NxNy = P.Nx * P.Ny;
-    int qi = bi / NxNy, ri = bi - qi * NxNy, a2i = ri / P.Nx, a1i = ri - a2i * P.Nx;
-    int qj = bj / NxNy, rj = bj - qj * NxNy, a2j = rj / P.Nx, a1j = rj - a2j * P.Nx;
+    const int q = b / NxNy, r = b - q * NxNy, a2 = r / P.Nx, a1 = r - a2 * P.Nx;
+    return (uint64_t)(uint32_t)a1 | ((uint64_t)(uint32_t)a2 << 16) | ((uint64_t)(uint32_t)q << 32);
+}
+
+// Entry H(bi, bj) of a panel's auxiliary operator between box nodes with
+// packed coordinates ci, cj (box_coords); zero when they are not stencil
+// neighbours.
+__device__ inline Cx<double> aux_entry(const ProbDev& Q, const PanelDev& P, const Cx<double>* et,
+                                       uint64_t ci, uint64_t cj, Cx<double> kappa2, double inv_h2) {
+    const int a1i = (int)(ci & 0xffff), a2i = (int)((ci >> 16) & 0xffff), qi = (int)(ci >> 32);
+    const int a1j = (int)(cj & 0xffff), a2j = (int)((cj >> 16) & 0xffff), qj = (int)(cj >> 32);
     const Cx<double>* e3n = et + P.e3_off;
     const Cx<double>* ie3 = et + P.e3_off + P.nz;
-    if (bi == bj) {
+    if (ci == cj) {
         NodeStretch st = node_stretch(Q, et, a1i, a2i, e3n, ie3, qi);
         double c = velocity_at(Q, a1i, a2i, P.lo - P.ga + qi);
         return diag_entry(st, c, kappa2, inv_h2);
@@ -77,17 +85,19 @@ __global__ __launch_bounds__(256) void k_assemble(const int2* __restrict__ work,
     int ti, tj;
     tri_decode_dev(w.y, ti, tj);
     const int r0 = ti * TILE, c0 = tj * TILE;
-    __shared__ int rpos[2][TILE], cpos[2][TILE], rbox[TILE], cbox[TILE];
+    __shared__ int rpos[2][TILE], cpos[2][TILE];
+    __shared__ uint64_t rbox[TILE], cbox[TILE];  // box coordinates (box_coords) of the rows and columns
     const int tid = threadIdx.x;
     const PanelDev P = pan[f.panel];
     if (tid < 2 * TILE) {
         const bool isrow = tid < TILE;
         const int l = isrow ? tid : tid - TILE;
         const int i = (isrow ? r0 : c0) + l;
-        int bx = -1, p0 = -1, p1 = -1;
+        uint64_t bx = 0;
+        int p0 = -1, p1 = -1;
         if (i < n) {
             int e = i < f.s ? f.start + i : ulist[f.uoff + i - f.s];
-            bx = perm[P.perm_off + e];
+            bx = box_coords(P, perm[P.perm_off + e]);
             if (f.child0 >= 0) p0 = cmap[f.moff + i];
             if (f.child1 >= 0) p1 = cmap[f.moff + n + i];
         }
