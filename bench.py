@@ -38,12 +38,12 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp64_mfma": 78.6}
 KERNEL_CLASSES = ["fwd", "bwd", "scatter", "diag", "panel", "trailing", "schur", "assemble", "inverse",
                   "matvec"]
-MM_MIN_RHS = 16  # right-hand-side groups of this size run the matrix-core solve passes
+MM_FROM = 4  # solves with this many right-hand sides or more take the matrix-core passes (mm_min_rhs)
 
 
 def kernel_info(kclass, nrhs):
     """(symbol in rocprof output, bound, source file) of a kernel class."""
-    mm = nrhs >= MM_MIN_RHS
+    mm = nrhs >= MM_FROM
     return {"fwd": ("k_fwd_mm" if mm else "k_fwd", "hbm", "solve.hip"),
             "bwd": ("k_bwd_mm" if mm else "k_bwd", "hbm", "solve.hip"),
             "scatter": ("k_rhs_scatter", "hbm", "solve.hip"),
@@ -385,6 +385,8 @@ def sub_record(rec):
         out["comparator"] = c128
         out["speedup_vs_fp64"] = (c64["value"] / c128["value"]) if c64["value"] and c128.get("value") \
             else None
+    if rec.get("roofline") is not None:
+        out["roofline"] = rec["roofline"]
     return out
 
 
@@ -408,7 +410,7 @@ def main():
                     help="skip the GMRES variant with the convergence test on the device")
     ap.add_argument("--set", default="",
                     help="context options of the headline's complex64 run, as key=value,... "
-                         "(e.g. mm_fwd_form=7; see hsw_set_option)")
+                         "(e.g. mm_fwd_form=2; see hsw_set_option)")
     ap.add_argument("--rhs-group", type=int, default=0,
                     help="solve the right-hand sides in groups of this many columns")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -442,7 +444,7 @@ def main():
     subs = {}
     for name in [s for s in args.sub.split(",") if s and s != args.workload]:
         rec = measure_workload(name, args.steps, args.warmup, comparator=not args.no_comparator,
-                               log=log)
+                               roofline=not args.no_roofline, log=log)
         subs[name] = sub_record(rec)
     cpu = None
     if not args.no_cpu_baseline:

@@ -275,8 +275,13 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *              pivots before it is factored, F_BR once at the end); 2 or -1
  *              (default) hybrid: right-looking over the pivot columns, F_BR
  *              once at the end.  The factors agree to rounding.
- *   "mm_fwd_form", "mm_bwd_form" the form of the matrix-core passes (16 or
- *              more right-hand sides) at every tree depth; -1 (default): the
+ *   "mm_min_rhs" 1..16 (default 4): solves (hsw_solve, hsw_apply,
+ *              hsw_panel_solve) with at least this many right-hand sides take
+ *              the matrix-core passes, in groups of 16 (the last one padded
+ *              with zeros); fewer take the single-vector passes.
+ *              hsw_apply_noalloc always takes the single-vector passes.
+ *   "mm_fwd_form", "mm_bwd_form" the form of the matrix-core passes (see
+ *              mm_min_rhs) at every tree depth; -1 (default): the
  *              autotuner's choice per panel class and depth.  Forward
  *              (-1..5): 0 / 3 workgroups of 64 rows whose 4 / 8 waves split
  *              the contraction, 1 / 4 workgroups of 16 rows with 4 / 8

@@ -209,6 +209,9 @@ struct hsw_ctx {
     // matrix-core pass forms for every depth (-1: the tuned choice; the
     // forms of launch_fwd_mm and launch_bwd_mm)
     int mm_fwd_form = -1, mm_bwd_form = -1;
+    // right-hand-side count from which the solves take the matrix-core passes
+    // (groups of 16, the last one padded)
+    int mm_min_rhs = MM_DEFAULT_FROM;
     std::vector<SweepGraph> graphs;
     hipStream_t gst = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -1072,6 +1075,9 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
             for (bool& t : ctx->tuned) t = false;  // the triangular passes come and go with the factors
             drop_graphs(ctx);
         }
+    } else if (k == "mm_min_rhs") {
+        if (value < 1 || value > MM_MIN_RHS) return fail(ctx, HSW_E_INVAL, "mm_min_rhs is 1..16");
+        ctx->mm_min_rhs = (int)value;
     } else if (k == "mm_fwd_form") {
         if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..5");
         ctx->mm_fwd_form = (int)value;
@@ -1232,7 +1238,7 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups);
 
 template <typename T>
 static hsw_status ensure_solve_ws(hsw_ctx* ctx, Lane& L, int nrhs) {
-    if (nrhs >= MM_MIN_RHS) {
+    if (nrhs >= ctx->mm_min_rhs) {
         hsw_status s = ensure_mm_ws<T>(ctx, L, (nrhs + 15) / 16);
         if (s != HSW_OK) return s;
     }
@@ -1309,7 +1315,7 @@ template <typename T>
 static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx<double>* src,
                          int64_t ld, int plane0, int emode, int couple, Cx<double>* dst, int nrhs,
                          int force_f = -1, int force_b = -1, hipEvent_t* ev = nullptr, int mm_force_f = -1,
-                         int mm_force_b = -1) {
+                         int mm_force_b = -1, bool no_mm = false) {
     hipStream_t st = ln.st;
     const PanelDev& P = ctx->pan_h[gpanel];
     const ProbDev& Q = ctx->prob_h[P.prob];
@@ -1369,7 +1375,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
     // the same arguments with the kept factor block in place of G
     PassArgs<T> AT = A;
     AT.G = (const Cx<T>*)ctx->d_L + f0.loff;
-    if (nrhs >= MM_MIN_RHS && force_f < 0 && !tri_all) {  // matrix-core passes, 16 right-hand sides per group
+    if (nrhs >= ctx->mm_min_rhs && !no_mm && force_f < 0 && !tri_all) {  // matrix-core passes, 16 right-hand sides per group
         const int64_t cls_c2 = ctx->cls_c2_base[P.cls], cls_h2 = ctx->cls_perm_off[P.cls];
         A.xmid = nullptr;  // x_S sits in front of x_U, in xu
         A.xu = (Cx<T>*)ln.d_mxu;
@@ -1473,7 +1479,7 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx);
 template <typename T>
 static hsw_status tune_solve(hsw_ctx* ctx, int nrhs) {
     const int key = rhs_key(nrhs);
-    if (nrhs >= MM_MIN_RHS) return tune_solve_mm<T>(ctx);
+    if (nrhs >= ctx->mm_min_rhs) return tune_solve_mm<T>(ctx);
     // inside a multi-lane solve the shapes are fixed (tuning runs on lane 0 before it)
     if (!ctx->autotune || ctx->tuned[key] || ctx->in_lanes) return HSW_OK;
     constexpr int REPS = 3;
@@ -1800,10 +1806,13 @@ static hsw_status apply_noalloc_impl(hsw_ctx* ctx, int prob, const Cx<double>* r
     ln.nrhs_cap = nrhs;
     const ProbHost& h = ctx->ph[prob];
     HIPCHK(hipMemcpy2DAsync(z, 16 * ld, r, 16 * ld, 16 * h.Npad, nrhs, hipMemcpyDeviceToDevice, ctx->st));
+    // the single-vector passes whatever mm_min_rhs says (the matrix-core
+    // passes' workspaces are not in the scratch)
     for (int i = 0; i < h.m; ++i)
-        panel_tsolve<T>(ctx, ln, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs);
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 0, z, ld, 0, 0, i < h.m - 1, z, nrhs, -1, -1, nullptr, -1, -1,
+                        true);
     for (int i = h.m - 2; i >= 0; --i)
-        panel_tsolve<T>(ctx, ln, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs);
+        panel_tsolve<T>(ctx, ln, h.panel_base + i, 1, z, ld, 0, 1, 0, z, nrhs, -1, -1, nullptr, -1, -1, true);
     HIPCHK(hipGetLastError());
     return HSW_OK;
 }

@@ -38,15 +38,17 @@ constexpr PassShape FWD_SHAPES[N_FWD_SHAPES] = {{64, 256}, {16, 256}, {64, 512},
                                                 {8, 256},  {8, 512},  {32, 512}};
 constexpr PassShape BWD_SHAPES[N_BWD_SHAPES] = {{32, 256}, {8, 256}, {32, 512}, {8, 512}, {16, 256}, {4, 256},
                                                 {64, 256}, {2, 128}, {4, 128}};
-// Groups of at least this many right-hand sides use the matrix-core passes,
-// 16 right-hand sides per group.  Without tuning, the forward pass takes
+// The matrix-core passes take the right-hand sides in groups of MM_MIN_RHS
+// = 16 (the last group padded with zeros); a solve takes them from
+// MM_DEFAULT_FROM right-hand sides on (option mm_min_rhs), below that the
+// single-vector passes.  Without tuning, the forward pass takes
 // items of 64 rows (shape 0) in complex64, or of 16 rows (shape 1) in
 // complex128 and in complex64 launches that would have fewer than
 // MM_NARROW_BELOW workgroups of 64 rows; the backward pass takes 64 columns
 // (shape 6) in launches of at least MM_TILES4_FROM workgroups of 64 columns,
 // else 16 columns (shape 4).  Launches of fewer than MM_WIDE_BELOW
 // workgroups take more waves per workgroup.
-constexpr int MM_MIN_RHS = 16;
+constexpr int MM_MIN_RHS = 16, MM_DEFAULT_FROM = 4;
 constexpr int MM_BWD_SHAPE = 4, MM_BWD_SHAPE64 = 6;
 constexpr int MM_NARROW_BELOW = 256, MM_TILES4_FROM = 512, MM_WIDE_BELOW = 512;
 // The split-contraction forms divide each item's contraction over

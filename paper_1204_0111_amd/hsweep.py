@@ -275,7 +275,7 @@ class Solver:
     def set_option(self, key, value):
         """Option of the context: "graph", "autotune", "update_order", "block_gmres",
         "solve_lanes", "keep_factors", "inverse_by_depth", "full_inverse",
-        "triangular_solves", "bf16_mfma", "mm_fwd_form", "mm_bwd_form" or
+        "triangular_solves", "bf16_mfma", "mm_min_rhs", "mm_fwd_form", "mm_bwd_form" or
         "gmres_device_test" (see hsw_set_option)."""
         self._check(self.lib.hsw_set_option(self.ctx, key.encode(), int(value)))
 

@@ -345,6 +345,28 @@ def test_sweep_matches_oracle(medium, prec, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("mm_from,nrhs", [(1, 1), (4, 3), (4, 4), (16, 5)])
+def test_matrix_core_threshold_takes_either_path(medium, prec, mm_from, nrhs):
+    """Option mm_min_rhs: from that many right-hand sides on the sweep takes
+    the matrix-core passes (a padded group of 16), below it the single-vector
+    passes; both match the oracle's sweep (Alg. 1.5).  Out-of-range values
+    are rejected."""
+    from paper_1204_0111_amd.hsweep import HswError
+    P = medium
+    S = _solver(P, prec)
+    for bad in (0, 17):
+        with pytest.raises(HswError):
+            S.set_option("mm_min_rhs", bad)
+    S.set_option("mm_min_rhs", mm_from)
+    O = sw.Sweep(P["c"], P["h"], P["omega"], P["alpha"], P["gamma"], P["C"], P["d"])
+    r = wl.random_complex((nrhs, O.N_pad), 7)
+    z = S.apply(0, _cuda(r)).cpu().numpy()
+    ref = O.apply(r.T).T
+    for k in range(nrhs):
+        assert rel(z[k], ref[k]) <= TOL[prec], k
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("fwd_form", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("bwd_form", [0, 1, 2, 3, 4, 5, 6])
 def test_sweep_each_matrix_core_form_matches_oracle(medium, prec, fwd_form, bwd_form):

@@ -29,10 +29,13 @@ def test_apply_noalloc_matches_apply_on_two_calls(prec):
     P = case(n=(14, 12, 13), gamma=3, d=3, leaf=4)
     S = Solver(P, precision=prec)
     S.set_option("autotune", 0)  # both entry points on the fixed block shapes
+    # and on the single-vector passes (hsw_apply_noalloc always takes them;
+    # hsw_apply would take the matrix-core passes from 4 right-hand sides)
+    S.set_option("mm_min_rhs", 16)
     S.assemble(P["c"])
     S.setup()
     n = S.N_pad()
-    for nrhs, seed in ((3, 61), (1, 62)):
+    for nrhs, seed in ((5, 60), (3, 61), (1, 62)):
         r = torch.as_tensor(wl.random_complex((nrhs, n), seed)).to("cuda")
         ref = S.apply(0, r).cpu().numpy()
         out = torch.full((nrhs, n), float("nan"), dtype=torch.complex128, device="cuda")
@@ -53,7 +56,7 @@ def test_apply_noalloc_rejects_sizes_past_its_limits():
     n = S.N_pad()
     r = torch.zeros((16, n), dtype=torch.complex128, device="cuda")
     out = torch.zeros_like(r)
-    assert _noalloc(S, r, out) == 1  # HSW_E_INVAL: 16 right-hand sides take the matrix-core passes
+    assert _noalloc(S, r, out) == 1  # HSW_E_INVAL: at most 15 right-hand sides per call
     assert b"at most 15" in S.lib.hsw_last_error(S.ctx)
     S.close()
     # the 100^3 layered workload needs about 19 MB of complex64 workspace per
