@@ -1911,11 +1911,12 @@ static hsw_status gmres_cycle_device(hsw_ctx* ctx, Lane& ln, int prob, Cx<double
             }
             timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st, act, run); });
-            for (int pass = 0; pass < 2; ++pass) {
-                launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
-                            pass, st);
-                launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
-            }
+            // classical Gram-Schmidt twice: products, update fused with the second
+            // products, update
+            launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef, 0, st);
+            launch_axpy_dots(V, vs, Vn, ld, N, j + 1, coef, hld, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
+                             st);
+            launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
             launch_norm(Vn, ld, N, nrhs, act, partn, nrm, H + (int64_t)j * (k + 1) + j + 1, hld, st);
             launch_scale(Vn, Vn, ld, N, nrhs, nrm, act, st);
             launch_givens(j, k, nrhs, H, cs, sn, g, bn, est, act, st);
@@ -2087,11 +2088,12 @@ static hsw_status gmres_impl(hsw_ctx* ctx, Lane& ln, int prob, const Cx<double>*
             if (s != HSW_OK) { cleanup(); return s; }
             timed(ctx, "matvec", 1, (double)N * (32.0 * nrhs + 8.0), 56.0 * (double)N * nrhs,
                   [&] { launch_matvec(Q, ctx->d_et, Zj, Vn, nullptr, ld, nrhs, 0, st); });
-            for (int pass = 0; pass < 2; ++pass) {
-                launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
-                            pass, st);
-                launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
-            }
+            // classical Gram-Schmidt twice: products, update fused with the second
+            // products, update
+            launch_dots(V, vs, Vn, ld, N, j + 1, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef, 0, st);
+            launch_axpy_dots(V, vs, Vn, ld, N, j + 1, coef, hld, nrhs, act, part, H + (int64_t)j * (k + 1), hld, coef,
+                             st);
+            launch_axpy_multi(V, vs, Vn, ld, N, j + 1, coef, hld, nullptr, act, 0, nrhs, st);
             launch_norm(Vn, ld, N, nrhs, act, partn, nrm, H + (int64_t)j * (k + 1) + j + 1, hld, st);
             launch_scale(Vn, Vn, ld, N, nrhs, nrm, act, st);
             launch_givens(j, k, nrhs, H, cs, sn, g, bn, est, act, st);

@@ -106,6 +106,12 @@ void launch_dots(const Cx<double>* V, int64_t vstride, const Cx<double>* w, int6
 void launch_axpy_multi(const Cx<double>* V, int64_t vstride, Cx<double>* w, int64_t ld, int64_t N,
                        int nvec, const Cx<double>* coef, int cld, const int* nvec_rhs,
                        const int* active, int mode, int nrhs, hipStream_t st);
+// w -= V coef (coef as written by launch_dots), then h += V^H w with the new
+// w (and hout := those products): launch_axpy_multi and launch_dots (mode 1)
+// in one pass over the basis
+void launch_axpy_dots(const Cx<double>* V, int64_t vstride, Cx<double>* w, int64_t ld, int64_t N, int nvec,
+                      const Cx<double>* coef, int cld, int nrhs, const int* active, Cx<double>* partial,
+                      Cx<double>* h, int hld, Cx<double>* hout, hipStream_t st);
 void launch_norm(const Cx<double>* w, int64_t ld, int64_t N, int nrhs, const int* active,
                  double* partial, double* norm, Cx<double>* hptr, int hld, hipStream_t st);
 void launch_scale(const Cx<double>* w, Cx<double>* v, int64_t ld, int64_t N, int nrhs,

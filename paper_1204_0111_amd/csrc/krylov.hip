@@ -165,6 +165,55 @@ __global__ __launch_bounds__(256) void k_axpy_multi(const C64* __restrict__ V, i
     *wp = mode == 0 ? *wp - acc : *wp + acc;
 }
 
+// The first Gram-Schmidt pass's update fused with the second pass's
+// products, for a basis of NV vectors: per entry, the basis values are
+// loaded once into registers, w -= sum_i coef[r * cld + i] V_i (the sum in
+// the order of k_axpy_multi) is stored, and conj(V_i) w is added to the
+// thread's product sums (entry by entry, as in k_dots_partial); then
+// partial[(r * nchunk + chunk) * NV + i] = the workgroup's sums.  The
+// results equal those of k_axpy_multi followed by k_dots_partial, with one
+// read of the basis instead of two.
+constexpr int AXPY_DOTS_MAXV = 16;
+template <int NV>
+__global__ __launch_bounds__(256) void k_axpy_dots(const C64* __restrict__ V, int64_t vstride,
+                                                   C64* __restrict__ w, int64_t ld, int64_t N,
+                                                   const C64* __restrict__ coef, int cld,
+                                                   const int* __restrict__ active,
+                                                   C64* __restrict__ partial) {
+    __shared__ C64 sh[4];
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int nchunk = gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * 256 * DOT_PER_THREAD;
+    C64* wr = w + r * ld;
+    const C64* vr = V + r * ld;
+    C64 cf[NV], acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        cf[i] = coef[r * cld + i];
+        acc[i] = cx<double>(0, 0);
+    }
+    for (int t = 0; t < DOT_PER_THREAD; ++t) {
+        const int64_t p = base + (int64_t)t * 256 + threadIdx.x;
+        if (p >= N) break;
+        C64 v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = vr[i * vstride + p];
+        C64 u = cx<double>(0, 0);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cfma(u, cf[i], v[i]);
+        const C64 wn = wr[p] - u;
+        wr[p] = wn;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = acc[i] + cjmul(v[i], wn);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const C64 t = block_sum(acc[i], sh);
+        if (threadIdx.x == 0) partial[((int64_t)r * nchunk + blockIdx.x) * NV + i] = t;
+    }
+}
+
 // partial[r * nchunk + chunk] = sum |w|^2 over the chunk.
 __global__ __launch_bounds__(256) void k_norm_partial(const C64* __restrict__ w, int64_t ld, int64_t N,
                                                       const int* __restrict__ active,
@@ -324,6 +373,28 @@ void launch_dots(const C64* V, int64_t vstride, const C64* w, int64_t ld, int64_
                        active, partial);
     hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(256), 0, st, partial, nch, nvec, active, h, hld,
                        hout, mode);
+}
+void launch_axpy_dots(const C64* V, int64_t vstride, C64* w, int64_t ld, int64_t N, int nvec, const C64* coef,
+                      int cld, int nrhs, const int* active, C64* partial, C64* h, int hld, C64* hout,
+                      hipStream_t st) {
+    if (nvec > AXPY_DOTS_MAXV) {  // longer bases: the two passes
+        launch_axpy_multi(V, vstride, w, ld, N, nvec, coef, cld, nullptr, active, 0, nrhs, st);
+        launch_dots(V, vstride, w, ld, N, nvec, nrhs, active, partial, h, hld, hout, 1, st);
+        return;
+    }
+    const int nch = dots_chunks(N);
+    const dim3 grid(nch, nrhs);
+    switch (nvec) {
+#define HSW_AXPY_DOTS(NV) \
+    case NV: hipLaunchKernelGGL(k_axpy_dots<NV>, grid, dim3(256), 0, st, V, vstride, w, ld, N, coef, cld, active, partial); break;
+        HSW_AXPY_DOTS(1) HSW_AXPY_DOTS(2) HSW_AXPY_DOTS(3) HSW_AXPY_DOTS(4) HSW_AXPY_DOTS(5) HSW_AXPY_DOTS(6)
+        HSW_AXPY_DOTS(7) HSW_AXPY_DOTS(8) HSW_AXPY_DOTS(9) HSW_AXPY_DOTS(10) HSW_AXPY_DOTS(11)
+        HSW_AXPY_DOTS(12) HSW_AXPY_DOTS(13) HSW_AXPY_DOTS(14) HSW_AXPY_DOTS(15) HSW_AXPY_DOTS(16)
+#undef HSW_AXPY_DOTS
+    default: return;  // nvec <= 0 has no products
+    }
+    hipLaunchKernelGGL(k_dots_final, dim3(nrhs), dim3(256), 0, st, partial, nch, nvec, active, h, hld,
+                       hout, 1);
 }
 void launch_axpy_multi(const C64* V, int64_t vstride, C64* w, int64_t ld, int64_t N, int nvec,
                        const C64* coef, int cld, const int* nvec_rhs, const int* active, int mode,
