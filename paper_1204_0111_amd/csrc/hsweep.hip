@@ -1079,10 +1079,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         if (value < 1 || value > MM_MIN_RHS) return fail(ctx, HSW_E_INVAL, "mm_min_rhs is 1..16");
         ctx->mm_min_rhs = (int)value;
     } else if (k == "mm_fwd_form") {
-        if (value < -1 || value > 5) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..5");
+        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..6");
         ctx->mm_fwd_form = (int)value;
     } else if (k == "mm_bwd_form") {
-        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..6");
+        if (value < -1 || value > 7) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..7");
         ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
@@ -1274,13 +1274,17 @@ static hsw_status ensure_mm_ws(hsw_ctx* ctx, Lane& L, int groups) {
     const size_t e = sizeof(Cx<T>) * 16 * (size_t)groups;
     const size_t bc2 = e * (size_t)std::max<int64_t>(ctx->total_c2, 1);
     const size_t bh2 = e * (size_t)std::max<int64_t>(ctx->total_naux, 1);
-    // partial blocks: the largest (items x splits) of any depth's 64-row or
-    // 64-column launch, 1024 entries per item, group and split
+    // partial blocks, in units of 1024 entries: the largest (items x splits)
+    // of any depth's launch, 1024 entries per item, group and split for the
+    // 64-row or 64-column items, 256 for the 16-row or 16-column ones
     int64_t parts = 1;
     for (const auto& lv : ctx->slevels)
-        for (const SolveLevel& sl : lv)
+        for (const SolveLevel& sl : lv) {
             for (int cnt : {sl.fcount[0], sl.bcount[MM_BWD_SHAPE64]})
                 parts = std::max<int64_t>(parts, (int64_t)cnt * groups * mm_split(cnt, groups));
+            for (int cnt : {sl.fcount[1], sl.bcount[MM_BWD_SHAPE]})
+                parts = std::max<int64_t>(parts, ((int64_t)cnt * groups * mm_split(cnt, groups) + 3) / 4);
+        }
     HIPCHK(hipMalloc(&L.d_mxu, e * (size_t)std::max<int64_t>(ctx->max_wsize, 1)));
     HIPCHK(hipMalloc(&L.d_mc2, bc2));
     HIPCHK(hipMalloc(&L.d_mh2, bh2));
@@ -1408,7 +1412,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 form = rt4 ? 0 : 1;
                 if (lv[d].fcount[rt4 ? 0 : 1] * groups < MM_WIDE_BELOW) form += 3;
             }
-            const int fs = (form == 1 || form == 4) ? 1 : 0;  // items of 16 rows
+            const int fs = (form == 1 || form == 4 || form == 6) ? 1 : 0;  // items of 16 rows
             A.items = ctx->d_sitems + lv[d].foff[fs];
             A.nsplit = mm_split(lv[d].fcount[fs], groups);
             run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec[pf],
@@ -1591,7 +1595,7 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        constexpr int NF = 6, NB = 7;  // forward and backward forms
+        constexpr int NF = 7, NB = 8;  // forward and backward forms
         constexpr int NK = NF > NB ? NF : NB;
         std::vector<std::array<float, NF>> tf(D + 1);
         std::vector<std::array<float, NB>> tb(D + 1);

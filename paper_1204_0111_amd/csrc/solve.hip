@@ -615,7 +615,7 @@ template <typename T, int RT, int NW, int SK = 0>
 __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    static_assert(SK == 0 || (RT == 4 && NW == 4), "split contraction: 64-row items, 4 waves");
+    static_assert(SK == 0 || NW == 4, "split contraction: 4 waves (one thread per partial entry)");
     const int S = SK != 0 ? A.nsplit : 1;
     const int ib = SK != 0 ? (int)blockIdx.x / S : (int)blockIdx.x;
     const int z = SK != 0 ? (int)blockIdx.x - ib * S : 0;
@@ -762,40 +762,40 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     }
 }
 
-// y[t] := sum over the S partial blocks at pp (1024 entries apart) of entry
+// y[t] := sum over the S partial blocks at pp (256 R entries apart) of entry
 // tid + 256 t, added in split order; the loads of eight splits are issued
 // before their sums.
-template <typename T>
-__device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[4]) {
+template <typename T, int R>
+__device__ inline void split_sums(const Cx<T>* pp, int S, int tid, Cx<T> (&y)[R]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) y[t] = cx<T>(0, 0);
+    for (int t = 0; t < R; ++t) y[t] = cx<T>(0, 0);
     for (int z0 = 0; z0 < S; z0 += 8) {
-        Cx<T> v[8][4];
+        Cx<T> v[8][R];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)  // unconditional loads (clamped split, dropped below)
-                v[u][t] = pp[(int64_t)min(z0 + u, S - 1) * 1024 + tid + 256 * t];
+            for (int t = 0; t < R; ++t)  // unconditional loads (clamped split, dropped below)
+                v[u][t] = pp[(int64_t)min(z0 + u, S - 1) * (256 * R) + tid + 256 * t];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < R; ++t)
                 if (z0 + u < S) y[t] = y[t] + v[u][t];
     }
 }
 
-// Sums the nsplit partial blocks of each 64-row item (in split order, so the
-// result does not depend on timing) and applies the forward epilogue.
-template <typename T>
+// Sums the nsplit partial blocks of each item of 16 RT rows (in split order,
+// so the result does not depend on timing) and applies the forward epilogue.
+template <typename T, int RT>
 __global__ __launch_bounds__(256) void k_fwd_fin(PassArgs<T> A) {
     if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
     const int grp = blockIdx.y, tid = threadIdx.x, r = tid & 15, S = A.nsplit;
     if ((int64_t)grp * 16 + r >= A.nrhs) return;
-    Cx<T> y[4];
-    split_sums(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * 1024, S, tid, y);
+    Cx<T> y[RT];
+    split_sums<T, RT>(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * (256 * RT), S, tid, y);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) fwd_store(A, it, grp, it.blk + ((tid + 256 * t) >> 4), r, y[t]);
+    for (int t = 0; t < RT; ++t) fwd_store(A, it, grp, it.blk + ((tid + 256 * t) >> 4), r, y[t]);
 }
 
 // Row-split form of the forward matrix-core pass for fronts whose v_S fits
@@ -1011,7 +1011,7 @@ template <typename T, int CT, int NW, int SK = 0, int IFB = 2>
 __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     typedef typename MfmaAcc<T>::type V4;
     constexpr int KC = 16;
-    static_assert(SK == 0 || (CT == 4 && NW == 4), "split contraction: 64-column items, 4 waves");
+    static_assert(SK == 0 || NW == 4, "split contraction: 4 waves (one thread per partial entry)");
     static_assert(IFB == 2 || (IFB == 4 && CT == 1), "four chunks in flight: one column tile");
     const int S = SK != 0 ? A.nsplit : 1;
     const int ib = SK != 0 ? (int)blockIdx.x / S : (int)blockIdx.x;
@@ -1127,7 +1127,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     };
     // with one column tile each wave issues two chunks' loads before their
     // products (loads past the end read zeros), as in k_fwd_mm
-    if constexpr (CT == 1 && IFB == 4) {
+    if constexpr (SK == 0 && CT == 1 && IFB == 4) {
         T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4], gre3[CT][4], gim3[CT][4], sre3[4], sim3[4];
         T gre4[CT][4], gim4[CT][4], sre4[4], sim4[4];
         for (int ch = wave; ch < nch; ch += 4 * NW) {
@@ -1141,7 +1141,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
             products(gre3, gim3, sre3, sim3);
             products(gre4, gim4, sre4, sim4);
         }
-    } else if constexpr (CT == 1) {
+    } else if constexpr (SK == 0 && CT == 1) {
         T gre2[CT][4], gim2[CT][4], sre2[4], sim2[4];
         for (int ch = wave; ch < nch; ch += 2 * NW) {
             load(ch, gre, gim, sre, sim);
@@ -1210,20 +1210,20 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     }
 }
 
-// Sums the nsplit partial blocks of each 64-column item (in split order) and
-// applies the backward epilogue.
-template <typename T>
+// Sums the nsplit partial blocks of each item of 16 CT columns (in split
+// order) and applies the backward epilogue.
+template <typename T, int CT>
 __global__ __launch_bounds__(256) void k_bwd_fin(PassArgs<T> A) {
     if (A.run && !*A.run) return;
     const SolveItem it = A.items[blockIdx.x];
-    if (leaf_aux_block(it, A.ga, it.blk, 64)) return;
+    if (leaf_aux_block(it, A.ga, it.blk, 16 * CT)) return;
     const int grp = blockIdx.y, tid = threadIdx.x, S = A.nsplit;
     const int64_t rhs0 = (int64_t)grp * 16;
-    __shared__ T Yre[64][17], Yim[64][17];
-    Cx<T> y[4];
-    split_sums(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * 1024, S, tid, y);
+    __shared__ T Yre[16 * CT][17], Yim[16 * CT][17];
+    Cx<T> y[CT];
+    split_sums<T, CT>(A.part + (int64_t)(blockIdx.x * gridDim.y + grp) * S * (256 * CT), S, tid, y);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < CT; ++t) {
         const int e = tid + 256 * t;
         Yre[e >> 4][e & 15] = y[t].re;
         Yim[e >> 4][e & 15] = y[t].im;
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(256) void k_bwd_fin(PassArgs<T> A) {
     __syncthreads();
     const int s = it.s, c0 = it.blk;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < CT; ++t) {
         {
             const int jl = 16 * t + (tid >> 4), r = tid & 15, j = c0 + jl;
             if (j < s && rhs0 + r < A.nrhs) bwd_push(A, it, grp, j, r, cx<T>(Yre[jl][r], Yim[jl][r]));
@@ -1601,10 +1601,16 @@ void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStrea
     case 2: HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A); break;
     case 3: HSW_LAUNCH((k_fwd_mm<T, 4, 8>), grid, dim3(512), 0, st, A); break;
     case 4: HSW_LAUNCH((k_fwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
+    case 6: {
+        const dim3 gs(nwork * A.nsplit, grid.y);
+        HSW_LAUNCH((k_fwd_mm<T, 1, 4, 1>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_fwd_fin<T, 1>), grid, dim3(256), 0, st, A);
+        break;
+    }
     default: {
         const dim3 gs(nwork * A.nsplit, grid.y);
         HSW_LAUNCH((k_fwd_mm<T, 4, 4, 1>), gs, dim3(256), 0, st, A);
-        HSW_LAUNCH(k_fwd_fin<T>, grid, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_fwd_fin<T, 4>), grid, dim3(256), 0, st, A);
     }
     }
 }
@@ -1626,7 +1632,13 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
     case 4: {
         const dim3 gs(nwork * A.nsplit, grid.y);
         HSW_LAUNCH((k_bwd_mm<T, 4, 4, 1>), gs, dim3(256), 0, st, A);
-        HSW_LAUNCH(k_bwd_fin<T>, grid, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_bwd_fin<T, 4>), grid, dim3(256), 0, st, A);
+        break;
+    }
+    case 7: {
+        const dim3 gs(nwork * A.nsplit, grid.y);
+        HSW_LAUNCH((k_bwd_mm<T, 1, 4, 1>), gs, dim3(256), 0, st, A);
+        HSW_LAUNCH((k_bwd_fin<T, 1>), grid, dim3(256), 0, st, A);
         break;
     }
     case 5: HSW_LAUNCH((k_bwd_mm<T, 1, 4, 0, 4>), grid, dim3(256), 0, st, A); break;
