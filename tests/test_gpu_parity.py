@@ -7,6 +7,8 @@ oracle's operator.  The plan (elimination order, update sets) must equal the
 oracle's independently written nested dissection exactly.
 """
 
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -403,14 +405,18 @@ def test_gmres_matches_oracle(medium, prec):
     b = b.reshape(2, -1)
     xs, info = S.solve([_cuda(b)], rtol=1e-5, restart=20)
     x = xs[0].cpu().numpy()
+    if prec == "c64":
+        # the FP64 path of the same driver: complex64 may take at most 1.2x its iterations
+        _, info64 = _solver(P, "c128").solve([_cuda(b)], rtol=1e-5, restart=20)
     for r in range(2):
         _, it_o, rr_o, _ = gm.gmres(lambda v: A @ v, O.apply, b[r], k=20, tol=1e-5)
         true = np.linalg.norm(b[r] - A @ x[r]) / np.linalg.norm(b[r])
         assert true < 1e-5 and abs(true - info["relres"][r]) <= 1e-3 * true + 1e-12
         if prec == "c128":
+            # the device orthogonalises by CGS2, the oracle by MGS: one step apart at most
             assert abs(info["iters"][r] - it_o) <= 1, (info["iters"][r], it_o)
         else:
-            assert info["iters"][r] <= 1.2 * it_o + 1, (info["iters"][r], it_o)
+            assert info["iters"][r] <= math.floor(1.2 * info64["iters"][r] + 1e-9), (info["iters"][r], info64["iters"])
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
