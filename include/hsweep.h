@@ -283,16 +283,16 @@ hsw_status hsw_kernel_timing(hsw_ctx* ctx, const char* kernel, int32_t enable, i
  *   "mm_fwd_form", "mm_bwd_form" the form of the matrix-core passes (see
  *              mm_min_rhs) at every tree depth; -1 (default): the
  *              autotuner's choice per panel class and depth.  Forward
- *              (-1..6): 0 / 3 workgroups of 64 rows whose 4 / 8 waves split
- *              the contraction, 1 / 4 workgroups of 16 rows with 4 / 8
- *              waves, 2 row-split workgroups of 64 rows
+ *              (-1..7): 0 / 3 workgroups of 64 rows whose 4 / 8 waves split
+ *              the contraction, 1 / 4 / 7 workgroups of 16 rows with 4 / 8 /
+ *              2 waves, 2 row-split workgroups of 64 rows
  *              with the front vector staged in LDS (depths whose largest
  *              front needs more than 64 KB of it take form 0), 5 workgroups
  *              of 64 rows with the contraction split over several workgroups
  *              and a second launch summing the parts, 6 the same for items
- *              of 16 rows.  Backward (-1..7): 0
- *              workgroups of 64 columns, 1 / 2 / 3 of 16 columns with 4 / 8 /
- *              16 waves (complex128: 8), 4 as forward 5 for columns, 5 / 6
+ *              of 16 rows.  Backward (-1..8): 0
+ *              workgroups of 64 columns, 1 / 2 / 3 / 8 of 16 columns with 4 /
+ *              8 / 16 (complex128: 8) / 2 waves, 4 as forward 5 for columns, 5 / 6
  *              as 1 / 2 with four chunks in flight per wave, 7 as 4 for
  *              items of 16 columns.  Out of range:
  *              HSW_E_INVAL.

@@ -1079,10 +1079,10 @@ extern "C" hsw_status hsw_set_option(hsw_ctx* ctx, const char* key, int64_t valu
         if (value < 1 || value > MM_MIN_RHS) return fail(ctx, HSW_E_INVAL, "mm_min_rhs is 1..16");
         ctx->mm_min_rhs = (int)value;
     } else if (k == "mm_fwd_form") {
-        if (value < -1 || value > 6) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..6");
+        if (value < -1 || value > 7) return fail(ctx, HSW_E_INVAL, "mm_fwd_form is -1..7");
         ctx->mm_fwd_form = (int)value;
     } else if (k == "mm_bwd_form") {
-        if (value < -1 || value > 7) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..7");
+        if (value < -1 || value > 8) return fail(ctx, HSW_E_INVAL, "mm_bwd_form is -1..8");
         ctx->mm_bwd_form = (int)value;
     } else if (k == "update_order") {
         if (value < -1 || value > 2) return fail(ctx, HSW_E_INVAL, "update_order is -1, 0, 1 or 2");
@@ -1412,7 +1412,7 @@ static void panel_tsolve(hsw_ctx* ctx, Lane& ln, int gpanel, int gmode, const Cx
                 form = rt4 ? 0 : 1;
                 if (lv[d].fcount[rt4 ? 0 : 1] * groups < MM_WIDE_BELOW) form += 3;
             }
-            const int fs = (form == 1 || form == 4 || form == 6) ? 1 : 0;  // items of 16 rows
+            const int fs = (form == 1 || form == 4 || form >= 6) ? 1 : 0;  // items of 16 rows
             A.items = ctx->d_sitems + lv[d].foff[fs];
             A.nsplit = mm_split(lv[d].fcount[fs], groups);
             run("fwd", lv[d].fcount[fs], es * lv[d].g_need(pf) * groups + nrhs * lv[d].fwd_vec[pf],
@@ -1595,7 +1595,7 @@ static hsw_status tune_solve_mm(hsw_ctx* ctx) {
         for (size_t g = 0; g < ctx->pan_h.size(); ++g)
             if (ctx->pan_h[g].cls == (int)ci) panels.push_back((int)g);
         const int D = c.maxdepth;
-        constexpr int NF = 7, NB = 8;  // forward and backward forms
+        constexpr int NF = 8, NB = 9;  // forward and backward forms
         constexpr int NK = NF > NB ? NF : NB;
         std::vector<std::array<float, NF>> tf(D + 1);
         std::vector<std::array<float, NB>> tb(D + 1);

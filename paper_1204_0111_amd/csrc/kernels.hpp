@@ -66,8 +66,8 @@ void launch_bwd(const PassArgs<T>& A, int nwork, int cb, int nmax, hipStream_t s
 // the contraction), 1 / 4 (items of 16 rows, 4 / 8 waves), 2 (row-split, items
 // of 64 rows, fwd_rs_lds_bytes(smax) bytes of LDS per workgroup), 5 (items of
 // 64 rows, contraction split over A.nsplit workgroups; A.part holds
-// nwork x groups x nsplit x 1024 partial entries) or 6 (as 5 for items of 16
-// rows, 256 partial entries each)
+// nwork x groups x nsplit x 1024 partial entries), 6 (as 5 for items of 16
+// rows, 256 partial entries each) or 7 (items of 16 rows, 2 waves)
 template <typename T>
 void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStream_t st);
 template <typename T>
@@ -78,8 +78,8 @@ void launch_rhs_scatter(const PassArgs<T>& A, hipStream_t st);
 // backward matrix-core pass: form 0 (items of 64 columns, 4 waves), 1 / 2 / 3
 // (items of 16 columns, 4 / 8 / 16 waves; complex128: 8), 4 (items of 64
 // columns, contraction split over A.nsplit workgroups, as forward form 5) or
-// 5 / 6 (as 1 / 2, four chunks in flight per wave) or 7 (as 4 for items of
-// 16 columns)
+// 5 / 6 (as 1 / 2, four chunks in flight per wave), 7 (as 4 for items of 16
+// columns) or 8 (items of 16 columns, 2 waves)
 template <typename T>
 void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st);
 template <typename T>

@@ -653,7 +653,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
     const int erow = it.blk + (tid >> 4), er = tid & 15;
     Cx<T> e_d = cx<T>(0, 0), e_a = cx<T>(0, 0), e_b = cx<T>(0, 0);
     int e_pm = 0, e_hm = -1;
-    if constexpr (RT == 1) {
+    if constexpr (RT == 1 && NW >= 4) {
         const BufRsrc rd = buf_rsrc(A.dinv + it.start, (uint32_t)s * ES);
         const BufRsrc rp = buf_rsrc(A.pmap + it.pmap, (uint32_t)(n - s) * 4);
         const BufRsrc rm = buf_rsrc(A.hmap + it.pmap, (uint32_t)(n - s) * 4);
@@ -736,6 +736,15 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mm(PassArgs<T> A) {
         for (int t = 0; t < RT; ++t) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
+        }
+        return;
+    }
+    if constexpr (NW < 4) {
+        // fewer than 256 threads: each takes several (row, right-hand side) outputs
+        for (int idx = tid; idx < 256 * RT; idx += 64 * NW) {
+            const int rr = idx & 15;
+            if (rhs0 + rr < A.nrhs)
+                fwd_store(A, it, grp, it.blk + (idx >> 4), rr, cx<T>(Yre[idx >> 4][rr], Yim[idx >> 4][rr]));
         }
         return;
     }
@@ -1041,7 +1050,7 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
     Cx<double> e_old = cx<double>(0, 0);
     Cx<double>* e_up = nullptr;
     int e_q = -1, e_lat = 0;
-    if constexpr (CT == 1) {
+    if constexpr (CT == 1 && NW >= 4) {
         const BufRsrc rm = buf_rsrc(A.cmap + it.moff, (uint32_t)(2 * n) * 4);
         const int jc = c0 + (tid >> 4) % 16;
         e_o0 = buf_load_i32(rm, (uint32_t)jc * 4);
@@ -1171,6 +1180,18 @@ __global__ __launch_bounds__(64 * NW) void k_bwd_mm(PassArgs<T> A) {
         for (int t = 0; t < CT; ++t) {
             const int e = tid + 256 * t;
             pp[e] = cx<T>(Yre[e >> 4][e & 15], Yim[e >> 4][e & 15]);
+        }
+        return;
+    }
+    if constexpr (NW < 4) {
+        // fewer than 256 threads: each takes several (column, right-hand side) outputs
+        for (int idx = tid; idx < 256 * CT; idx += 64 * NW) {
+            const int jl = idx >> 4, rr = idx & 15, j = c0 + jl;
+            if (j < s && rhs0 + rr < A.nrhs) {
+                const Cx<T> x = cx<T>(Yre[jl][rr], Yim[jl][rr]);
+                bwd_push(A, it, grp, j, rr, x);
+                bwd_grid(A, it, j, rhs0 + rr, x);
+            }
         }
         return;
     }
@@ -1601,6 +1622,7 @@ void launch_fwd_mm(const PassArgs<T>& A, int nwork, int form, int smax, hipStrea
     case 2: HSW_LAUNCH((k_fwd_rs<T, FP>), grid, dim3(256), fwd_rs_lds_bytes<T>(smax), st, A); break;
     case 3: HSW_LAUNCH((k_fwd_mm<T, 4, 8>), grid, dim3(512), 0, st, A); break;
     case 4: HSW_LAUNCH((k_fwd_mm<T, 1, 8>), grid, dim3(512), 0, st, A); break;
+    case 7: HSW_LAUNCH((k_fwd_mm<T, 1, 2>), grid, dim3(128), 0, st, A); break;
     case 6: {
         const dim3 gs(nwork * A.nsplit, grid.y);
         HSW_LAUNCH((k_fwd_mm<T, 1, 4, 1>), gs, dim3(256), 0, st, A);
@@ -1635,6 +1657,7 @@ void launch_bwd_mm(const PassArgs<T>& A, int nwork, int form, hipStream_t st) {
         HSW_LAUNCH((k_bwd_fin<T, 4>), grid, dim3(256), 0, st, A);
         break;
     }
+    case 8: HSW_LAUNCH((k_bwd_mm<T, 1, 2>), grid, dim3(128), 0, st, A); break;
     case 7: {
         const dim3 gs(nwork * A.nsplit, grid.y);
         HSW_LAUNCH((k_bwd_mm<T, 1, 4, 1>), gs, dim3(256), 0, st, A);

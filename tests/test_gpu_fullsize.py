@@ -118,15 +118,15 @@ def test_middle_panel_many_rhs_matrix_core_passes_match_oracle(name, nrhs, prec)
 
 @pytest.mark.parametrize("name", ["grf50", "layered100"])
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-@pytest.mark.parametrize("forms", [(2, -1), (5, 4), (1, 6), (6, 7)],
-                         ids=["row-split", "split", "bwd-4-in-flight", "split-16"])
+@pytest.mark.parametrize("forms", [(2, -1), (5, 4), (1, 6), (6, 7), (7, 8)],
+                         ids=["row-split", "split", "bwd-4-in-flight", "split-16", "two-waves"])
 def test_middle_panel_forced_matrix_core_forms_match_oracle(name, prec, forms):
     """Forms of the matrix-core passes forced at every depth, 17 right-hand
     sides, against the oracle's sparse LU per right-hand side: the row-split
     forward form (where it fits; other depths keep 64-row workgroups), both
     passes' split-contraction forms (shares summed by a finishing launch),
-    the backward form with four chunks in flight per wave, and the split
-    forms for items of 16 rows or columns."""
+    the backward form with four chunks in flight per wave, the split forms
+    for items of 16 rows or columns, and the two-wave forms."""
     P, v, ref = _panel_reference(name, 5)
     S = _solver(P, prec)
     S.set_option("mm_fwd_form", forms[0])

@@ -369,8 +369,8 @@ def test_matrix_core_threshold_takes_either_path(medium, prec, mm_from, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("fwd_form", [0, 1, 2, 3, 4, 5, 6])
-@pytest.mark.parametrize("bwd_form", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("fwd_form", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("bwd_form", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_sweep_each_matrix_core_form_matches_oracle(medium, prec, fwd_form, bwd_form):
     """Every form of the 16-right-hand-side passes, forced at every depth
     (the autotuner picks among them per depth): the sweep of Alg. 1.5 for 17
