@@ -317,6 +317,64 @@ __device__ inline void cgemm64_pipe(typename MfmaAcc<T>::type (&are)[2][2],
     }
 }
 
+// acc += R C^T over k < K for a 64 x 64 tile whose R operand is already in
+// LDS as planar [k][row] tiles (Rre, Rim, at least K rows); only C, read by
+// ldC(k, col) with consecutive threads on consecutive cols, is staged (as in
+// cgemm64_pipe: chunks of KC, the next chunk's loads in flight during this
+// one's products), and each complex product is three real ones
+// (tile_cgemm3).  Ends with a barrier (except for K <= 0).
+template <typename T, int KC, typename LC>
+__device__ inline void cgemm64_rlds(typename MfmaAcc<T>::type (&are)[2][2],
+                                    typename MfmaAcc<T>::type (&aim)[2][2], int K, const T (*Rre)[LDP],
+                                    const T (*Rim)[LDP], LC ldC, T (*Cre)[KC][LDP], T (*Cim)[KC][LDP]) {
+    constexpr int PER = KC * 64 / 256;
+    const int tid = threadIdx.x;
+    const int nch = (K + KC - 1) / KC;
+    if (nch <= 0) return;
+    const int wq = __builtin_amdgcn_readfirstlane(tid >> 6);
+    Cx<T> c[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int m = wq + 4 * q;
+            c[q] = k0 + m < K ? ldC(k0 + m, tid & 63) : cx<T>(0, 0);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            Cre[buf][wq + 4 * q][tid & 63] = c[q].re;
+            Cim[buf][wq + 4 * q][tid & 63] = c[q].im;
+        }
+    };
+    typename MfmaAcc<T>::type k1[2][2], k2[2][2], k3[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            k1[bi][bj] = typename MfmaAcc<T>::type{0, 0, 0, 0};
+            k2[bi][bj] = aim[bi][bj];
+            k3[bi][bj] = -are[bi][bj];
+        }
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) fetch((ch + 1) * KC);
+        tile_cgemm3<T, KC>(k1, k2, k3, Rre + ch * KC, Rim + ch * KC, Cre[buf], Cim[buf], K - ch * KC);
+        if (ch + 1 < nch) put(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            are[bi][bj] = k1[bi][bj] - k3[bi][bj];
+            aim[bi][bj] = k1[bi][bj] + k2[bi][bj];
+        }
+}
+
 // ---------------------------------------------------------------------------
 // The same 64 x 64 tile product with complex BF16 inputs on the BF16 matrix
 // cores (16 x 16 x 16 products, FP32 accumulation): the operands are rounded
@@ -992,8 +1050,10 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && !BF) ? 4 : 1) void k_update
 // diagonal-block inverse the factorisation stored above the diagonal.  A
 // block's columns depend only on later columns, so stopping the sweep at
 // the front's first formed column g0 leaves the formed columns unchanged.
+// Complex64 is held to 168 registers: with its 51 KB of LDS, three
+// workgroups share a compute unit.
 template <typename T>
-__global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void k_inverse(const int2* __restrict__ work,
                                                  const FrontInst* __restrict__ inst, const Cx<T>* Lb,
                                                  Cx<T>* Gb, Cx<T>* Tb) {
     constexpr int KC = 16;
@@ -1016,8 +1076,16 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
     const int tid = threadIdx.x;
     const int l = tid & 63, wv = tid >> 6;
     const int li = l & 15, lk = l >> 4;
-    __shared__ T Rre[2][KC][LDP], Rim[2][KC][LDP], Cre[2][KC][LDP], Cim[2][KC][LDP];
-    __shared__ T Are[64][LDP], Aim[64][LDP];  // the block accumulator [col][row]
+    __shared__ T Cre[2][KC][LDP], Cim[2][KC][LDP];
+    // the block accumulator [col][row] (Are, Aim), which the second product
+    // takes as its R operand in place; the first product stages its R chunks
+    // in the same memory (it ends before the accumulator is written)
+    __shared__ T ubuf[2 * 64 * LDP];
+    T(*Are)[LDP] = reinterpret_cast<T(*)[LDP]>(ubuf);
+    T(*Aim)[LDP] = reinterpret_cast<T(*)[LDP]>(ubuf + 64 * LDP);
+    T(*Rre)[KC][LDP] = reinterpret_cast<T(*)[KC][LDP]>(ubuf);
+    T(*Rim)[KC][LDP] = reinterpret_cast<T(*)[KC][LDP]>(ubuf + 2 * KC * LDP);
+    static_assert(4 * KC <= 2 * 64, "the first product's R buffers fit in the accumulator's memory");
     const int ncb = (s + 63) / 64;
     for (int cbk = ncb - 1; cbk >= f.g0 / 64; --cbk) {
         const int c0 = cbk * 64, c1 = min(c0 + 64, s), bw = c1 - c0;
@@ -1069,15 +1137,15 @@ __global__ __launch_bounds__(256) void k_inverse(const int2* __restrict__ work,
                 }
         __syncthreads();
         // X_blk = acc L_blk^{-1}: X(r, j) = sum_{m >= j} acc(r, m) Linv(m, j)
-        cgemm64_pipe<T, KC, false, true>(
-            are, aim, bw, [&](int m, int a) { return cx<T>(Are[m][a], Aim[m][a]); },
+        cgemm64_rlds<T, KC>(
+            are, aim, bw, Are, Aim,
             [&](int m, int a) {
                 // Linv(m, a) for m > a is stored at L(c0 + a, c0 + m) (upper triangle)
                 if (a >= bw || m < a) return cx<T>(0, 0);
                 if (m == a) return cx<T>(1, 0);
                 return L[(int64_t)(c0 + m) * n + c0 + a];
             },
-            Rre, Rim, Cre, Cim);
+            Cre, Cim);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
